@@ -1,0 +1,171 @@
+"""Pins of the oracle's extension E and operator A (paper Sec. 2.1, eq. lapBel).
+
+Independent facts used: the product (Lagrange) form of the interpolation
+basis, partition of unity and exact reproduction of Q_p polynomials, unit
+rows at grid-node closest points, A 1 = c 1 (E 1 = 1 and the neighbour sum
+of a constant is 2d times it), the reduction of the CPM on a straight line to
+the textbook periodic second difference (solved in closed form by FFT), and
+manufactured surface eigenfunctions (circle sin(theta), sphere Y_4) with the
+expected O(h^2) convergence for p = 3.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import band as B
+from oracle import operator as O
+from oracle import surfaces
+from paper_2110_06322_amd import inputs
+from tests import oracle_cases as C
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_barycentric_equals_product_form(p):
+    t = np.random.default_rng(p).uniform(-0.5, p + 0.5, 500)
+    t = np.concatenate([t, np.arange(p + 1, dtype=float)])
+    W = O.bary_weights_1d(t, p)
+    for j in range(p + 1):
+        prod = np.ones_like(t)
+        for m in range(p + 1):
+            if m != j:
+                prod *= (t - m) / (j - m)
+        assert np.abs(W[:, j] - prod).max() < 1e-12
+
+
+@pytest.mark.parametrize("kind,params,d,h,p", [
+    ("circle", (1.0,), 2, 0.05, 2),
+    ("circle", (1.0,), 2, 0.05, 3),
+    ("sphere", (1.0,), 3, 0.1, 3),
+    ("torus", (1.0, 0.4), 3, 0.1, 2),
+])
+def test_E_partition_of_unity_and_Qp_reproduction(kind, params, d, h, p):
+    bd = C.band(kind, params, d, h, p)
+    E = O.assemble_E(bd)
+    assert np.abs(E @ np.ones(bd.n_active) - 1.0).max() < 1e-13
+    xa = B.coords(bd.active_ijk, bd.lo, h)
+    cp = bd.all_cp
+    for a in itertools.product(range(p + 1), repeat=d):
+        g = np.prod(xa ** np.array(a)[None, :], axis=1)
+        want = np.prod(cp ** np.array(a)[None, :], axis=1)
+        assert np.abs(E @ g - want).max() < 1e-12 * max(1.0, np.abs(want).max())
+    # degree p+1 in one variable is not reproduced (the pin is sharp)
+    g = xa[:, 0] ** (p + 1)
+    assert np.abs(E @ g - cp[:, 0] ** (p + 1)).max() > 1e-8
+
+
+def test_E_unit_row_at_grid_node_cp():
+    bd = C.band("circle", (1.0,), 2, 0.05, 2)
+    E = O.assemble_E(bd)
+    ijk = bd.all_ijk
+    j = int(np.nonzero((ijk[:, 0] == 62) & (ijk[:, 1] == 40))[0][0])
+    row = E.getrow(j).toarray().ravel()
+    k = int(np.nonzero((bd.active_ijk[:, 0] == 60) & (bd.active_ijk[:, 1] == 40))[0][0])
+    e = np.zeros(bd.n_active)
+    e[k] = 1.0
+    assert np.abs(row - e).max() < 1e-13
+
+
+@pytest.mark.parametrize("kind,params,d,h,p,c", [
+    ("circle", (1.0,), 2, 0.05, 2, 1.0),
+    ("sphere", (1.0,), 3, 0.1, 3, 2.5),
+])
+def test_A_constant_vector(kind, params, d, h, p, c):
+    bd, E, Om, A, P = C.matrices(kind, params, d, h, p, c)
+    r = A @ np.ones(bd.n_active) - c
+    assert np.abs(r).max() < 64 * np.finfo(float).eps * (c + 2 * d / h ** 2)
+
+
+def test_A_2d_matches_semidiscrete_form():
+    """d = 2: (A u)_i = c u_i + 4/h^2 u_i - h^-2 sum_{4 nbrs} (E u)(nbr)  (Sec. 3.1.2, eq. semiDisc),
+    checked on a field that is constant along normals, where (E u)(nbr) = u(cp(nbr)) up to O(h^3)."""
+    bd, E, Om, A, P = C.config1()
+    h = bd.h
+    u = inputs.circle_sin(bd.cp_active)
+    nb_cp = []
+    for k in range(2):
+        for s in (-1, 1):
+            x = B.coords(bd.active_ijk, bd.lo, h)
+            x[:, k] += s * h
+            nb_cp.append(surfaces.cp_sphere(x, (0.0, 0.0), 1.0))
+    lap = -4 / h ** 2 * u + sum(inputs.circle_sin(q) for q in nb_cp) / h ** 2
+    # A u = c u - Lap_S^h u; the interpolation error (O(h^3) per value) is amplified by h^-2
+    assert np.abs(A @ u - (1.0 * u - lap)).max() < 40 * h
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_periodic_straight_line_reduces_to_textbook_second_difference(p):
+    """Line y = y0 on an x-periodic strip: cp lies on grid nodes, E rows are unit
+    vectors, and the CPM system reduces to (c - D2) U = F on the line (solved by FFT)."""
+    h = 0.0625
+    n = 64
+    lo, hi = [0.0, 0.0], [(n - 1) * h, 1.0]
+    y0 = 0.5
+    g = inputs.ruuth_merriman_gamma(2, p, h)
+    bd = B.build_band(surfaces.make_cp("line", (y0,)), 2, h, p, lo, hi, g, periodic=(True, False))
+    c = 3.0
+    A = O.assemble_A(bd, c)
+    X = bd.active_ijk[:, 0] * h
+    F = np.cos(2 * math.pi * 3 * X / (n * h)) + 0.3 * np.sin(2 * math.pi * 7 * X / (n * h))
+    u = spla.spsolve(A.tocsc(), F)
+    xs = np.arange(n) * h
+    Fl = np.cos(2 * math.pi * 3 * xs / (n * h)) + 0.3 * np.sin(2 * math.pi * 7 * xs / (n * h))
+    k = np.arange(n)
+    U = np.fft.ifft(np.fft.fft(Fl) / (c + 4.0 / h ** 2 * np.sin(math.pi * k / n) ** 2)).real
+    assert np.abs(u - U[bd.active_ijk[:, 0]]).max() < 1e-12
+
+
+def _circle_error(h, p):
+    bd, E, Om, A, P = C.matrices("circle", (1.0,), 2, h, p, 1.0)
+    s = inputs.circle_sin(bd.cp_active)
+    u = spla.spsolve(A.tocsc(), 2.0 * s)
+    return np.abs(u - s).max()
+
+
+def test_circle_manufactured_order_p3():
+    e = [_circle_error(h, 3) for h in (0.1, 0.05, 0.025)]
+    orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert all(1.7 < o < 2.6 for o in orders), (e, orders)
+
+
+def test_circle_manufactured_p2_converges():
+    """p = 2: consistency O(h^2) + O(h^{p+1}/h^2) = O(h); measured order >= 0.8 and reported."""
+    e = [_circle_error(h, 2) for h in (0.1, 0.05, 0.025)]
+    orders = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert e[0] > e[1] > e[2] and min(orders) > 0.8, (e, orders)
+
+
+@pytest.mark.slow
+def test_sphere_y4_manufactured_order_p3():
+    errs = []
+    for h in (0.2, 0.1, 0.05):
+        bd, E, Om, A, P = C.matrices("sphere", (1.0,), 3, h, 3, 1.0)
+        Y = inputs.sphere_y4(bd.cp_active, seed=2)
+        ilu = spla.spilu(A.tocsc(), drop_tol=1e-5, fill_factor=20)
+        u, info = spla.gmres(A, 21.0 * Y, M=spla.LinearOperator(A.shape, ilu.solve),
+                             rtol=1e-13, restart=50, maxiter=200)
+        assert info == 0
+        errs.append(np.abs(u - Y).max() / np.abs(Y).max())
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert orders[-1] > 1.6, (errs, orders)
+
+
+def test_quartic_harmonics_are_harmonic_and_homogeneous():
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, (50, 3))
+
+    def lap(f, x, s):
+        out = -6 * f(x)
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = s
+            out = out + f(x + e) + f(x - e)
+        return out / s ** 2
+    f = inputs.quartic_harmonics
+    # for a quartic the central second difference is exact up to a pure s^2 term,
+    # which Richardson extrapolation removes
+    L = (4 * lap(f, x, 0.05) - lap(f, x, 0.1)) / 3
+    assert np.abs(L).max() < 1e-8
+    assert np.abs(f(2.0 * x) - 16.0 * f(x)).max() < 1e-12

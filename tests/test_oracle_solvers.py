@@ -1,0 +1,174 @@
+"""Pins of the oracle's GMRES, (O)RAS preconditioner, adjoint and IMEX step (CPU only).
+
+Independent facts used: dense LU solutions; GMRES with restart >= n
+terminating in at most n steps; the ILU(0) defining identity (LU)_ik = a_ik on
+the pattern and its equality with exact LU when there is no fill; RAS
+partition of unity and disjoint ownership; one subdomain with exact local
+solves is A^-1 (one iteration); alpha -> infinity turns ORAS into RAS;
+the preconditioner does not change the solution; the loss is quadratic in f,
+so central differences are exact; a spatially uniform Gray-Scott state
+follows the explicit-Euler reaction ODE exactly because A 1 = c 1.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from oracle import adjoint, krylov, reaction, schwarz
+from paper_2110_06322_amd import inputs
+from tests import oracle_cases as C
+
+
+def test_gmres_matches_dense_solve_config1():
+    bd, E, Om, A, P = C.config1()
+    f = 2.0 * inputs.circle_sin(bd.cp_active)
+    x, info = krylov.fgmres(A, f, restart=30, rtol=1e-10)
+    xd = np.linalg.solve(A.toarray(), f)
+    assert info["converged"] and info["relres"] <= 1e-10
+    assert np.abs(x - xd).max() / np.abs(xd).max() < 1e-9
+
+
+def test_gmres_full_restart_terminates_in_n_steps():
+    bd, E, Om, A, P = C.matrices("circle", (1.0,), 2, 0.2, 2, 1.0)
+    n = bd.n_active
+    f = inputs.normal(5, 0, bd.active_keys)
+    x, info = krylov.fgmres(A, f, restart=n, rtol=1e-12)
+    assert info["iters"] <= n
+    assert np.abs(x - np.linalg.solve(A.toarray(), f)).max() < 1e-8 * np.abs(x).max()
+
+
+def test_ilu0_identity_on_pattern():
+    bd, E, Om, A, P = C.matrices("sphere", (1.0,), 3, 0.2, 3, 1.0)
+    idx = np.arange(min(400, bd.n_active))
+    Aj = sp.csr_matrix(A[idx][:, idx])
+    L, U = schwarz.ilu0(Aj)
+    LU = ((L + sp.identity(idx.size)) @ U).tocsr()
+    Ad = Aj.toarray()
+    mask = Aj.toarray() != 0
+    mask |= sp.csr_matrix((np.ones(Aj.nnz), Aj.indices, Aj.indptr), shape=Aj.shape).toarray() != 0
+    assert np.abs((LU.toarray() - Ad)[mask]).max() < 1e-9 * np.abs(Ad).max()
+    # L and U live on the pattern
+    assert set(zip(*sp.triu(U).nonzero())) <= set(zip(*np.nonzero(mask)))
+
+
+def test_ilu0_without_fill_is_exact_lu():
+    n = 50
+    rng = np.random.default_rng(2)
+    T = sp.diags([rng.uniform(-1, 0, n - 1), rng.uniform(4, 5, n), rng.uniform(-1, 0, n - 1)],
+                 [-1, 0, 1], format="csr")
+    L, U = schwarz.ilu0(T)
+    Pm, Ld, Ud = sla.lu(T.toarray())
+    assert np.allclose(Pm, np.eye(n))
+    assert np.abs((L + sp.identity(n)).toarray() - Ld).max() < 1e-14
+    assert np.abs(U.toarray() - Ud).max() < 1e-13
+
+
+def _sphere_ras(kind="ras", n_parts=8, h=0.1, alpha=4.0, alpha_cross=20.0, subsolver="ilu0", c=1.0):
+    bd, E, Om, A, P = C.matrices("sphere", (1.0,), 3, h, 3, c)
+    S = schwarz.build_schwarz(A, P, bd.cp_active, bd.active_keys, h, n_parts, 2.0, kind=kind,
+                              alpha=alpha, alpha_cross=alpha_cross, subsolver=subsolver)
+    return bd, A, S
+
+
+def test_ras_partition_of_unity_and_ownership():
+    bd, A, S = _sphere_ras()
+    n = bd.n_active
+    cover = np.zeros(n, dtype=int)
+    for j, idx in enumerate(S.omegas):
+        own = S.owner[idx] == j
+        cover[idx[own]] += 1
+        assert (S.owner == j).sum() == own.sum()   # every owned node lies in its Omega_j
+    assert (cover == 1).all()
+    # restricted recombination of R_j x gives x back
+    x = np.random.default_rng(0).standard_normal(n)
+    z = np.zeros(n)
+    for j, idx in enumerate(S.omegas):
+        own = S.owner[idx] == j
+        z[idx[own]] = x[idx][own]
+    assert np.array_equal(z, x)
+    sizes = np.bincount(S.owner)
+    assert sizes.min() > 0.7 * sizes.mean()
+
+
+def test_single_subdomain_exact_lu_is_inverse():
+    bd, A, S = _sphere_ras(n_parts=1, subsolver="lu")
+    f = inputs.sphere_y4(bd.cp_active, 2) * 21.0
+    x, info = krylov.fgmres(A, f, M=S.apply, rtol=1e-10)
+    assert info["iters"] == 1 and info["converged"]
+
+
+def test_oras_large_alpha_is_ras():
+    bd, A, S1 = _sphere_ras(kind="ras")
+    _, _, S2 = _sphere_ras(kind="oras", alpha=1e300, alpha_cross=1e300)
+    r = np.random.default_rng(1).standard_normal(bd.n_active)
+    z1, z2 = S1.apply(r), S2.apply(r)
+    assert np.abs(z1 - z2).max() <= 1e-13 * np.abs(z1).max()
+    _, _, S3 = _sphere_ras(kind="oras")
+    assert np.abs(S3.apply(r) - z1).max() > 1e-6 * np.abs(z1).max()
+
+
+def test_preconditioners_leave_solution_unchanged_and_help():
+    """Every preconditioner converges to the same solution; RAS with ILU(0) and ORAS with
+    exact local solves cut the iteration count. (ORAS with ILU(0) local solves can be worse
+    than no preconditioner: the paper reports this ILU/Robin interaction, Sec. 4.1.1.)"""
+    bd, A, Sr = _sphere_ras(kind="ras")
+    _, _, So = _sphere_ras(kind="oras")
+    _, _, Srl = _sphere_ras(kind="ras", subsolver="lu")
+    _, _, Sol = _sphere_ras(kind="oras", subsolver="lu")
+    f = inputs.sphere_y4(bd.cp_active, 2) * 21.0
+    x0, i0 = krylov.fgmres(A, f, rtol=1e-11)
+    s = np.abs(x0).max()
+    its = {}
+    for name, S in (("ras", Sr), ("oras", So), ("ras_lu", Srl), ("oras_lu", Sol)):
+        x, info = krylov.fgmres(A, f, M=S.apply, rtol=1e-11, max_it=2000)
+        assert info["converged"] and np.abs(x - x0).max() < 1e-9 * s, name
+        its[name] = info["iters"]
+    assert its["ras"] < i0["iters"] and its["ras_lu"] < its["ras"]
+    assert its["oras_lu"] <= its["ras_lu"]
+
+
+def test_adjoint_gradients_exact_central_differences():
+    bd, E, Om, A, P = C.matrices("circle", (1.0,), 2, 0.1, 3, 1.5)
+    n = bd.n_active
+    f = inputs.normal(1, 0, bd.active_keys)
+    ut = inputs.normal(1, 1, bd.active_keys)
+    L, u, gf, gc = adjoint.quadratic_loss_grads(A, f, ut)
+    Ld, ud, gfd, gcd = adjoint.quadratic_loss_grads(A, f, ut, dense=True)
+    assert abs(L - Ld) < 1e-10 * L and np.abs(gf - gfd).max() < 1e-10 * np.abs(gf).max()
+    eps = max(1.0, np.abs(f).max())
+    for i in np.random.default_rng(0).choice(n, 8, replace=False):
+        e = np.zeros(n)
+        e[i] = eps
+        fd = (adjoint.quadratic_loss_grads(A, f + e, ut)[0]
+              - adjoint.quadratic_loss_grads(A, f - e, ut)[0]) / (2 * eps)
+        assert abs(fd - gf[i]) <= 1e-8 * max(abs(gf[i]), 1e-3 * np.abs(gf).max())
+    # derivative in c: A(c) = A + (c' - c) I
+    ec = 1e-4 * 1.5
+    Ip = sp.identity(n, format="csr")
+    fd = (adjoint.quadratic_loss_grads(A + ec * Ip, f, ut)[0]
+          - adjoint.quadratic_loss_grads(A - ec * Ip, f, ut)[0]) / (2 * ec)
+    assert abs(fd - gc) <= 1e-6 * abs(gc)
+    # transpose identity on the assembled operator
+    x, y = inputs.normal(2, 0, bd.active_keys), inputs.normal(2, 1, bd.active_keys)
+    assert abs(np.dot(A @ x, y) - np.dot(x, adjoint.transpose_apply(A, y))) < 1e-12 * np.abs(A @ x).sum()
+
+
+def test_gray_scott_uniform_state_follows_reaction_ode():
+    bd, E, Om, A0, P = C.matrices("circle", (1.0,), 2, 0.1, 3, 0.0)
+    mu, dt, F, k = (2e-5, 1e-5), 1.0, 0.04, 0.06
+    n = bd.n_active
+    Ip = sp.identity(n, format="csr")
+    Au = (A0 + (1.0 / (mu[0] * dt)) * Ip).tocsc()
+    Av = (A0 + (1.0 / (mu[1] * dt)) * Ip).tocsc()
+    import scipy.sparse.linalg as spla
+    su, sv = spla.factorized(Au), spla.factorized(Av)
+    u, v = np.full(n, 0.7), np.full(n, 0.2)
+    uu, vv = 0.7, 0.2
+    for _ in range(5):
+        u, v = reaction.imex_step(su, sv, u, v, F, k, mu, dt)
+        Ru, Rv = reaction.gray_scott_reaction(uu, vv, F, k)
+        uu, vv = uu + dt * Ru, vv + dt * Rv
+    assert np.abs(u - uu).max() < 1e-10 and np.abs(v - vv).max() < 1e-10
+    # (1, 0) is a fixed point
+    u1, v1 = reaction.imex_step(su, sv, np.ones(n), np.zeros(n), F, k, mu, dt)
+    assert np.abs(u1 - 1).max() < 1e-10 and np.abs(v1).max() < 1e-12
