@@ -1,0 +1,275 @@
+/*
+ * cpm.h - C ABI of the MI355X closest point method (CPM) solver hot path.
+ *
+ * Method: May, Haynes & Ruuth, "A closest point method library for PDEs on
+ * surfaces with parallel domain decomposition solvers and preconditioners"
+ * (arXiv 2110.06322). The library discretizes the shifted surface Poisson
+ * problem (c - Lap_S) u = f (Sec. 1, eq. shiftPoisson) with the stabilized
+ * CPM operator (Sec. 2.1, eq. lapBel)
+ *
+ *     A = c I - Delta_S^h = (c + 2d/h^2) I - h^-2 O E,
+ *
+ * E the tensor-product degree-p Lagrange extension from the active nodes
+ * Sigma_A to Sigma_A u Sigma_G, O the sum over the 2d grid neighbours, and
+ * solves it with right-preconditioned GMRES (Sec. 4.1.1) and restricted /
+ * optimized restricted additive Schwarz preconditioners (Sec. 2.2).
+ *
+ * Conventions for every entry point:
+ *   - All functions return cpm_status; CPM_OK is 0. On failure a message is
+ *     available from cpm_last_error() (thread-local, valid until the next
+ *     call on the same thread). No C++ exception crosses this interface.
+ *   - Arguments are validated before any device work is queued.
+ *   - Handles are opaque and owned by the library; *_destroy releases their
+ *     host and device memory (destroy(NULL) is a no-op).
+ *   - "device" pointers are HIP device pointers (e.g. torch tensor
+ *     data_ptr()); "host" pointers are ordinary CPU memory. The library never
+ *     keeps a caller pointer after the call returns. Calls taking a `stream`
+ *     (a hipStream_t passed as void*, NULL = default stream) are
+ *     asynchronous on that stream unless stated otherwise: the caller keeps
+ *     its buffers alive until the stream has passed the call.
+ *   - Vectors over the unknowns are FP64, contiguous, in the library's node
+ *     order (cpm_band_export); with nrhs > 1 they are interleaved
+ *     [node][rhs].
+ */
+#ifndef CPM_H
+#define CPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPM_VERSION 1
+
+typedef enum {
+  CPM_OK = 0,
+  CPM_ERR_ARG = 1,        /* invalid handle, size, option or pointer */
+  CPM_ERR_BAND = 2,       /* band leaves the grid box or closure failed */
+  CPM_ERR_PIVOT = 3,      /* zero pivot in a local factorization */
+  CPM_ERR_DEVICE = 4,     /* HIP runtime error, or no usable GPU */
+  CPM_ERR_OOM = 5,        /* host or device allocation failed */
+  CPM_NOT_CONVERGED = 6,  /* solver stopped before reaching the tolerance */
+  CPM_ERR_STATE = 7       /* object used in a state that does not allow it */
+} cpm_status;
+
+/* ---------------------------------------------------------------------
+ * Surfaces and the computational band (Sec. 2.1: closest point function
+ * eq. cpFunc; active nodes Sigma_A containing every (p+1)^d interpolation
+ * cube; ghost nodes Sigma_G completing the finite-difference stencils).
+ * ------------------------------------------------------------------- */
+typedef enum {
+  CPM_SURF_CIRCLE = 0,    /* d = 2: params[0] = R, centre[0..1] */
+  CPM_SURF_SPHERE = 1,    /* d = 3: params[0] = R, centre[0..2] */
+  CPM_SURF_TORUS = 2,     /* d = 3, axis z, centre 0: params = {R, r} */
+  CPM_SURF_ELLIPSOID = 3  /* d = 3, centre 0, axis-aligned: params = {a, b, c} */
+} cpm_surface_kind;
+
+typedef struct {
+  int32_t kind;           /* cpm_surface_kind */
+  double params[3];
+  double center[3];
+} cpm_surface;
+
+typedef struct cpm_band_s cpm_band;
+
+typedef struct {
+  int64_t n_active;       /* N_A = |Sigma_A|, the unknowns */
+  int64_t n_ghost;        /* N_G = |Sigma_G| */
+  int64_t n_band;         /* |B_gamma| */
+  int32_t d, p;
+  double h, gamma;
+  double lo[3];
+  int32_t shape[3];       /* grid points per axis */
+  int64_t n_bricks;       /* 4x4x4 (d=3) or 8x8 (d=2) node bricks holding band nodes */
+  int32_t closure_iterations;
+} cpm_band_info;
+
+/* Build the band on the host. Grid nodes x_i = lo + i h, i_k in
+ * [0, floor((hi_k-lo_k)/h + 0.5)]. B_gamma = {x : |x - cp(x)| <= gamma(1+1e-10)};
+ * Sigma_A = union over x in B_gamma of the cube b + {0..p}^d with
+ * b = floor((cp(x)-lo)/h - (p-1)/2); Sigma_G = grid neighbours of Sigma_A not
+ * in Sigma_A. gamma <= 0 selects h sqrt((d-1)((p+1)/2)^2 + (1+(p+1)/2)^2).
+ * d in {2,3}, p in {1,2,3}. Errors: CPM_ERR_ARG (bad sizes / surface),
+ * CPM_ERR_BAND (a cube or neighbour leaves the grid box, or closure needs
+ * more than one extra pass). lo/hi: host arrays of d doubles. */
+cpm_status cpm_band_build(const cpm_surface* surface, int32_t d, double h, int32_t p,
+                          const double* lo, const double* hi, double gamma,
+                          cpm_band** out);
+cpm_status cpm_band_get_info(const cpm_band* band, cpm_band_info* info);
+/* Export the library's node order: Sigma_A first (indices 0..N_A-1, the
+ * unknowns), then Sigma_G. Host arrays, caller-owned, any may be NULL:
+ * gidx [(N_A+N_G) x d] int32 grid indices, cp [(N_A+N_G) x d] closest
+ * points, kind [N_A+N_G] (0 active, 1 ghost). Row-major [node][axis]. */
+cpm_status cpm_band_export(const cpm_band* band, int32_t* gidx, double* cp, uint8_t* kind);
+void cpm_band_destroy(cpm_band* band);
+
+/* ---------------------------------------------------------------------
+ * Operator A = (c + 2d/h^2) I - h^-2 O E (Sec. 2.1 eq. lapBel, Sec. 1 eq.
+ * shiftPoisson), matrix-free on the GPU.
+ * ------------------------------------------------------------------- */
+typedef struct cpm_operator_s cpm_operator;
+
+/* Uploads the band (closest points, brick map, tiles) to device memory
+ * owned by the operator. The band may be destroyed afterwards. c > 0. */
+cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out);
+cpm_status cpm_operator_set_shift(cpm_operator* op, double c);
+double cpm_operator_get_shift(const cpm_operator* op);
+int64_t cpm_operator_n_active(const cpm_operator* op);
+void cpm_operator_destroy(cpm_operator* op);
+
+/* v = E u: the extension at every node of Sigma_A u Sigma_G (Sec. 2.1).
+ * u: device [N_A], v: device [N_A+N_G]. Test hook; one right-hand side. */
+cpm_status cpm_extend_apply(const cpm_operator* op, const double* u, double* v, void* stream);
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1).
+ * x, y: device [N_A * nrhs], interleaved [node][rhs], must not alias;
+ * nrhs in {1, 2, 4}. A^T x = (c + 2d/h^2) x - h^-2 E^T (O^T x) is evaluated
+ * without atomics (each output gathers the extension rows that reach it). */
+cpm_status cpm_apply(const cpm_operator* op, const double* x, double* y, int32_t nrhs, void* stream);
+cpm_status cpm_apply_T(const cpm_operator* op, const double* x, double* y, int32_t nrhs, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Restricted (RAS) and optimized restricted (ORAS) additive Schwarz
+ * preconditioners (Sec. 2.2, eq. ddIter and the restricted recombination;
+ * Sec. 4.1.1: alpha = 4, alpha_cross = 20, "one level incomplete LU").
+ *   partition : recursive coordinate bisection of Sigma_A by closest point
+ *               (axis of largest extent, split value = floor(n/2)-th smallest
+ *               coordinate, cp < split goes first); n_parts a power of two;
+ *   overlap   : Omega_j = nodes whose cp lies in box_j grown by overlap*h;
+ *   local     : rows/columns of A in Omega_j (ascending grid key), on A's
+ *               structural pattern;
+ *   ORAS      : a_ii += s_i/(1 + alpha_i h), s_i the sum of the dropped
+ *               couplings of row i, alpha_i = alpha_cross when they belong
+ *               to >= 2 other subdomains;
+ *   subsolver : ILU(0) (default) or exact dense LU (tests, small parts);
+ *   apply     : z = sum_j Rt_j^T A_j^-1 R_j r, written only at owned nodes.
+ * ------------------------------------------------------------------- */
+typedef enum { CPM_PC_NONE = 0, CPM_PC_RAS = 1, CPM_PC_ORAS = 2 } cpm_pc_kind;
+typedef enum { CPM_SUB_ILU0 = 0, CPM_SUB_DENSE_LU = 1 } cpm_subsolver;
+typedef enum { CPM_PREC_FP64 = 0, CPM_PREC_FP32 = 1 } cpm_precision;
+
+typedef struct {
+  int32_t kind;           /* cpm_pc_kind */
+  int32_t n_parts;        /* N_S, power of two, >= 1 */
+  double overlap;         /* N_O in units of h, >= 0 */
+  double alpha;           /* Robin parameter (ORAS), > 0 */
+  double alpha_cross;     /* Robin parameter at cross points (ORAS), > 0 */
+  int32_t subsolver;      /* cpm_subsolver */
+  int32_t precision;      /* cpm_precision of the factors and local solves */
+  int32_t transpose;      /* 1: build on A^T (for adjoint solves) */
+} cpm_precond_opts;
+
+typedef struct cpm_precond_s cpm_precond;
+
+typedef struct {
+  int32_t n_parts;
+  int64_t total_rows;     /* sum_j |Omega_j| */
+  int64_t total_nnz;      /* sum_j nnz(A_j) */
+  int32_t max_rows;       /* max_j |Omega_j| */
+  int32_t max_levels;     /* longest dependency chain of a triangular solve */
+  int32_t precision;
+  int32_t kind;
+} cpm_precond_info;
+
+/* Builds partition, local matrices and factors on the host, uploads them to
+ * device memory owned by the preconditioner. Uses op's current shift c.
+ * Errors: CPM_ERR_ARG, CPM_ERR_PIVOT (zero pivot), CPM_ERR_OOM. */
+cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* opts,
+                              cpm_precond** out);
+cpm_status cpm_precond_get_info(const cpm_precond* pc, cpm_precond_info* info);
+/* Host arrays: owner [N_A] (subdomain owning each node), ovl_ptr
+ * [n_parts+1] int64, ovl_idx [total_rows] (node indices of each Omega_j in
+ * local order). Any may be NULL. */
+cpm_status cpm_precond_export_partition(const cpm_precond* pc, int32_t* owner,
+                                        int64_t* ovl_ptr, int32_t* ovl_idx);
+/* z = M^-1 r. r, z: device [N_A * nrhs], must not alias; nrhs in {1,2,4}. */
+cpm_status cpm_precond_apply(const cpm_precond* pc, const double* r, double* z, int32_t nrhs,
+                             void* stream);
+void cpm_precond_destroy(cpm_precond* pc);
+
+/* ---------------------------------------------------------------------
+ * Solver: restarted right-preconditioned flexible GMRES in FP64 with
+ * classical Gram-Schmidt twice (CGS2) and Givens rotations on the device.
+ * mode FP64     : preconditioner as built (FP64 or FP32 factors);
+ * mode MIXED_IR : GMRES-based iterative refinement: each restart cycle
+ *                 solves the correction equation A d = r to inner_rtol
+ *                 relative to its own residual, r = f - A u is recomputed
+ *                 in FP64 at every restart (requires an FP32 preconditioner
+ *                 or none).
+ * Stopping: |f - A u|_2 <= max(rtol |f|_2, atol), checked on the true FP64
+ * residual at every restart and at exit; x0 = contents of u (zero it for
+ * x0 = 0). Blocks until the solution is in u and stats are final.
+ * Returns CPM_NOT_CONVERGED (u = last iterate, stats filled) when max_it is
+ * reached, on stagnation, or on a non-finite residual.
+ * ------------------------------------------------------------------- */
+typedef enum { CPM_MODE_FP64 = 0, CPM_MODE_MIXED_IR = 1 } cpm_solve_mode;
+
+typedef struct {
+  int32_t restart;        /* Krylov dimension per cycle, 1..64 (default 30) */
+  double rtol;
+  double atol;
+  int32_t max_it;         /* cap on Arnoldi steps */
+  int32_t mode;           /* cpm_solve_mode */
+  int32_t transpose;      /* 1: solve A^T u = f (pc must be built with transpose=1) */
+  int32_t use_graph;      /* 1: replay each restart cycle as a captured hipGraph */
+  double inner_rtol;      /* MIXED_IR: per-cycle reduction target (default 1e-4) */
+  int32_t stagnation_cycles; /* cycles without 1% progress before giving up (default 50) */
+} cpm_solve_opts;
+
+typedef struct {
+  int32_t iterations;     /* Arnoldi steps */
+  int32_t restarts;       /* restart cycles */
+  int32_t converged;
+  int32_t status;         /* cpm_status of this system */
+  double relres;          /* true |f - A u| / |f| at exit */
+  double ms_total;        /* wall time of the solve (hipEvent) */
+  double ms_precond;      /* time in the preconditioner kernels (0 unless profiled) */
+  double ms_apply;        /* time in the operator kernels (0 unless profiled) */
+  int32_t n_precond;      /* preconditioner applications */
+  int32_t n_apply;        /* operator applications */
+} cpm_solve_stats;
+
+cpm_status cpm_solve_opts_default(cpm_solve_opts* opts);
+cpm_status cpm_precond_opts_default(cpm_precond_opts* opts);
+
+/* f, u: device [N_A * nrhs]; pc may be NULL (no preconditioner). stats may be NULL. */
+cpm_status cpm_solve(const cpm_operator* op, const cpm_precond* pc, const double* f, double* u,
+                     int32_t nrhs, const cpm_solve_opts* opts, cpm_solve_stats* stats,
+                     void* stream);
+
+/* ---------------------------------------------------------------------
+ * Batched solves: many surfaces (operators of different sizes, shifts and
+ * preconditioners) and many right-hand sides, advanced together: every
+ * kernel of an Arnoldi step is one launch over all instances' tiles,
+ * subdomains and vector chunks. Instances finish independently.
+ * ------------------------------------------------------------------- */
+typedef struct cpm_batch_s cpm_batch;
+
+/* ops[i], pcs[i] (pcs may be NULL or hold NULLs): borrowed, must outlive
+ * the batch; nrhs[i] in {1,2,4}. */
+cpm_status cpm_batch_create(int32_t n, const cpm_operator* const* ops,
+                            const cpm_precond* const* pcs, const int32_t* nrhs,
+                            cpm_batch** out);
+/* f[i], u[i]: device [N_A(i) * nrhs(i)]. stats: host array of
+ * sum_i nrhs(i) entries (system order: instance-major) or NULL. Returns
+ * CPM_NOT_CONVERGED if any system did not converge. */
+cpm_status cpm_batch_solve(cpm_batch* batch, const double* const* f, double* const* u,
+                           const cpm_solve_opts* opts, cpm_solve_stats* stats, void* stream);
+/* y[i] = A_i x[i] for every instance in one launch. */
+cpm_status cpm_batch_apply(cpm_batch* batch, const double* const* x, double* const* y,
+                           void* stream);
+void cpm_batch_destroy(cpm_batch* batch);
+
+/* ---------------------------------------------------------------------
+ * Misc
+ * ------------------------------------------------------------------- */
+const char* cpm_last_error(void);
+int32_t cpm_version(void);
+/* Number of HIP devices visible (0 when none); never fails. */
+int32_t cpm_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPM_H */

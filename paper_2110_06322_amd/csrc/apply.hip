@@ -1,0 +1,563 @@
+// Matrix-free CPM operator kernels for CDNA4 (gfx950).
+//
+//   (E u)_j   = sum_{a in {0..p}^d} prod_k l_{a_k}(s_jk) u[b_j + a]          (Sec. 2.1)
+//   (A u)_i   = (c + 2d/h^2) u_i - h^-2 sum_{nbr n of i} (E u)_n               (eq. lapBel)
+//   (A^T y)_k = (c + 2d/h^2) y_k - h^-2 sum_{j : k in cube(j)} W_jk (O^T y)_j
+// with b_j = floor((cp_j - lo)/h - (p-1)/2), s_j = (cp_j - lo)/h - b_j and the
+// Lagrange basis on nodes 0..p in product form (equal to the barycentric form
+// of the paper's reference in exact arithmetic).
+//
+// Forward apply: one workgroup per 8^3-node tile (16^2 in 2-D). It stages the
+// tile's interpolation footprint of u into LDS (one wavefront per 64-node
+// brick, lane = node, compacted loads addressed with mbcnt over the brick's
+// occupancy mask), evaluates every extension row the tile's stencils need
+// (tile nodes plus the face halo) into an LDS box, then applies the
+// (2d+1)-point stencil from LDS. Every extension row is read from HBM once
+// per tile that needs it and no intermediate vector goes back to HBM.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace cpm {
+
+// ------------------------------------------------------------- helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// number of set bits of m strictly below this lane
+__device__ __forceinline__ int mbcnt64(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ __forceinline__ int popc_below(uint64_t m, int bit) {
+  uint64_t below = bit == 0 ? 0ull : ((~0ull) >> (64 - bit));
+  return __popcll(m & below);
+}
+
+template <int D>
+__device__ __forceinline__ void local_of(int bit, int* l) {
+  if (D == 3) { l[0] = bit >> 4; l[1] = (bit >> 2) & 3; l[2] = bit & 3; }
+  else { l[0] = bit >> 3; l[1] = bit & 7; l[2] = 0; }
+}
+template <int D>
+__device__ __forceinline__ int bit_of(int l0, int l1, int l2) {
+  return D == 3 ? l0 * 16 + l1 * 4 + l2 : l0 * 8 + l1;
+}
+template <int D> constexpr int kEdge = D == 3 ? 4 : 8;
+template <int D> constexpr int kShift = D == 3 ? 2 : 3;
+template <int D> constexpr int kTile = 2 * kEdge<D>;   // tile edge in nodes
+
+// brick id holding grid node g, or -1
+template <int D>
+__device__ __forceinline__ int brick_at(const DevInst& I, const int* g) {
+  int r = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    int b = (g[k] >> kShift<D>) - I.bm_lo[k];
+    if (b < 0 || b >= I.bm_dim[k] || g[k] < 0) return -1;
+    r = r * I.bm_dim[k] + b;
+  }
+  return I.bmap[r];
+}
+
+// node index (Sigma_A then Sigma_G) of grid node g, -1 if not in the band
+template <int D>
+__device__ __forceinline__ int node_at(const DevInst& I, const int* g) {
+  int id = brick_at<D>(I, g);
+  if (id < 0) return -1;
+  int bit = bit_of<D>(g[0] & (kEdge<D> - 1), g[1] & (kEdge<D> - 1), D == 3 ? (g[2] & 3) : 0);
+  uint64_t mA = I.maskA[id];
+  if ((mA >> bit) & 1ull) return I.offA[id] + popc_below(mA, bit);
+  uint64_t mG = I.maskG[id];
+  if ((mG >> bit) & 1ull) return I.nA + I.offG[id] + popc_below(mG, bit);
+  return -1;
+}
+
+// Lagrange basis on nodes 0..P at s, product form
+template <int P>
+__device__ __forceinline__ void lagrange(double s, double* w) {
+  if (P == 1) { w[0] = 1.0 - s; w[1] = s; }
+  else if (P == 2) {
+    double a = s, b = s - 1.0, c = s - 2.0;
+    w[0] = 0.5 * b * c; w[1] = -a * c; w[2] = 0.5 * a * b;
+  } else {
+    double a = s, b = s - 1.0, c = s - 2.0, e = s - 3.0;
+    const double i6 = 1.0 / 6.0;
+    w[0] = -i6 * (b * c) * e; w[1] = 0.5 * (a * c) * e;
+    w[2] = -0.5 * (a * b) * e; w[3] = i6 * (a * b) * c;
+  }
+}
+
+// cube corner b and per-axis weights of the extension row of closest point cp
+template <int D, int P>
+__device__ __forceinline__ void erow_weights(const DevInst& I, const double* cp, int* b, double (*w)[P + 1]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    double t = (cp[k] - I.lo[k]) / I.h;
+    double bf = floor(t - (P - 1) * 0.5);
+    b[k] = (int)bf;
+    lagrange<P>(t - bf, w[k]);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void load_cp(const DevInst& I, int j, double* cp) {
+  const int n = I.nA + I.nG;
+#pragma unroll
+  for (int k = 0; k < D; ++k) cp[k] = I.cp[(int64_t)k * n + j];
+}
+
+// Extension row evaluated with per-node index lookups into a global vector
+// (slow path: test hook and tiles whose footprint does not fit in LDS).
+template <int D, int P, int NRHS>
+__device__ void erow_global(const DevInst& I, const double* cp, const double* __restrict__ x, double* out) {
+  int b[3] = {0, 0, 0};
+  double w[D][P + 1];
+  erow_weights<D, P>(I, cp, b, w);
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r) out[r] = 0.0;
+  if (D == 3) {
+    for (int a0 = 0; a0 <= P; ++a0) {
+      double acc1[NRHS];
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) acc1[r] = 0.0;
+      for (int a1 = 0; a1 <= P; ++a1) {
+        double acc2[NRHS];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc2[r] = 0.0;
+        for (int a2 = 0; a2 <= P; ++a2) {
+          int g[3] = {b[0] + a0, b[1] + a1, b[2] + a2};
+          int j = node_at<3>(I, g);
+          if (j < 0 || j >= I.nA) continue;  // cannot happen on a closed band
+          const double* xp = x + (I.vec_off + j) * NRHS;
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r) acc2[r] += w[2][a2] * xp[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc1[r] += w[1][a1] * acc2[r];
+      }
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) out[r] += w[0][a0] * acc1[r];
+    }
+  } else {
+    for (int a0 = 0; a0 <= P; ++a0) {
+      double acc1[NRHS];
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) acc1[r] = 0.0;
+      for (int a1 = 0; a1 <= P; ++a1) {
+        int g[3] = {b[0] + a0, b[1] + a1, 0};
+        int j = node_at<2>(I, g);
+        if (j < 0 || j >= I.nA) continue;  // cannot happen on a closed band
+        const double* xp = x + (I.vec_off + j) * NRHS;
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc1[r] += w[1][a1] * xp[r];
+      }
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) out[r] += w[0][a0] * acc1[r];
+    }
+  }
+}
+
+// Extension row evaluated from the LDS footprint U ([f0][f1][f2][NRHS]).
+template <int D, int P, int NRHS>
+__device__ __forceinline__ void erow_lds(const DevInst& I, const double* cp, const double* U,
+                                         const int* flo, const int* fdim, double* out) {
+  int b[3] = {0, 0, 0};
+  double w[D][P + 1];
+  erow_weights<D, P>(I, cp, b, w);
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r) out[r] = 0.0;
+  if (D == 3) {
+    const int s1 = fdim[2], s0 = fdim[1] * fdim[2];
+    const int base = (b[0] - flo[0]) * s0 + (b[1] - flo[1]) * s1 + (b[2] - flo[2]);
+#pragma unroll
+    for (int a0 = 0; a0 <= P; ++a0) {
+      double acc1[NRHS];
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) acc1[r] = 0.0;
+#pragma unroll
+      for (int a1 = 0; a1 <= P; ++a1) {
+        const double* col = U + (base + a0 * s0 + a1 * s1) * NRHS;
+        double acc2[NRHS];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc2[r] = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 <= P; ++a2)
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r) acc2[r] += w[2][a2] * col[a2 * NRHS + r];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc1[r] += w[1][a1] * acc2[r];
+      }
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) out[r] += w[0][a0] * acc1[r];
+    }
+  } else {
+    const int s0 = fdim[1];
+    const int base = (b[0] - flo[0]) * s0 + (b[1] - flo[1]);
+#pragma unroll
+    for (int a0 = 0; a0 <= P; ++a0) {
+      const double* col = U + (base + a0 * s0) * NRHS;
+      double acc1[NRHS];
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) acc1[r] = 0.0;
+#pragma unroll
+      for (int a1 = 0; a1 <= P; ++a1)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc1[r] += w[1][a1] * col[a1 * NRHS + r];
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) out[r] += w[0][a0] * acc1[r];
+    }
+  }
+}
+
+// Work item w of n for block i so that consecutive work items run on the same
+// XCD (the dispatcher deals workgroups to the 8 XCDs round-robin).
+__device__ __forceinline__ int xcd_remap(int i, int n) {
+  const int X = 8;
+  int q = n / X, r = n % X;
+  int xcd = i % X, k = i / X;
+  return xcd * q + min(xcd, r) + k;
+}
+
+// ------------------------------------------------------------- kernels
+// v = E u over all nodes of Sigma_A u Sigma_G (one right-hand side)
+template <int D, int P>
+__global__ void __launch_bounds__(256) k_extend(DevInst I, const double* __restrict__ u, double* __restrict__ v) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= I.nA + I.nG) return;
+  double cp[3], out[1];
+  load_cp<D>(I, j, cp);
+  erow_global<D, P, 1>(I, cp, u, out);
+  v[j] = out[0];
+}
+
+template <int D, int NRHS>
+__device__ __forceinline__ int vbox_index(const int* l) {
+  // tile-local coordinates in [-1, T] -> box of edge T+2
+  constexpr int W = kTile<D> + 2;
+  return D == 3 ? (((l[0] + 1) * W + (l[1] + 1)) * W + (l[2] + 1)) * NRHS
+                : ((l[0] + 1) * W + (l[1] + 1)) * NRHS;
+}
+
+template <int D, int NRHS>
+constexpr int vbox_doubles() {
+  constexpr int W = kTile<D> + 2;
+  return (D == 3 ? W * W * W : W * W) * NRHS;
+}
+
+// Fused y = A x over the tiles of one or more instances. LDS holds one
+// right-hand side at a time: U = footprint of x (ucap doubles), V = extension
+// values on the tile plus its face halo.
+template <int D, int P, int NRHS>
+__global__ void __launch_bounds__(256) k_apply_tile(const DevInst* __restrict__ insts,
+                                                    const WorkItem* __restrict__ work, int nwork, int ucap,
+                                                    const double* __restrict__ x, double* __restrict__ y) {
+  extern __shared__ double smem[];
+  constexpr int NB = D == 3 ? 8 : 4;        // bricks per tile
+  constexpr int T = kTile<D>;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  if (w >= nwork) return;
+  const WorkItem wi = work[w];
+  const DevInst& I = insts[wi.inst];
+  const DevTile& tile = I.tiles[wi.idx];
+  int flo[3], fdim[3], org[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { flo[k] = tile.flo[k]; fdim[k] = tile.fdim[k]; org[k] = tile.origin[k]; }
+  double* U = smem;
+  double* V = smem + ucap;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int nwaves = blockDim.x >> 6;
+  const double* xb = x + I.vec_off * NRHS;
+  double* yb = y + I.vec_off * NRHS;
+  int blo[3] = {0, 0, 0}, bn[3] = {1, 1, 1};
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    blo[k] = flo[k] >> kShift<D>;
+    bn[k] = ((flo[k] + fdim[k] - 1) >> kShift<D>) - blo[k] + 1;
+  }
+  const int nfb = bn[0] * bn[1] * bn[2];
+  constexpr int FACE = D == 3 ? T * T : T;
+  constexpr int W = T + 2;
+  constexpr int S0 = D == 3 ? W * W : W, S1 = D == 3 ? W : 1, S2 = 1;
+
+  for (int r = 0; r < NRHS; ++r) {
+    if (r > 0) __syncthreads();
+    // 1. stage the footprint of x into LDS, brick by brick (lane = node of the brick)
+    for (int q = wave; q < nfb; q += nwaves) {
+      int bb[3];
+      bb[2] = D == 3 ? q % bn[2] : 0;
+      bb[1] = D == 3 ? (q / bn[2]) % bn[1] : q % bn[1];
+      bb[0] = D == 3 ? q / (bn[2] * bn[1]) : q / bn[1];
+      int g0[3] = {0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < D; ++k) g0[k] = (blo[k] + bb[k]) << kShift<D>;
+      int id = brick_at<D>(I, g0);
+      if (id < 0) continue;
+      uint64_t m = I.maskA[id];
+      int l[3];
+      local_of<D>(lane, l);
+      int idx = I.offA[id] + mbcnt64(m);
+      bool inside = (m >> lane) & 1ull;
+      int li = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        int o = g0[k] + l[k] - flo[k];
+        inside = inside && o >= 0 && o < fdim[k];
+        li = li * fdim[k] + o;
+      }
+      if (inside) U[li] = xb[(int64_t)idx * NRHS + r];
+    }
+    __syncthreads();
+
+    // 2a. extension rows of every band node in the tile
+    for (int q = wave; q < NB; q += nwaves) {
+      int id = tile.brick[q];
+      if (id < 0) continue;
+      uint64_t mA = I.maskA[id], mG = I.maskG[id];
+      if (!(((mA | mG) >> lane) & 1ull)) continue;
+      int j = ((mA >> lane) & 1ull) ? I.offA[id] + mbcnt64(mA) : I.nA + I.offG[id] + mbcnt64(mG);
+      double cp[3], out[1];
+      load_cp<D>(I, j, cp);
+      erow_lds<D, P, 1>(I, cp, U, flo, fdim, out);
+      int l[3];
+      local_of<D>(lane, l);
+      int sub[3] = {D == 3 ? (q >> 2) : (q >> 1), D == 3 ? ((q >> 1) & 1) : (q & 1), D == 3 ? (q & 1) : 0};
+#pragma unroll
+      for (int k = 0; k < D; ++k) l[k] += sub[k] * kEdge<D>;
+      V[vbox_index<D, 1>(l)] = out[0];
+    }
+    // 2b. face halo: outward neighbours of the tile's active boundary nodes
+    for (int q = threadIdx.x; q < 2 * D * FACE; q += blockDim.x) {
+      int f = q / FACE, pos = q % FACE;
+      int axis = f >> 1, side = f & 1;
+      int l[3] = {0, 0, 0};
+      int o1 = D == 3 ? pos / T : pos, o2 = D == 3 ? pos % T : 0;
+      int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+      l[axis] = side ? T - 1 : 0;
+      l[a1] = o1;
+      if (D == 3) l[a2] = o2;
+      int sb = D == 3 ? (l[0] >> 2) * 4 + (l[1] >> 2) * 2 + (l[2] >> 2) : (l[0] >> 3) * 2 + (l[1] >> 3);
+      int id = tile.brick[sb];
+      if (id < 0) continue;
+      int bit = bit_of<D>(l[0] & (kEdge<D> - 1), l[1] & (kEdge<D> - 1), D == 3 ? (l[2] & 3) : 0);
+      if (!((I.maskA[id] >> bit) & 1ull)) continue;
+      l[axis] += side ? 1 : -1;
+      int g[3] = {org[0] + l[0], org[1] + l[1], D == 3 ? org[2] + l[2] : 0};
+      int j = node_at<D>(I, g);
+      if (j < 0) continue;  // cannot happen on a closed band
+      double cp[3], out[1];
+      load_cp<D>(I, j, cp);
+      erow_lds<D, P, 1>(I, cp, U, flo, fdim, out);
+      V[vbox_index<D, 1>(l)] = out[0];
+    }
+    __syncthreads();
+
+    // 3. (2d+1)-point stencil for the tile's active nodes
+    for (int q = wave; q < NB; q += nwaves) {
+      int id = tile.brick[q];
+      if (id < 0) continue;
+      uint64_t mA = I.maskA[id];
+      if (!((mA >> lane) & 1ull)) continue;
+      int i = I.offA[id] + mbcnt64(mA);
+      int l[3];
+      local_of<D>(lane, l);
+      int sub[3] = {D == 3 ? (q >> 2) : (q >> 1), D == 3 ? ((q >> 1) & 1) : (q & 1), D == 3 ? (q & 1) : 0};
+#pragma unroll
+      for (int k = 0; k < D; ++k) l[k] += sub[k] * kEdge<D>;
+      const int vi = vbox_index<D, 1>(l);
+      double s = V[vi - S0] + V[vi + S0];
+      s += V[vi - S1] + V[vi + S1];
+      if (D == 3) s += V[vi - S2] + V[vi + S2];
+      const int64_t e = (int64_t)i * NRHS + r;
+      yb[e] = I.diag * xb[e] - I.inv_h2 * s;
+    }
+  }
+}
+
+// Slow path for tiles whose footprint exceeds the LDS budget: each active
+// node evaluates its 2d neighbours' extension rows with index lookups.
+template <int D, int P, int NRHS>
+__global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restrict__ insts,
+                                                        const WorkItem* __restrict__ work, int nwork,
+                                                        const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int NB = D == 3 ? 8 : 4;
+  const int w = blockIdx.x;
+  if (w >= nwork) return;
+  const WorkItem wi = work[w];
+  const DevInst& I = insts[wi.inst];
+  const DevTile& tile = I.tiles[wi.idx];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  for (int q = wave; q < NB; q += (blockDim.x >> 6)) {
+    int id = tile.brick[q];
+    if (id < 0) continue;
+    uint64_t mA = I.maskA[id];
+    if (!((mA >> lane) & 1ull)) continue;
+    int i = I.offA[id] + mbcnt64(mA);
+    int l[3];
+    local_of<D>(lane, l);
+    int g[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < D; ++k) g[k] = I.bcoord[id * 3 + k] * kEdge<D> + l[k];
+    double s[NRHS];
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) s[r] = 0.0;
+    for (int k = 0; k < D; ++k)
+      for (int sd = -1; sd <= 1; sd += 2) {
+        int gn[3] = {g[0], g[1], g[2]};
+        gn[k] += sd;
+        int j = node_at<D>(I, gn);
+        if (j < 0) continue;  // cannot happen on a closed band
+        double cp[3], out[NRHS];
+        load_cp<D>(I, j, cp);
+        erow_global<D, P, NRHS>(I, cp, x, out);
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) s[r] += out[r];
+      }
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) {
+      const int64_t e = (I.vec_off + i) * NRHS + r;
+      y[e] = I.diag * x[e] - I.inv_h2 * s[r];
+    }
+  }
+}
+
+// ---- transpose: z = O^T y over Sigma_A u Sigma_G
+template <int D, int NRHS>
+__global__ void __launch_bounds__(256) k_OT(DevInst I, const double* __restrict__ y, double* __restrict__ z) {
+  const int id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (id >= I.nbricks) return;
+  const int lane = lane_id();
+  uint64_t mA = I.maskA[id], mG = I.maskG[id];
+  if (!(((mA | mG) >> lane) & 1ull)) return;
+  int j = ((mA >> lane) & 1ull) ? I.offA[id] + mbcnt64(mA) : I.nA + I.offG[id] + mbcnt64(mG);
+  int l[3];
+  local_of<D>(lane, l);
+  int g[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) g[k] = I.bcoord[id * 3 + k] * kEdge<D> + l[k];
+  double s[NRHS];
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r) s[r] = 0.0;
+  for (int k = 0; k < D; ++k)
+    for (int sd = -1; sd <= 1; sd += 2) {
+      int gn[3] = {g[0], g[1], g[2]};
+      gn[k] += sd;
+      int n = node_at<D>(I, gn);
+      if (n >= 0 && n < I.nA) {
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) s[r] += y[(I.vec_off + n) * NRHS + r];
+      }
+    }
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r) z[(int64_t)j * NRHS + r] = s[r];
+}
+
+// ---- transpose: y_out = diag y - h^-2 E^T z, each output gathers the rows whose cube holds it
+template <int D, int P, int NRHS>
+__global__ void __launch_bounds__(256) k_ET(DevInst I, const double* __restrict__ yin, const double* __restrict__ z,
+                                            double* __restrict__ yout) {
+  const int id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (id >= I.nbricks) return;
+  const int lane = lane_id();
+  uint64_t mA = I.maskA[id];
+  if (!((mA >> lane) & 1ull)) return;
+  const int k = I.offA[id] + mbcnt64(mA);
+  int l[3];
+  local_of<D>(lane, l);
+  int g[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) g[a] = I.bcoord[id * 3 + a] * kEdge<D> + l[a];
+  double acc[NRHS];
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r) acc[r] = 0.0;
+  constexpr int NC = D == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1);
+  for (int c = 0; c < NC; ++c) {
+    int a[3] = {0, 0, 0};
+    int rem = c;
+    for (int q = D - 1; q >= 0; --q) { a[q] = rem % (P + 1); rem /= (P + 1); }
+    int gb[3] = {g[0] - a[0], g[1] - a[1], D == 3 ? g[2] - a[2] : 0};
+    int bnode = node_at<D>(I, gb);
+    if (bnode < 0 || bnode >= I.nA) continue;
+    for (int e = I.bucket_ptr[bnode]; e < I.bucket_ptr[bnode + 1]; ++e) {
+      int j = I.bucket_rows[e];
+      double cp[3];
+      load_cp<D>(I, j, cp);
+      double wgt = 1.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        double t = (cp[q] - I.lo[q]) / I.h;
+        double bf = floor(t - (P - 1) * 0.5);
+        double wl[P + 1];
+        lagrange<P>(t - bf, wl);
+        wgt *= wl[a[q]];
+      }
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) acc[r] += wgt * z[(int64_t)j * NRHS + r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r) {
+    const int64_t e = (I.vec_off + k) * NRHS + r;
+    yout[e] = I.diag * yin[e] - I.inv_h2 * acc[r];
+  }
+}
+
+// ------------------------------------------------------------- launchers
+template <int D, int P, int NRHS>
+static hipError_t launch_apply_t(const DevInst* insts, const WorkItem* work, int nwork, int ucap, const WorkItem* fb,
+                                 int nfb, const double* x, double* y, hipStream_t s) {
+  if (nwork > 0) {
+    size_t shm = (size_t)(ucap + vbox_doubles<D, 1>()) * sizeof(double);
+    hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(nwork), dim3(256), shm, s, insts, work, nwork, ucap, x, y);
+  }
+  if (nfb > 0) hipLaunchKernelGGL((k_apply_fallback<D, P, NRHS>), dim3(nfb), dim3(256), 0, s, insts, fb, nfb, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(int d, int p, int nrhs, const DevInst* insts, const WorkItem* work, int nwork, int ucap,
+                        const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s) {
+#define CPM_CASE(D, P, R) \
+  if (d == D && p == P && nrhs == R) return launch_apply_t<D, P, R>(insts, work, nwork, ucap, fb, nfb, x, y, s);
+  CPM_CASE(3, 3, 1) CPM_CASE(3, 3, 2) CPM_CASE(3, 3, 4)
+  CPM_CASE(3, 2, 1) CPM_CASE(3, 2, 2) CPM_CASE(3, 2, 4)
+  CPM_CASE(3, 1, 1) CPM_CASE(3, 1, 2) CPM_CASE(3, 1, 4)
+  CPM_CASE(2, 3, 1) CPM_CASE(2, 3, 2) CPM_CASE(2, 3, 4)
+  CPM_CASE(2, 2, 1) CPM_CASE(2, 2, 2) CPM_CASE(2, 2, 4)
+  CPM_CASE(2, 1, 1) CPM_CASE(2, 1, 2) CPM_CASE(2, 1, 4)
+#undef CPM_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream_t s) {
+  const int n = I.nA + I.nG;
+  if (n == 0) return hipSuccess;
+  dim3 g((n + 255) / 256), b(256);
+#define CPM_CASE(D, P) \
+  if (I.d == D && I.p == P) { hipLaunchKernelGGL((k_extend<D, P>), g, b, 0, s, I, u, v); return hipGetLastError(); }
+  CPM_CASE(3, 3) CPM_CASE(3, 2) CPM_CASE(3, 1) CPM_CASE(2, 3) CPM_CASE(2, 2) CPM_CASE(2, 1)
+#undef CPM_CASE
+  return hipErrorInvalidValue;
+}
+
+template <int D, int P, int NRHS>
+static hipError_t launch_apply_T_t(const DevInst& I, const double* x, double* z, double* y, hipStream_t s) {
+  dim3 g((I.nbricks + 3) / 4), b(256);
+  hipLaunchKernelGGL((k_OT<D, NRHS>), g, b, 0, s, I, x, z);
+  hipLaunchKernelGGL((k_ET<D, P, NRHS>), g, b, 0, s, I, x, z, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* zscratch, double* y, hipStream_t s) {
+  if (I.nbricks == 0) return hipSuccess;
+#define CPM_CASE(D, P, R) \
+  if (I.d == D && I.p == P && nrhs == R) return launch_apply_T_t<D, P, R>(I, x, zscratch, y, s);
+  CPM_CASE(3, 3, 1) CPM_CASE(3, 3, 2) CPM_CASE(3, 3, 4)
+  CPM_CASE(3, 2, 1) CPM_CASE(3, 2, 2) CPM_CASE(3, 2, 4)
+  CPM_CASE(3, 1, 1) CPM_CASE(3, 1, 2) CPM_CASE(3, 1, 4)
+  CPM_CASE(2, 3, 1) CPM_CASE(2, 3, 2) CPM_CASE(2, 3, 4)
+  CPM_CASE(2, 2, 1) CPM_CASE(2, 2, 2) CPM_CASE(2, 2, 4)
+  CPM_CASE(2, 1, 1) CPM_CASE(2, 1, 2) CPM_CASE(2, 1, 4)
+#undef CPM_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace cpm

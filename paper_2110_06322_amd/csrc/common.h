@@ -1,0 +1,82 @@
+// Host-side helpers: HIP error checks, device buffers, the operator object.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+namespace cpm {
+
+inline void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    fail(CPM_ERR_OOM, std::string(what) + ": device allocation failed");
+  fail(CPM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Owning device allocation.
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    release();
+    if (count == 0) return;
+    hip_check(hipMalloc((void**)&p, count * sizeof(T)), "hipMalloc");
+    n = count;
+  }
+  void upload(const T* src, size_t count) {
+    alloc(count);
+    if (count) hip_check(hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice), "upload");
+  }
+  void upload(const std::vector<T>& v) { upload(v.data(), v.size()); }
+};
+
+// kernel launchers (apply.hip)
+hipError_t launch_apply(int d, int p, int nrhs, const DevInst* insts, const WorkItem* work, int nwork, int ucap,
+                        const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s);
+hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream_t s);
+hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* zscratch, double* y,
+                          hipStream_t s);
+
+inline int vbox_nodes(int d) { return d == 3 ? 10 * 10 * 10 : 18 * 18; }
+constexpr size_t kApplyLdsBytes = 64 * 1024;
+
+}  // namespace cpm
+
+struct cpm_operator_s {
+  std::shared_ptr<const cpm_band_s> band;   // host copy (preconditioner setup reads it)
+  double c = 1.0;
+  cpm::DevInst I{};                         // device pointers, vec_off = 0
+  cpm::DevBuf<cpm::DevInst> d_inst;
+  cpm::DevBuf<double> d_cp;
+  cpm::DevBuf<uint64_t> d_maskA, d_maskG;
+  cpm::DevBuf<int32_t> d_offA, d_offG, d_bcoord, d_bmap, d_bptr, d_brows;
+  cpm::DevBuf<cpm::DevTile> d_tiles;
+  std::vector<cpm::DevTile> tiles;          // host copy
+  std::vector<int32_t> tile_fvol;           // footprint nodes per tile
+  cpm::DevBuf<cpm::WorkItem> d_work, d_fb;      // (instance 0, tile) lists: LDS path / fallback
+  int nwork = 0, nfb = 0, ucap = 0;
+  mutable cpm::DevBuf<double> d_z;          // transpose scratch [(nA+nG) * 4]
+  int64_t nA() const { return band->nA; }
+};

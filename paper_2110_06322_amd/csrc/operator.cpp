@@ -1,0 +1,271 @@
+// Operator setup: tiles and LDS footprints for the fused apply, extension-row
+// buckets for the atomic-free transpose, upload of the band to the device.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+using namespace cpm;
+
+namespace {
+
+void base_of(const cpm_band_s& B, const double* cp, int32_t* b) {
+  for (int k = 0; k < B.d; ++k) {
+    double t = (cp[k] - B.lo[k]) / B.h;
+    b[k] = (int32_t)std::floor(t - (B.p - 1) / 2.0);
+  }
+}
+
+void local_of(int d, int bit, int* l) {
+  if (d == 3) { l[0] = bit >> 4; l[1] = (bit >> 2) & 3; l[2] = bit & 3; }
+  else { l[0] = bit >> 3; l[1] = bit & 7; l[2] = 0; }
+}
+
+// Tiles (2^d bricks) and the bounding box of every interpolation cube a tile evaluates.
+void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<int32_t>& fvol) {
+  bool orphan = false;
+  const int d = B.d, E = brick_edge(d), T = 2 * E, P = B.p;
+  const int64_t nb = B.nbricks();
+  std::vector<int64_t> start;
+  for (int64_t i = 0; i < nb; ++i) {
+    bool fresh = i == 0;
+    if (!fresh)
+      for (int k = 0; k < d; ++k)
+        if ((B.bcoord[i * 3 + k] >> 1) != (B.bcoord[(i - 1) * 3 + k] >> 1)) fresh = true;
+    if (fresh) start.push_back(i);
+  }
+  start.push_back(nb);
+  const int64_t nt = (int64_t)start.size() - 1;
+  tiles.assign(nt, DevTile{});
+  fvol.assign(nt, 0);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t t = 0; t < nt; ++t) {
+    DevTile& tl = tiles[t];
+    for (int q = 0; q < 8; ++q) tl.brick[q] = -1;
+    for (int k = 0; k < 3; ++k) tl.origin[k] = 0;
+    for (int k = 0; k < d; ++k) tl.origin[k] = (B.bcoord[start[t] * 3 + k] >> 1) * T;
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    auto grow = [&](int64_t node) {
+      int32_t b[3];
+      base_of(B, &B.cp[node * d], b);
+      for (int k = 0; k < d; ++k) { lo[k] = std::min(lo[k], b[k]); hi[k] = std::max(hi[k], b[k] + P); }
+    };
+    for (int64_t i = start[t]; i < start[t + 1]; ++i) {
+      int sub = 0;
+      for (int k = 0; k < d; ++k) sub = sub * 2 + (B.bcoord[i * 3 + k] & 1);
+      tl.brick[sub] = (int32_t)i;
+      for (int set = 0; set < 2; ++set) {
+        uint64_t m = set == 0 ? B.maskA[i] : B.maskG[i];
+        int64_t base = set == 0 ? B.offA[i] : B.nA + B.offG[i];
+        int64_t j = 0;
+        while (m) {
+          int bit = __builtin_ctzll(m);
+          m &= m - 1;
+          int64_t node = base + j++;
+          grow(node);
+          if (set != 0) continue;
+          // face halo: outward neighbours of active nodes on the tile boundary
+          int l[3];
+          local_of(d, bit, l);
+          int32_t g[3] = {0, 0, 0};
+          for (int k = 0; k < d; ++k) g[k] = B.bcoord[i * 3 + k] * E + l[k];
+          for (int k = 0; k < d; ++k)
+            for (int s = -1; s <= 1; s += 2) {
+              int32_t gn[3] = {g[0], g[1], g[2]};
+              gn[k] += s;
+              if ((gn[k] - tl.origin[k]) >= 0 && (gn[k] - tl.origin[k]) < T) continue;
+              int64_t nn = B.lookup(gn);
+              if (nn < 0) {
+#pragma omp atomic write
+                orphan = true;
+                continue;
+              }
+              grow(nn);
+            }
+        }
+      }
+    }
+    for (int k = 0; k < 3; ++k) { tl.flo[k] = 0; tl.fdim[k] = 1; }
+    int64_t vol = 1;
+    for (int k = 0; k < d; ++k) {
+      tl.flo[k] = lo[k];
+      tl.fdim[k] = hi[k] - lo[k] + 1;
+      vol *= tl.fdim[k];
+    }
+    fvol[t] = (int32_t)std::min<int64_t>(vol, INT32_MAX);
+  }
+  if (orphan) fail(CPM_ERR_BAND, "active node without a band neighbour");
+}
+
+// Extension rows bucketed by their cube's lower corner (an active node).
+void build_buckets(const cpm_band_s& B, std::vector<int32_t>& ptr, std::vector<int32_t>& rows) {
+  const int64_t n = B.nodes();
+  std::vector<int32_t> corner(n);
+  bool bad = false;
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < n; ++j) {
+    int32_t b[3] = {0, 0, 0};
+    base_of(B, &B.cp[j * B.d], b);
+    int64_t c = B.lookup(b);
+    if (c < 0 || c >= B.nA) {
+#pragma omp atomic write
+      bad = true;
+      corner[j] = 0;
+    } else {
+      corner[j] = (int32_t)c;
+    }
+  }
+  if (bad) fail(CPM_ERR_BAND, "interpolation cube corner outside Sigma_A");
+  ptr.assign(B.nA + 1, 0);
+  for (int64_t j = 0; j < n; ++j) ptr[corner[j] + 1]++;
+  for (int64_t i = 0; i < B.nA; ++i) ptr[i + 1] += ptr[i];
+  rows.assign(n, 0);
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int64_t j = 0; j < n; ++j) rows[fill[corner[j]]++] = (int32_t)j;
+}
+
+}  // namespace
+
+cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out) {
+  (void)stream;
+  try {
+    if (!band || !out) fail(CPM_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (!(c > 0) || !std::isfinite(c)) fail(CPM_ERR_ARG, "shift c must be positive and finite");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) fail(CPM_ERR_DEVICE, "no HIP device available");
+    auto op = std::make_unique<cpm_operator_s>();
+    op->band = std::make_shared<cpm_band_s>(*band);
+    op->c = c;
+    const cpm_band_s& B = *op->band;
+    const int d = B.d;
+    const int64_t n = B.nodes();
+    build_tiles(B, op->tiles, op->tile_fvol);
+    std::vector<int32_t> bptr, brows;
+    build_buckets(B, bptr, brows);
+    // SoA closest points
+    std::vector<double> cps(n * d);
+    for (int64_t j = 0; j < n; ++j)
+      for (int k = 0; k < d; ++k) cps[k * n + j] = B.cp[j * d + k];
+    op->d_cp.upload(cps);
+    op->d_maskA.upload(B.maskA);
+    op->d_maskG.upload(B.maskG);
+    op->d_offA.upload(B.offA);
+    op->d_offG.upload(B.offG);
+    op->d_bcoord.upload(B.bcoord);
+    op->d_bmap.upload(B.bmap);
+    op->d_tiles.upload(op->tiles);
+    op->d_bptr.upload(bptr);
+    op->d_brows.upload(brows);
+    DevInst& I = op->I;
+    std::memset(&I, 0, sizeof(I));
+    I.d = d; I.p = B.p; I.nA = (int32_t)B.nA; I.nG = (int32_t)B.nG;
+    I.h = B.h;
+    I.inv_h2 = 1.0 / (B.h * B.h);
+    I.diag = c + 2.0 * d / (B.h * B.h);
+    for (int k = 0; k < 3; ++k) { I.lo[k] = B.lo[k]; I.bm_lo[k] = B.bm_lo[k]; I.bm_dim[k] = B.bm_dim[k]; }
+    I.cp = op->d_cp.p;
+    I.maskA = op->d_maskA.p; I.maskG = op->d_maskG.p;
+    I.offA = op->d_offA.p; I.offG = op->d_offG.p;
+    I.bcoord = op->d_bcoord.p; I.bmap = op->d_bmap.p;
+    I.tiles = op->d_tiles.p;
+    I.ntiles = (int32_t)op->tiles.size();
+    I.nbricks = (int32_t)B.nbricks();
+    I.bucket_ptr = op->d_bptr.p; I.bucket_rows = op->d_brows.p;
+    I.vec_off = 0;
+    op->d_inst.upload(&I, 1);
+    // work lists: tiles whose footprint fits the LDS budget, the rest take the slow path
+    const int cap = (int)(kApplyLdsBytes / sizeof(double)) - vbox_nodes(d);
+    std::vector<WorkItem> fast, slow;
+    int ucap = 0;
+    for (size_t t = 0; t < op->tiles.size(); ++t) {
+      bool has_active = false;
+      for (int q = 0; q < 8; ++q) {
+        int id = op->tiles[t].brick[q];
+        if (id >= 0 && B.maskA[id]) has_active = true;
+      }
+      if (!has_active) continue;
+      if (op->tile_fvol[t] <= cap) {
+        fast.push_back(WorkItem{0, (int32_t)t});
+        ucap = std::max(ucap, op->tile_fvol[t]);
+      } else {
+        slow.push_back(WorkItem{0, (int32_t)t});
+      }
+    }
+    op->d_work.upload(fast);
+    op->d_fb.upload(slow);
+    op->nwork = (int)fast.size();
+    op->nfb = (int)slow.size();
+    op->ucap = ucap;
+    *out = op.release();
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed in cpm_operator_create");
+    return CPM_ERR_OOM;
+  }
+}
+
+cpm_status cpm_operator_set_shift(cpm_operator* op, double c) {
+  try {
+    if (!op) fail(CPM_ERR_ARG, "null operator");
+    if (!(c > 0) || !std::isfinite(c)) fail(CPM_ERR_ARG, "shift c must be positive and finite");
+    hip_check(hipDeviceSynchronize(), "set_shift");
+    op->c = c;
+    op->I.diag = c + 2.0 * op->I.d / (op->I.h * op->I.h);
+    op->d_inst.upload(&op->I, 1);
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+double cpm_operator_get_shift(const cpm_operator* op) { return op ? op->c : 0.0; }
+int64_t cpm_operator_n_active(const cpm_operator* op) { return op ? op->band->nA : -1; }
+
+void cpm_operator_destroy(cpm_operator* op) { delete op; }
+
+cpm_status cpm_extend_apply(const cpm_operator* op, const double* u, double* v, void* stream) {
+  try {
+    if (!op || (!u && op->band->nA) || (!v && op->band->nodes())) fail(CPM_ERR_ARG, "null argument");
+    hip_check(launch_extend(op->I, u, v, (hipStream_t)stream), "cpm_extend_apply");
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+cpm_status cpm_apply(const cpm_operator* op, const double* x, double* y, int32_t nrhs, void* stream) {
+  try {
+    if (!op || !x || !y) fail(CPM_ERR_ARG, "null argument");
+    if (nrhs != 1 && nrhs != 2 && nrhs != 4) fail(CPM_ERR_ARG, "nrhs must be 1, 2 or 4");
+    if (x == y) fail(CPM_ERR_ARG, "x and y must not alias");
+    hip_check(launch_apply(op->I.d, op->I.p, nrhs, op->d_inst.p, op->d_work.p, op->nwork, op->ucap,
+                           op->d_fb.p, op->nfb, x, y, (hipStream_t)stream),
+              "cpm_apply");
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+cpm_status cpm_apply_T(const cpm_operator* op, const double* x, double* y, int32_t nrhs, void* stream) {
+  try {
+    if (!op || !x || !y) fail(CPM_ERR_ARG, "null argument");
+    if (nrhs != 1 && nrhs != 2 && nrhs != 4) fail(CPM_ERR_ARG, "nrhs must be 1, 2 or 4");
+    if (x == y) fail(CPM_ERR_ARG, "x and y must not alias");
+    op->d_z.alloc((size_t)op->band->nodes() * 4);
+    hip_check(launch_apply_T(op->I, nrhs, x, op->d_z.p, y, (hipStream_t)stream), "cpm_apply_T");
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
