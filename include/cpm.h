@@ -215,6 +215,7 @@ typedef struct {
   int32_t use_graph;      /* 1: replay each restart cycle as a captured hipGraph */
   double inner_rtol;      /* MIXED_IR: per-cycle reduction target (default 1e-4) */
   int32_t stagnation_cycles; /* cycles without 1% progress before giving up (default 50) */
+  int32_t profile;        /* 1: time operator / preconditioner kernels with hipEvents (adds syncs) */
 } cpm_solve_opts;
 
 typedef struct {

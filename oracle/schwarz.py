@@ -135,6 +135,8 @@ class Schwarz:
     def apply(self, r: np.ndarray) -> np.ndarray:
         z = np.zeros_like(r, dtype=np.float64)
         for j, idx in enumerate(self.omegas):
+            if self.factors[j] is None:
+                continue
             rl = r[idx].astype(np.float64)
             if self.subsolver == "ilu0":
                 L, U = self.factors[j]
@@ -151,11 +153,12 @@ class Schwarz:
 def build_schwarz(A: sp.csr_matrix, pattern: sp.csr_matrix, cp: np.ndarray, keys: np.ndarray,
                   h: float, n_parts: int, overlap: float, kind: str = "ras",
                   alpha: float = 4.0, alpha_cross: float = 20.0, subsolver: str = "ilu0",
-                  partition=None) -> Schwarz:
+                  partition=None, only=None) -> Schwarz:
     """Partition, overlap, local matrices, optional Robin change, local factorizations.
 
     `A` must carry values on `pattern` (see operator.values_on_pattern). `overlap`
-    is N_O, the growth in units of h.
+    is N_O, the growth in units of h. `only` restricts the local solves to the
+    listed subdomains (the others contribute zero), to sample large cases.
     """
     if partition is None:
         owner, blo, bhi = rcb_partition(cp, n_parts)
@@ -166,6 +169,10 @@ def build_schwarz(A: sp.csr_matrix, pattern: sp.csr_matrix, cp: np.ndarray, keys
     n = A.shape[0]
     S = Schwarz(owner=owner, boxes_lo=blo, boxes_hi=bhi, omegas=omegas, subsolver=subsolver)
     for j, idx in enumerate(omegas):
+        if only is not None and j not in only:
+            S.local.append(None)
+            S.factors.append(None)
+            continue
         Aj = sp.csr_matrix(A[idx][:, idx])
         Aj.sort_indices()
         inside = np.zeros(n, dtype=bool)

@@ -49,7 +49,8 @@ class PrecondInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double),
                 ("max_it", C.c_int32), ("mode", C.c_int32), ("transpose", C.c_int32),
-                ("use_graph", C.c_int32), ("inner_rtol", C.c_double), ("stagnation_cycles", C.c_int32)]
+                ("use_graph", C.c_int32), ("inner_rtol", C.c_double), ("stagnation_cycles", C.c_int32),
+                ("profile", C.c_int32)]
 
 
 class SolveStats(C.Structure):

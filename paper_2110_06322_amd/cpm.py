@@ -217,6 +217,7 @@ class SolveOptions:
     use_graph: bool = False
     inner_rtol: float = 1e-4
     stagnation_cycles: int = 50
+    profile: bool = False
 
     def to_c(self):
         o = _capi.SolveOpts()
@@ -229,6 +230,7 @@ class SolveOptions:
         o.use_graph = int(bool(self.use_graph))
         o.inner_rtol = float(self.inner_rtol)
         o.stagnation_cycles = int(self.stagnation_cycles)
+        o.profile = int(bool(self.profile))
         return o
 
 

@@ -244,16 +244,36 @@ constexpr int vbox_doubles() {
   return (D == 3 ? W * W * W : W * W) * NRHS;
 }
 
-// Fused y = A x over the tiles of one or more instances. LDS holds one
-// right-hand side at a time: U = footprint of x (ucap doubles), V = extension
-// values on the tile plus its face halo.
+template <int D> constexpr int kNbrBricks = D == 3 ? 64 : 16;   // tile bricks grown by one brick
+template <int D> constexpr int kMaxJobs = D == 3 ? 512 + 6 * 64 : 256 + 4 * 16;
+
+// LDS bytes of the fused apply besides the footprint U
+template <int D>
+constexpr size_t tile_lds_extra() {
+  return (size_t)vbox_doubles<D, 1>() * 8 + (size_t)kNbrBricks<D> * 24 + (size_t)kMaxFootprintBricks * 16 +
+         (size_t)kMaxJobs<D> * 6 + 16;
+}
+
+// Fused y = A x over the tiles of one or more instances. Per tile:
+//  A. brick directories into LDS, in parallel: the tile's brick neighbourhood
+//     (masks and offsets of the 2^d tile bricks grown by one brick) and the
+//     non-empty bricks overlapping the interpolation footprint;
+//  B. a compacted job list: every band node of the tile and every outward
+//     face neighbour of an active boundary node needs its extension row;
+//  then per right-hand side:
+//  C. stage the footprint of x into LDS (one wavefront per brick, lane = node);
+//  D. evaluate the jobs' extension rows into the LDS box V;
+//  E. (2d+1)-point stencil from V for the tile's active nodes.
 template <int D, int P, int NRHS>
-__global__ void __launch_bounds__(256) k_apply_tile(const DevInst* __restrict__ insts,
+__global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ insts,
                                                     const WorkItem* __restrict__ work, int nwork, int ucap,
                                                     const double* __restrict__ x, double* __restrict__ y) {
   extern __shared__ double smem[];
-  constexpr int NB = D == 3 ? 8 : 4;        // bricks per tile
-  constexpr int T = kTile<D>;
+  constexpr int T = kTile<D>, E = kEdge<D>, SH = kShift<D>;
+  constexpr int NBR = kNbrBricks<D>, MFB = kMaxFootprintBricks;
+  constexpr int FACE = D == 3 ? T * T : T;
+  constexpr int W = T + 2;
+  constexpr int S0 = D == 3 ? W * W : W, S1 = D == 3 ? W : 1, S2 = 1;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   if (w >= nwork) return;
   const WorkItem wi = work[w];
@@ -262,114 +282,161 @@ __global__ void __launch_bounds__(256) k_apply_tile(const DevInst* __restrict__ 
   int flo[3], fdim[3], org[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) { flo[k] = tile.flo[k]; fdim[k] = tile.fdim[k]; org[k] = tile.origin[k]; }
+  const int fcnt = tile.fb_cnt;
   double* U = smem;
-  double* V = smem + ucap;
-  const int wave = threadIdx.x >> 6, lane = lane_id();
+  double* V = U + ucap;
+  uint64_t* nbA = (uint64_t*)(V + vbox_doubles<D, 1>());
+  uint64_t* nbG = nbA + NBR;
+  uint64_t* fdM = nbG + NBR;
+  int32_t* nbOA = (int32_t*)(fdM + MFB);
+  int32_t* nbOG = nbOA + NBR;
+  int32_t* fdO = nbOG + NBR;
+  int32_t* fdR = fdO + MFB;
+  int32_t* jobJ = fdR + MFB;
+  int16_t* jobV = (int16_t*)(jobJ + kMaxJobs<D>);
+  int* njob = (int*)(jobV + kMaxJobs<D> + 2);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
   const int nwaves = blockDim.x >> 6;
   const double* xb = x + I.vec_off * NRHS;
   double* yb = y + I.vec_off * NRHS;
-  int blo[3] = {0, 0, 0}, bn[3] = {1, 1, 1};
+
+  // ---- A. directories
+  if (tid < NBR) {
+    int rel[3] = {D == 3 ? tid / 16 - 1 : tid / 4 - 1, D == 3 ? (tid / 4) % 4 - 1 : tid % 4 - 1,
+                  D == 3 ? tid % 4 - 1 : 0};
+    int g0[3] = {0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    blo[k] = flo[k] >> kShift<D>;
-    bn[k] = ((flo[k] + fdim[k] - 1) >> kShift<D>) - blo[k] + 1;
+    for (int k = 0; k < D; ++k) g0[k] = org[k] + rel[k] * E;
+    int id = brick_at<D>(I, g0);
+    nbA[tid] = id >= 0 ? I.maskA[id] : 0ull;
+    nbG[tid] = id >= 0 ? I.maskG[id] : 0ull;
+    nbOA[tid] = id >= 0 ? I.offA[id] : 0;
+    nbOG[tid] = id >= 0 ? I.offG[id] : 0;
   }
-  const int nfb = bn[0] * bn[1] * bn[2];
-  constexpr int FACE = D == 3 ? T * T : T;
-  constexpr int W = T + 2;
-  constexpr int S0 = D == 3 ? W * W : W, S1 = D == 3 ? W : 1, S2 = 1;
+  int blo[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) blo[k] = flo[k] >> SH;
+  for (int t = tid; t < fcnt; t += blockDim.x) {
+    int id = I.fbricks[tile.fb_off + t];
+    fdM[t] = I.maskA[id];
+    fdO[t] = I.offA[id];
+    int r0 = I.bcoord[id * 3] - blo[0], r1 = I.bcoord[id * 3 + 1] - blo[1];
+    int r2 = D == 3 ? I.bcoord[id * 3 + 2] - blo[2] : 0;
+    fdR[t] = (r0 << 16) | (r1 << 8) | r2;
+  }
+  if (tid == 0) *njob = 0;
+  __syncthreads();
+
+  // ---- B. job list (order is irrelevant: every job owns its V slot)
+  for (int q = wave; q < (1 << D); q += nwaves) {
+    int sub[3] = {D == 3 ? (q >> 2) : (q >> 1), D == 3 ? ((q >> 1) & 1) : (q & 1), D == 3 ? (q & 1) : 0};
+    int nbi = D == 3 ? (sub[0] + 1) * 16 + (sub[1] + 1) * 4 + (sub[2] + 1) : (sub[0] + 1) * 4 + (sub[1] + 1);
+    uint64_t mA = nbA[nbi], mG = nbG[nbi];
+    if (!(((mA | mG) >> lane) & 1ull)) continue;
+    int j = ((mA >> lane) & 1ull) ? nbOA[nbi] + mbcnt64(mA) : I.nA + nbOG[nbi] + mbcnt64(mG);
+    int l[3];
+    local_of<D>(lane, l);
+#pragma unroll
+    for (int k = 0; k < D; ++k) l[k] += sub[k] * E;
+    int pos = atomicAdd(njob, 1);
+    jobJ[pos] = j;
+    jobV[pos] = (int16_t)vbox_index<D, 1>(l);
+  }
+  for (int q = tid; q < 2 * D * FACE; q += blockDim.x) {
+    int f = q / FACE, ps = q % FACE;
+    int axis = f >> 1, side = f & 1;
+    int l[3] = {0, 0, 0};
+    int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    l[axis] = side ? T - 1 : 0;
+    l[a1] = D == 3 ? ps / T : ps;
+    if (D == 3) l[a2] = ps % T;
+    int nbi = D == 3 ? ((l[0] >> SH) + 1) * 16 + ((l[1] >> SH) + 1) * 4 + ((l[2] >> SH) + 1)
+                     : ((l[0] >> SH) + 1) * 4 + ((l[1] >> SH) + 1);
+    int bit = bit_of<D>(l[0] & (E - 1), l[1] & (E - 1), D == 3 ? (l[2] & (E - 1)) : 0);
+    if (!((nbA[nbi] >> bit) & 1ull)) continue;
+    l[axis] += side ? 1 : -1;
+    int nbo = D == 3 ? (((l[0] + E) >> SH)) * 16 + (((l[1] + E) >> SH)) * 4 + (((l[2] + E) >> SH))
+                     : (((l[0] + E) >> SH)) * 4 + (((l[1] + E) >> SH));
+    int bo = bit_of<D>(l[0] & (E - 1), l[1] & (E - 1), D == 3 ? (l[2] & (E - 1)) : 0);
+    uint64_t mA = nbA[nbo], mG = nbG[nbo];
+    int j;
+    if ((mA >> bo) & 1ull) j = nbOA[nbo] + popc_below(mA, bo);
+    else if ((mG >> bo) & 1ull) j = I.nA + nbOG[nbo] + popc_below(mG, bo);
+    else continue;  // cannot happen on a closed band
+    int pos = atomicAdd(njob, 1);
+    jobJ[pos] = j;
+    jobV[pos] = (int16_t)vbox_index<D, 1>(l);
+  }
+  __syncthreads();
+  const int nj = *njob;
 
   for (int r = 0; r < NRHS; ++r) {
-    if (r > 0) __syncthreads();
-    // 1. stage the footprint of x into LDS, brick by brick (lane = node of the brick)
-    for (int q = wave; q < nfb; q += nwaves) {
-      int bb[3];
-      bb[2] = D == 3 ? q % bn[2] : 0;
-      bb[1] = D == 3 ? (q / bn[2]) % bn[1] : q % bn[1];
-      bb[0] = D == 3 ? q / (bn[2] * bn[1]) : q / bn[1];
-      int g0[3] = {0, 0, 0};
+    // ---- C. stage the footprint of x (8 bricks per wavefront in flight)
+    int l[3];
+    local_of<D>(lane, l);
+    for (int q0 = wave; q0 < fcnt; q0 += 8 * nwaves) {
+      double val[8];
+      int slot[8];
 #pragma unroll
-      for (int k = 0; k < D; ++k) g0[k] = (blo[k] + bb[k]) << kShift<D>;
-      int id = brick_at<D>(I, g0);
-      if (id < 0) continue;
-      uint64_t m = I.maskA[id];
-      int l[3];
-      local_of<D>(lane, l);
-      int idx = I.offA[id] + mbcnt64(m);
-      bool inside = (m >> lane) & 1ull;
-      int li = 0;
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * nwaves;
+        slot[u] = -1;
+        if (q < fcnt) {
+          const uint64_t m = fdM[q];
+          if ((m >> lane) & 1ull) {
+            const int rp = fdR[q];
+            const int rel[3] = {rp >> 16, (rp >> 8) & 255, rp & 255};
+            int li = 0;
+            bool inside = true;
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        int o = g0[k] + l[k] - flo[k];
-        inside = inside && o >= 0 && o < fdim[k];
-        li = li * fdim[k] + o;
+            for (int k = 0; k < D; ++k) {
+              const int o = ((blo[k] + rel[k]) << SH) + l[k] - flo[k];
+              inside = inside && o >= 0 && o < fdim[k];
+              li = li * fdim[k] + o;
+            }
+            if (inside) {
+              slot[u] = li;
+              val[u] = xb[(int64_t)(fdO[q] + mbcnt64(m)) * NRHS + r];
+            }
+          }
+        }
       }
-      if (inside) U[li] = xb[(int64_t)idx * NRHS + r];
-    }
-    __syncthreads();
-
-    // 2a. extension rows of every band node in the tile
-    for (int q = wave; q < NB; q += nwaves) {
-      int id = tile.brick[q];
-      if (id < 0) continue;
-      uint64_t mA = I.maskA[id], mG = I.maskG[id];
-      if (!(((mA | mG) >> lane) & 1ull)) continue;
-      int j = ((mA >> lane) & 1ull) ? I.offA[id] + mbcnt64(mA) : I.nA + I.offG[id] + mbcnt64(mG);
-      double cp[3], out[1];
-      load_cp<D>(I, j, cp);
-      erow_lds<D, P, 1>(I, cp, U, flo, fdim, out);
-      int l[3];
-      local_of<D>(lane, l);
-      int sub[3] = {D == 3 ? (q >> 2) : (q >> 1), D == 3 ? ((q >> 1) & 1) : (q & 1), D == 3 ? (q & 1) : 0};
 #pragma unroll
-      for (int k = 0; k < D; ++k) l[k] += sub[k] * kEdge<D>;
-      V[vbox_index<D, 1>(l)] = out[0];
-    }
-    // 2b. face halo: outward neighbours of the tile's active boundary nodes
-    for (int q = threadIdx.x; q < 2 * D * FACE; q += blockDim.x) {
-      int f = q / FACE, pos = q % FACE;
-      int axis = f >> 1, side = f & 1;
-      int l[3] = {0, 0, 0};
-      int o1 = D == 3 ? pos / T : pos, o2 = D == 3 ? pos % T : 0;
-      int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-      l[axis] = side ? T - 1 : 0;
-      l[a1] = o1;
-      if (D == 3) l[a2] = o2;
-      int sb = D == 3 ? (l[0] >> 2) * 4 + (l[1] >> 2) * 2 + (l[2] >> 2) : (l[0] >> 3) * 2 + (l[1] >> 3);
-      int id = tile.brick[sb];
-      if (id < 0) continue;
-      int bit = bit_of<D>(l[0] & (kEdge<D> - 1), l[1] & (kEdge<D> - 1), D == 3 ? (l[2] & 3) : 0);
-      if (!((I.maskA[id] >> bit) & 1ull)) continue;
-      l[axis] += side ? 1 : -1;
-      int g[3] = {org[0] + l[0], org[1] + l[1], D == 3 ? org[2] + l[2] : 0};
-      int j = node_at<D>(I, g);
-      if (j < 0) continue;  // cannot happen on a closed band
-      double cp[3], out[1];
-      load_cp<D>(I, j, cp);
-      erow_lds<D, P, 1>(I, cp, U, flo, fdim, out);
-      V[vbox_index<D, 1>(l)] = out[0];
+      for (int u = 0; u < 8; ++u)
+        if (slot[u] >= 0) U[slot[u]] = val[u];
     }
     __syncthreads();
-
-    // 3. (2d+1)-point stencil for the tile's active nodes
-    for (int q = wave; q < NB; q += nwaves) {
-      int id = tile.brick[q];
-      if (id < 0) continue;
-      uint64_t mA = I.maskA[id];
+    // ---- D. extension rows (the next job's closest point is fetched ahead)
+    {
+      int q = tid;
+      double cpn[3] = {0, 0, 0};
+      if (q < nj) load_cp<D>(I, jobJ[q], cpn);
+      for (; q < nj; q += blockDim.x) {
+        double cp[3] = {cpn[0], cpn[1], cpn[2]};
+        const int qn = q + blockDim.x;
+        if (qn < nj) load_cp<D>(I, jobJ[qn], cpn);
+        double out[1];
+        erow_lds<D, P, 1>(I, cp, U, flo, fdim, out);
+        V[jobV[q]] = out[0];
+      }
+    }
+    __syncthreads();
+    // ---- E. stencil
+    for (int q = wave; q < (1 << D); q += nwaves) {
+      int sub[3] = {D == 3 ? (q >> 2) : (q >> 1), D == 3 ? ((q >> 1) & 1) : (q & 1), D == 3 ? (q & 1) : 0};
+      int nbi = D == 3 ? (sub[0] + 1) * 16 + (sub[1] + 1) * 4 + (sub[2] + 1) : (sub[0] + 1) * 4 + (sub[1] + 1);
+      uint64_t mA = nbA[nbi];
       if (!((mA >> lane) & 1ull)) continue;
-      int i = I.offA[id] + mbcnt64(mA);
-      int l[3];
-      local_of<D>(lane, l);
-      int sub[3] = {D == 3 ? (q >> 2) : (q >> 1), D == 3 ? ((q >> 1) & 1) : (q & 1), D == 3 ? (q & 1) : 0};
-#pragma unroll
-      for (int k = 0; k < D; ++k) l[k] += sub[k] * kEdge<D>;
-      const int vi = vbox_index<D, 1>(l);
+      int i = nbOA[nbi] + mbcnt64(mA);
+      int ll[3] = {l[0] + sub[0] * E, l[1] + sub[1] * E, l[2] + sub[2] * E};
+      const int vi = vbox_index<D, 1>(ll);
       double s = V[vi - S0] + V[vi + S0];
       s += V[vi - S1] + V[vi + S1];
       if (D == 3) s += V[vi - S2] + V[vi + S2];
       const int64_t e = (int64_t)i * NRHS + r;
       yb[e] = I.diag * xb[e] - I.inv_h2 * s;
     }
+    if (r + 1 < NRHS) __syncthreads();
   }
 }
 
@@ -506,8 +573,8 @@ template <int D, int P, int NRHS>
 static hipError_t launch_apply_t(const DevInst* insts, const WorkItem* work, int nwork, int ucap, const WorkItem* fb,
                                  int nfb, const double* x, double* y, hipStream_t s) {
   if (nwork > 0) {
-    size_t shm = (size_t)(ucap + vbox_doubles<D, 1>()) * sizeof(double);
-    hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(nwork), dim3(256), shm, s, insts, work, nwork, ucap, x, y);
+    size_t shm = (size_t)ucap * sizeof(double) + tile_lds_extra<D>();
+    hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(nwork), dim3(512), shm, s, insts, work, nwork, ucap, x, y);
   }
   if (nfb > 0) hipLaunchKernelGGL((k_apply_fallback<D, P, NRHS>), dim3(nfb), dim3(256), 0, s, insts, fb, nfb, x, y);
   return hipGetLastError();

@@ -60,10 +60,16 @@ hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* z
                           hipStream_t s);
 
 inline int vbox_nodes(int d) { return d == 3 ? 10 * 10 * 10 : 18 * 18; }
+// LDS of the fused apply besides the footprint (kept equal to tile_lds_extra<D>() in apply.hip)
+inline size_t tile_lds_extra_bytes(int d) {
+  const size_t nbr = d == 3 ? 64 : 16, jobs = d == 3 ? 512 + 6 * 64 : 256 + 4 * 16;
+  return (size_t)vbox_nodes(d) * 8 + nbr * 24 + (size_t)kMaxFootprintBricks * 16 + jobs * 6 + 16;
+}
 constexpr size_t kApplyLdsBytes = 64 * 1024;
 
 }  // namespace cpm
 
+struct cpm_batch_s;
 struct cpm_operator_s {
   std::shared_ptr<const cpm_band_s> band;   // host copy (preconditioner setup reads it)
   double c = 1.0;
@@ -73,10 +79,15 @@ struct cpm_operator_s {
   cpm::DevBuf<uint64_t> d_maskA, d_maskG;
   cpm::DevBuf<int32_t> d_offA, d_offG, d_bcoord, d_bmap, d_bptr, d_brows;
   cpm::DevBuf<cpm::DevTile> d_tiles;
+  cpm::DevBuf<int32_t> d_fbricks;
   std::vector<cpm::DevTile> tiles;          // host copy
   std::vector<int32_t> tile_fvol;           // footprint nodes per tile
   cpm::DevBuf<cpm::WorkItem> d_work, d_fb;      // (instance 0, tile) lists: LDS path / fallback
+  std::vector<cpm::WorkItem> h_work, h_fb;
   int nwork = 0, nfb = 0, ucap = 0;
+  // workspace of single solves (one solve at a time per operator)
+  mutable std::shared_ptr<cpm_batch_s> solve_cache;
+  mutable int64_t solve_cache_key = -1;
   mutable cpm::DevBuf<double> d_z;          // transpose scratch [(nA+nG) * 4]
   int64_t nA() const { return band->nA; }
 };

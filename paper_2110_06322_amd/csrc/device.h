@@ -12,7 +12,11 @@ struct DevTile {
   int32_t brick[8];    // brick ids (-1 when absent); 3-D index bx*4+by*2+bz, 2-D bx*2+by
   int32_t flo[3];      // LDS footprint of the tile's interpolation cubes: lower corner
   int32_t fdim[3];     //   and extent (node units)
+  int32_t fb_off;      // non-empty bricks overlapping the footprint: fbricks[fb_off .. fb_off+fb_cnt)
+  int32_t fb_cnt;
 };
+
+constexpr int kMaxFootprintBricks = 256;
 
 struct DevInst {
   int32_t d, p, nA, nG;
@@ -27,6 +31,7 @@ struct DevInst {
   const int32_t* bmap;      // dense brick map over [bm_lo, bm_lo+bm_dim), -1 = none
   int32_t bm_lo[3], bm_dim[3];
   const DevTile* tiles;
+  const int32_t* fbricks;   // per-tile footprint brick lists
   int32_t ntiles;
   int32_t nbricks;
   // transpose: extension rows bucketed by their cube's lower-corner node (an active node)

@@ -24,7 +24,8 @@ void local_of(int d, int bit, int* l) {
 }
 
 // Tiles (2^d bricks) and the bounding box of every interpolation cube a tile evaluates.
-void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<int32_t>& fvol) {
+void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<int32_t>& fvol,
+                 std::vector<int32_t>& fbricks) {
   bool orphan = false;
   const int d = B.d, E = brick_edge(d), T = 2 * E, P = B.p;
   const int64_t nb = B.nbricks();
@@ -40,6 +41,7 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
   const int64_t nt = (int64_t)start.size() - 1;
   tiles.assign(nt, DevTile{});
   fvol.assign(nt, 0);
+  std::vector<std::vector<int32_t>> fb(nt);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t t = 0; t < nt; ++t) {
     DevTile& tl = tiles[t];
@@ -95,6 +97,32 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
       vol *= tl.fdim[k];
     }
     fvol[t] = (int32_t)std::min<int64_t>(vol, INT32_MAX);
+    // non-empty Sigma_A bricks overlapping the footprint
+    const int sh = brick_shift(d);
+    int32_t b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
+    for (int k = 0; k < d; ++k) { b0[k] = lo[k] >> sh; b1[k] = hi[k] >> sh; }
+    for (int32_t x = b0[0]; x <= b1[0]; ++x)
+      for (int32_t yv = b0[1]; yv <= b1[1]; ++yv)
+        for (int32_t z = b0[2]; z <= (d == 3 ? b1[2] : b0[2]); ++z) {
+          int32_t g[3] = {x << sh, yv << sh, d == 3 ? (z << sh) : 0};
+          int32_t rel[3] = {0, 0, 0};
+          bool in = true;
+          for (int k = 0; k < d; ++k) {
+            rel[k] = (g[k] >> sh) - B.bm_lo[k];
+            if (g[k] < 0 || rel[k] < 0 || rel[k] >= B.bm_dim[k]) in = false;
+          }
+          if (!in) continue;
+          int64_t bi = d == 3 ? ((int64_t)rel[0] * B.bm_dim[1] + rel[1]) * B.bm_dim[2] + rel[2]
+                              : (int64_t)rel[0] * B.bm_dim[1] + rel[1];
+          int32_t id = B.bmap[bi];
+          if (id >= 0 && B.maskA[id]) fb[t].push_back(id);
+        }
+    tl.fb_cnt = (int32_t)fb[t].size();
+  }
+  fbricks.clear();
+  for (int64_t t = 0; t < nt; ++t) {
+    tiles[t].fb_off = (int32_t)fbricks.size();
+    fbricks.insert(fbricks.end(), fb[t].begin(), fb[t].end());
   }
   if (orphan) fail(CPM_ERR_BAND, "active node without a band neighbour");
 }
@@ -142,7 +170,9 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     const cpm_band_s& B = *op->band;
     const int d = B.d;
     const int64_t n = B.nodes();
-    build_tiles(B, op->tiles, op->tile_fvol);
+    std::vector<int32_t> fbricks;
+    build_tiles(B, op->tiles, op->tile_fvol, fbricks);
+    op->d_fbricks.upload(fbricks);
     std::vector<int32_t> bptr, brows;
     build_buckets(B, bptr, brows);
     // SoA closest points
@@ -171,13 +201,14 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     I.offA = op->d_offA.p; I.offG = op->d_offG.p;
     I.bcoord = op->d_bcoord.p; I.bmap = op->d_bmap.p;
     I.tiles = op->d_tiles.p;
+    I.fbricks = op->d_fbricks.p;
     I.ntiles = (int32_t)op->tiles.size();
     I.nbricks = (int32_t)B.nbricks();
     I.bucket_ptr = op->d_bptr.p; I.bucket_rows = op->d_brows.p;
     I.vec_off = 0;
     op->d_inst.upload(&I, 1);
     // work lists: tiles whose footprint fits the LDS budget, the rest take the slow path
-    const int cap = (int)(kApplyLdsBytes / sizeof(double)) - vbox_nodes(d);
+    const int cap = (int)((kApplyLdsBytes - tile_lds_extra_bytes(d)) / sizeof(double));
     std::vector<WorkItem> fast, slow;
     int ucap = 0;
     for (size_t t = 0; t < op->tiles.size(); ++t) {
@@ -187,7 +218,7 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
         if (id >= 0 && B.maskA[id]) has_active = true;
       }
       if (!has_active) continue;
-      if (op->tile_fvol[t] <= cap) {
+      if (op->tile_fvol[t] <= cap && op->tiles[t].fb_cnt <= kMaxFootprintBricks) {
         fast.push_back(WorkItem{0, (int32_t)t});
         ucap = std::max(ucap, op->tile_fvol[t]);
       } else {
@@ -196,6 +227,8 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     }
     op->d_work.upload(fast);
     op->d_fb.upload(slow);
+    op->h_work = fast;
+    op->h_fb = slow;
     op->nwork = (int)fast.size();
     op->nfb = (int)slow.size();
     op->ucap = ucap;

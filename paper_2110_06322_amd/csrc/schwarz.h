@@ -1,0 +1,80 @@
+// Schwarz preconditioner: host setup result and the device-side view.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "common.h"
+
+namespace cpm {
+
+struct SchwarzHost {
+  struct Sub {
+    int n = 0;
+    int64_t nnz = 0;
+    int levels = 0;
+    std::vector<int32_t> rows;     // global active indices of Omega_j, local order
+    std::vector<int32_t> perm;     // input slot q takes local row perm[q] (pivoting; identity for ILU)
+    std::vector<int64_t> lptr, uptr;
+    std::vector<uint16_t> lcol, ucol;
+    std::vector<double> lval, uval, dinv;
+  };
+  int nparts = 0;
+  int64_t global_nnz = 0;
+  std::vector<int32_t> owner;
+  std::vector<Sub> subs;
+};
+
+void build_schwarz_host(const cpm_band_s& B, double c, const cpm_precond_opts& o, SchwarzHost& S);
+void extension_row(const cpm_band_s& B, int64_t n, std::vector<int32_t>& cols, std::vector<double>& w);
+void operator_row(const cpm_band_s& B, double c, int64_t i, std::vector<int32_t>& cols, std::vector<double>& vals,
+                  std::vector<int32_t>& scratch_c, std::vector<double>& scratch_w);
+
+// One subdomain as the kernel sees it (offsets into the preconditioner's packed arrays).
+struct DevSub {
+  int64_t row_off;   // into in_idx / out_idx / dinv (n entries)
+  int64_t ptr_off;   // into lptr / uptr (n + 1 entries)
+  int32_t n;
+  int32_t pad;
+};
+
+struct DevPC {
+  int32_t nparts;
+  int32_t fp32;                 // values (lval, uval, dinv) are float
+  const DevSub* subs;
+  const int32_t* in_idx;        // global node feeding input slot q
+  const int32_t* out_idx;       // global node of local row q, bit 31 set when owned
+  const int64_t* lptr;
+  const int64_t* uptr;
+  const uint16_t* lcol;
+  const uint16_t* ucol;
+  const void* lval;
+  const void* uval;
+  const void* dinv;
+  int32_t* error_flag;          // set when a bounded wait expires
+  int64_t vec_off;              // node offset of this instance inside packed batch vectors
+};
+
+int64_t next_serial();
+hipError_t launch_schwarz(const DevPC* pcs, const WorkItem* work, int nwork, int max_rows, int fp32, int nrhs,
+                          const double* r, double* z, hipStream_t s);
+
+}  // namespace cpm
+
+struct cpm_precond_s {
+  const cpm_operator_s* op = nullptr;
+  cpm_precond_opts opts{};
+  cpm::SchwarzHost host;        // partition and sizes kept for export / info (factor arrays freed)
+  cpm::DevPC P{};
+  cpm::DevBuf<cpm::DevPC> d_pc;
+  cpm::DevBuf<cpm::DevSub> d_subs;
+  cpm::DevBuf<int32_t> d_in, d_out, d_err;
+  cpm::DevBuf<int64_t> d_lptr, d_uptr;
+  cpm::DevBuf<uint16_t> d_lcol, d_ucol;
+  cpm::DevBuf<char> d_lval, d_uval, d_dinv;
+  cpm::DevBuf<cpm::WorkItem> d_work;
+  std::vector<cpm::WorkItem> h_work;
+  int64_t serial = 0;           // identifies this preconditioner in solver caches
+  int max_rows = 0, max_levels = 0;
+  int64_t total_rows = 0, total_nnz = 0;
+};

@@ -1,0 +1,216 @@
+// C ABI of the (O)RAS preconditioner: setup on the host, packed upload, apply.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "schwarz.h"
+
+using namespace cpm;
+
+cpm_status cpm_precond_opts_default(cpm_precond_opts* o) {
+  if (!o) { set_error("null argument"); return CPM_ERR_ARG; }
+  o->kind = CPM_PC_ORAS;
+  o->n_parts = 64;
+  o->overlap = 2.0;
+  o->alpha = 4.0;
+  o->alpha_cross = 20.0;
+  o->subsolver = CPM_SUB_ILU0;
+  o->precision = CPM_PREC_FP64;
+  o->transpose = 0;
+  return CPM_OK;
+}
+
+namespace {
+
+template <class T>
+void pack_values(const std::vector<SchwarzHost::Sub>& subs, bool lower, std::vector<T>& out) {
+  size_t tot = 0;
+  for (auto& s : subs) tot += lower ? s.lval.size() : s.uval.size();
+  out.resize(tot);
+  size_t o = 0;
+  for (auto& s : subs) {
+    const auto& v = lower ? s.lval : s.uval;
+    for (double x : v) out[o++] = (T)x;
+  }
+}
+
+template <class T>
+void upload_values(cpm_precond_s* pc) {
+  const auto& subs = pc->host.subs;
+  std::vector<T> lv, uv, dv;
+  pack_values(subs, true, lv);
+  pack_values(subs, false, uv);
+  for (auto& s : subs)
+    for (double x : s.dinv) dv.push_back((T)x);
+  pc->d_lval.upload(reinterpret_cast<const char*>(lv.data()), lv.size() * sizeof(T));
+  pc->d_uval.upload(reinterpret_cast<const char*>(uv.data()), uv.size() * sizeof(T));
+  pc->d_dinv.upload(reinterpret_cast<const char*>(dv.data()), dv.size() * sizeof(T));
+}
+
+}  // namespace
+
+cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* opts, cpm_precond** out) {
+  try {
+    if (!op || !opts || !out) fail(CPM_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (opts->kind != CPM_PC_RAS && opts->kind != CPM_PC_ORAS) fail(CPM_ERR_ARG, "kind must be RAS or ORAS");
+    if (opts->subsolver != CPM_SUB_ILU0 && opts->subsolver != CPM_SUB_DENSE_LU) fail(CPM_ERR_ARG, "bad subsolver");
+    if (opts->precision != CPM_PREC_FP64 && opts->precision != CPM_PREC_FP32) fail(CPM_ERR_ARG, "bad precision");
+    auto pc = std::make_unique<cpm_precond_s>();
+    pc->op = op;
+    pc->opts = *opts;
+    build_schwarz_host(*op->band, op->c, *opts, pc->host);
+    SchwarzHost& H = pc->host;
+    const int np = H.nparts;
+    std::vector<DevSub> subs(np);
+    std::vector<int32_t> in_idx, out_idx;
+    std::vector<int64_t> lptr, uptr;
+    std::vector<uint16_t> lcol, ucol;
+    int64_t row_off = 0, loff = 0, uoff = 0;
+    for (int j = 0; j < np; ++j) {
+      const auto& s = H.subs[j];
+      subs[j].row_off = row_off;
+      subs[j].ptr_off = row_off + j;
+      subs[j].n = s.n;
+      subs[j].pad = 0;
+      for (int q = 0; q < s.n; ++q) {
+        in_idx.push_back(s.rows[s.perm[q]]);
+        int32_t g = s.rows[q];
+        out_idx.push_back(H.owner[g] == j ? (int32_t)(g | 0x80000000u) : g);
+      }
+      for (int q = 0; q <= s.n; ++q) {
+        lptr.push_back(loff + s.lptr[q]);
+        uptr.push_back(uoff + s.uptr[q]);
+      }
+      lcol.insert(lcol.end(), s.lcol.begin(), s.lcol.end());
+      ucol.insert(ucol.end(), s.ucol.begin(), s.ucol.end());
+      loff += (int64_t)s.lcol.size();
+      uoff += (int64_t)s.ucol.size();
+      row_off += s.n;
+      pc->max_rows = std::max(pc->max_rows, s.n);
+      pc->max_levels = std::max(pc->max_levels, s.levels);
+      pc->total_nnz += s.nnz;
+    }
+    pc->total_rows = row_off;
+    pc->d_subs.upload(subs);
+    pc->d_in.upload(in_idx);
+    pc->d_out.upload(out_idx);
+    pc->d_lptr.upload(lptr);
+    pc->d_uptr.upload(uptr);
+    pc->d_lcol.upload(lcol);
+    pc->d_ucol.upload(ucol);
+    const bool fp32 = opts->precision == CPM_PREC_FP32;
+    if (fp32) upload_values<float>(pc.get());
+    else upload_values<double>(pc.get());
+    int32_t zero = 0;
+    pc->d_err.upload(&zero, 1);
+    // release the host factors; keep partition and row lists for export
+    for (auto& s : H.subs) {
+      std::vector<int64_t>().swap(s.lptr);
+      std::vector<int64_t>().swap(s.uptr);
+      std::vector<uint16_t>().swap(s.lcol);
+      std::vector<uint16_t>().swap(s.ucol);
+      std::vector<double>().swap(s.lval);
+      std::vector<double>().swap(s.uval);
+      std::vector<double>().swap(s.dinv);
+      std::vector<int32_t>().swap(s.perm);
+    }
+    DevPC& P = pc->P;
+    std::memset(&P, 0, sizeof(P));
+    P.nparts = np;
+    P.fp32 = fp32 ? 1 : 0;
+    P.subs = pc->d_subs.p;
+    P.in_idx = pc->d_in.p;
+    P.out_idx = pc->d_out.p;
+    P.lptr = pc->d_lptr.p;
+    P.uptr = pc->d_uptr.p;
+    P.lcol = pc->d_lcol.p;
+    P.ucol = pc->d_ucol.p;
+    P.lval = pc->d_lval.p;
+    P.uval = pc->d_uval.p;
+    P.dinv = pc->d_dinv.p;
+    P.error_flag = pc->d_err.p;
+    P.vec_off = 0;
+    pc->d_pc.upload(&P, 1);
+    // largest subdomains first
+    std::vector<int> order(np);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return H.subs[a].n > H.subs[b].n; });
+    std::vector<WorkItem> work(np);
+    for (int j = 0; j < np; ++j) work[j] = WorkItem{0, order[j]};
+    pc->d_work.upload(work);
+    pc->h_work = work;
+    pc->serial = next_serial();
+    *out = pc.release();
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed in cpm_precond_create");
+    return CPM_ERR_OOM;
+  }
+}
+
+cpm_status cpm_precond_get_info(const cpm_precond* pc, cpm_precond_info* info) {
+  if (!pc || !info) { set_error("null argument"); return CPM_ERR_ARG; }
+  std::memset(info, 0, sizeof(*info));
+  info->n_parts = pc->host.nparts;
+  info->total_rows = pc->total_rows;
+  info->total_nnz = pc->total_nnz;
+  info->max_rows = pc->max_rows;
+  info->max_levels = pc->max_levels;
+  info->precision = pc->opts.precision;
+  info->kind = pc->opts.kind;
+  return CPM_OK;
+}
+
+cpm_status cpm_precond_export_partition(const cpm_precond* pc, int32_t* owner, int64_t* ovl_ptr, int32_t* ovl_idx) {
+  if (!pc) { set_error("null argument"); return CPM_ERR_ARG; }
+  const auto& H = pc->host;
+  if (owner) std::memcpy(owner, H.owner.data(), H.owner.size() * sizeof(int32_t));
+  int64_t o = 0;
+  for (int j = 0; j < H.nparts; ++j) {
+    if (ovl_ptr) ovl_ptr[j] = o;
+    if (ovl_idx) std::memcpy(ovl_idx + o, H.subs[j].rows.data(), H.subs[j].rows.size() * sizeof(int32_t));
+    o += (int64_t)H.subs[j].rows.size();
+  }
+  if (ovl_ptr) ovl_ptr[H.nparts] = o;
+  return CPM_OK;
+}
+
+namespace cpm {
+// z = M^-1 r for one preconditioner (also used by the solver)
+hipError_t precond_apply_raw(const cpm_precond_s* pc, const double* r, double* z, int nrhs, hipStream_t s) {
+  return launch_schwarz(pc->d_pc.p, pc->d_work.p, pc->host.nparts, pc->max_rows, pc->P.fp32, nrhs, r, z, s);
+}
+// error flag of the bounded waits (0 = fine); resets it
+int precond_take_error(const cpm_precond_s* pc) {
+  int32_t v = 0;
+  if (hipMemcpy(&v, pc->d_err.p, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return 1;
+  if (v) {
+    int32_t zero = 0;
+    (void)hipMemcpy(pc->d_err.p, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  }
+  return v;
+}
+}  // namespace cpm
+
+cpm_status cpm_precond_apply(const cpm_precond* pc, const double* r, double* z, int32_t nrhs, void* stream) {
+  try {
+    if (!pc || !r || !z) fail(CPM_ERR_ARG, "null argument");
+    if (nrhs != 1 && nrhs != 2 && nrhs != 4) fail(CPM_ERR_ARG, "nrhs must be 1, 2 or 4");
+    if (r == z) fail(CPM_ERR_ARG, "r and z must not alias");
+    hipError_t e = precond_apply_raw(pc, r, z, nrhs, (hipStream_t)stream);
+    if (e == hipErrorInvalidConfiguration)
+      fail(CPM_ERR_ARG, "subdomains too large for the local-memory budget at this nrhs/precision");
+    hip_check(e, "cpm_precond_apply");
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+void cpm_precond_destroy(cpm_precond* pc) { delete pc; }

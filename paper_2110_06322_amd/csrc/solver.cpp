@@ -1,0 +1,513 @@
+// Restarted right-preconditioned FGMRES on the GPU for one or many systems
+// (Sec. 4.1.1: GMRES with the DD preconditioners), with CGS2 orthogonalisation,
+// device-side Givens rotations, one host synchronisation per restart cycle and
+// a one-step-lagged convergence poll inside a cycle. GMRES-based iterative
+// refinement (Carson & Higham 2017) reuses the same cycle: every restart
+// recomputes r = f - A u in FP64 and solves the correction to inner_rtol with
+// the FP32 preconditioner.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "krylov.h"
+#include "schwarz.h"
+
+using namespace cpm;
+
+namespace cpm {
+hipError_t precond_apply_raw(const cpm_precond_s* pc, const double* r, double* z, int nrhs, hipStream_t s);
+int precond_take_error(const cpm_precond_s* pc);
+}  // namespace cpm
+
+struct cpm_batch_s {
+  int ni = 0, R = 1, ns = 0, d = 3, p = 3;
+  std::vector<const cpm_operator_s*> ops;
+  std::vector<const cpm_precond_s*> pcs;
+  std::vector<int64_t> off;
+  int64_t Ntot = 0;
+  // operator apply over all instances
+  std::vector<DevInst> hinst;
+  DevBuf<DevInst> d_insts;
+  DevBuf<WorkItem> d_work, d_fb;
+  int nwork = 0, nfb = 0, ucap = 0;
+  // preconditioners
+  bool any_pc = false, all_pc = true;
+  int pc_fp32 = 0, pc_transpose = -1, max_rows = 0, npcwork = 0;
+  DevBuf<DevPC> d_pcs;
+  DevBuf<WorkItem> d_pcwork;
+  DevBuf<int32_t> d_copy_inst;
+  // reduction chunks
+  std::vector<Chunk> chunks;
+  DevBuf<Chunk> d_chunks;
+  std::vector<int32_t> cbeg;
+  DevBuf<int32_t> d_cbeg;
+  int nchunks = 0;
+  // workspace
+  int m_alloc = 0;
+  DevBuf<double> V, Z, w, r, t, f, x, part, partn, zT;
+  DevBuf<double> H, g, cs, sn, y, hcol, hv, nrm2, beta, scale, tol_in, est;
+  DevBuf<int32_t> act, steps, bad, n_active;
+  int32_t* h_nact = nullptr;   // pinned [2]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~cpm_batch_s() {
+    if (h_nact) (void)hipHostFree(h_nact);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const cpm_precond_s* const* pcs, int R) {
+  if (n < 1) fail(CPM_ERR_ARG, "empty batch");
+  if (R != 1 && R != 2 && R != 4) fail(CPM_ERR_ARG, "nrhs must be 1, 2 or 4");
+  if ((int64_t)n * R > kMaxSystems) fail(CPM_ERR_ARG, "too many systems in one batch (max 1024)");
+  Bt.ni = n;
+  Bt.R = R;
+  Bt.ns = n * R;
+  Bt.d = ops[0]->I.d;
+  Bt.p = ops[0]->I.p;
+  Bt.off.assign(n + 1, 0);
+  std::vector<WorkItem> fast, slow, pcw;
+  std::vector<DevPC> hpcs(n);
+  std::vector<int32_t> copy_inst(n, 0);
+  for (int i = 0; i < n; ++i) {
+    const cpm_operator_s* op = ops[i];
+    if (!op) fail(CPM_ERR_ARG, "null operator in batch");
+    if (op->I.d != Bt.d || op->I.p != Bt.p) fail(CPM_ERR_ARG, "all operators of a batch need the same d and p");
+    Bt.ops.push_back(op);
+    Bt.off[i + 1] = Bt.off[i] + op->band->nA;
+    DevInst I = op->I;
+    I.vec_off = Bt.off[i];
+    Bt.hinst.push_back(I);
+    for (const WorkItem& wi : op->h_work) fast.push_back(WorkItem{i, wi.idx});
+    for (const WorkItem& wi : op->h_fb) slow.push_back(WorkItem{i, wi.idx});
+    Bt.ucap = std::max(Bt.ucap, op->ucap);
+    const cpm_precond_s* pc = pcs ? pcs[i] : nullptr;
+    Bt.pcs.push_back(pc);
+    if (pc) {
+      if (pc->op != op) fail(CPM_ERR_ARG, "preconditioner built for another operator");
+      if (Bt.any_pc && pc->P.fp32 != Bt.pc_fp32) fail(CPM_ERR_ARG, "mixed preconditioner precisions in one batch");
+      if (Bt.pc_transpose >= 0 && pc->opts.transpose != Bt.pc_transpose)
+        fail(CPM_ERR_ARG, "mixed transposed / plain preconditioners in one batch");
+      Bt.pc_fp32 = pc->P.fp32;
+      Bt.pc_transpose = pc->opts.transpose;
+      Bt.any_pc = true;
+      DevPC P = pc->P;
+      P.vec_off = Bt.off[i];
+      hpcs[i] = P;
+      for (const WorkItem& wi : pc->h_work) pcw.push_back(WorkItem{i, wi.idx});
+      Bt.max_rows = std::max(Bt.max_rows, pc->max_rows);
+    } else {
+      Bt.all_pc = false;
+      copy_inst[i] = 1;
+      std::memset(&hpcs[i], 0, sizeof(DevPC));
+    }
+  }
+  Bt.Ntot = Bt.off[n];
+  Bt.d_insts.upload(Bt.hinst);
+  Bt.d_work.upload(fast);
+  Bt.d_fb.upload(slow);
+  Bt.nwork = (int)fast.size();
+  Bt.nfb = (int)slow.size();
+  // largest subdomains first across the whole batch
+  if (Bt.any_pc) {
+    std::stable_sort(pcw.begin(), pcw.end(), [&](const WorkItem& a, const WorkItem& b) {
+      return pcs[a.inst]->host.subs[a.idx].n > pcs[b.inst]->host.subs[b.idx].n;
+    });
+    Bt.d_pcs.upload(hpcs);
+    Bt.d_pcwork.upload(pcw);
+    Bt.npcwork = (int)pcw.size();
+  }
+  Bt.d_copy_inst.upload(copy_inst);
+  Bt.cbeg.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const int64_t nA = ops[i]->band->nA;
+    for (int64_t a = 0; a < nA; a += kChunkNodes)
+      Bt.chunks.push_back(Chunk{i, 0, Bt.off[i] + a, std::min<int64_t>(kChunkNodes, nA - a)});
+    Bt.cbeg[i + 1] = (int32_t)Bt.chunks.size();
+  }
+  Bt.nchunks = (int)Bt.chunks.size();
+  Bt.d_chunks.upload(Bt.chunks);
+  Bt.d_cbeg.upload(Bt.cbeg);
+  hip_check(hipHostMalloc((void**)&Bt.h_nact, 2 * sizeof(int32_t)), "hipHostMalloc");
+  for (auto& e : Bt.ev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+}
+
+void ensure_workspace(cpm_batch_s& Bt, int m) {
+  const size_t Ns = (size_t)Bt.Ntot * Bt.R;
+  if (Bt.m_alloc < m) {
+    Bt.V.alloc(Ns * (m + 1));
+    Bt.Z.alloc(Ns * m);
+    Bt.part.alloc((size_t)(m + 1) * Bt.nchunks * Bt.R);
+    const size_t ns = Bt.ns;
+    Bt.H.alloc(ns * (m + 1) * m);
+    Bt.g.alloc(ns * (m + 1));
+    Bt.cs.alloc(ns * m);
+    Bt.sn.alloc(ns * m);
+    Bt.y.alloc(ns * m);
+    Bt.hcol.alloc(ns * (m + 1));
+    Bt.hv.alloc(ns * (m + 1));
+    Bt.m_alloc = m;
+  }
+  Bt.w.alloc(Ns);
+  Bt.r.alloc(Ns);
+  Bt.t.alloc(Ns);
+  Bt.f.alloc(Ns);
+  Bt.x.alloc(Ns);
+  Bt.partn.alloc((size_t)Bt.nchunks * Bt.R);
+  const size_t ns = Bt.ns;
+  Bt.nrm2.alloc(ns);
+  Bt.beta.alloc(ns);
+  Bt.scale.alloc(ns);
+  Bt.tol_in.alloc(ns);
+  Bt.est.alloc(ns);
+  Bt.act.alloc(ns);
+  Bt.steps.alloc(ns);
+  Bt.bad.alloc(ns);
+  Bt.n_active.alloc(1);
+}
+
+GmresState state_of(cpm_batch_s& Bt, int m) {
+  GmresState S;
+  std::memset(&S, 0, sizeof(S));
+  S.m = m;
+  S.H = Bt.H.p; S.g = Bt.g.p; S.cs = Bt.cs.p; S.sn = Bt.sn.p; S.y = Bt.y.p;
+  S.hcol = Bt.hcol.p; S.hv = Bt.hv.p; S.nrm2 = Bt.nrm2.p; S.beta = Bt.beta.p; S.scale = Bt.scale.p;
+  S.tol_in = Bt.tol_in.p; S.est = Bt.est.p; S.act = Bt.act.p; S.steps = Bt.steps.p; S.bad = Bt.bad.p;
+  S.n_active = Bt.n_active.p;
+  return S;
+}
+
+// y = A x (or A^T x) over all instances of the batch, packed layout
+void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hipStream_t s) {
+  if (!transpose) {
+    hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap, Bt.d_fb.p, Bt.nfb, x, y, s),
+              "operator apply");
+    return;
+  }
+  int64_t mx = 0;
+  for (auto* op : Bt.ops) mx = std::max<int64_t>(mx, op->band->nodes());
+  Bt.zT.alloc((size_t)mx * Bt.R);
+  for (int i = 0; i < Bt.ni; ++i)
+    hip_check(launch_apply_T(Bt.hinst[i], Bt.R, x, Bt.zT.p, y, s), "transposed operator apply");
+}
+
+void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s) {
+  if (Bt.any_pc) {
+    hipError_t e = launch_schwarz(Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.pc_fp32, Bt.R, v, z, s);
+    if (e == hipErrorInvalidConfiguration)
+      fail(CPM_ERR_ARG, "subdomains too large for the local-memory budget at this nrhs/precision");
+    hip_check(e, "preconditioner apply");
+  }
+  if (!Bt.all_pc) hip_check(vec_copy(Bt.R, v, z, Bt.d_chunks.p, Bt.nchunks, Bt.d_copy_inst.p, s), "copy");
+}
+
+// |v|^2 per system (packed v) into host array
+void norms2(cpm_batch_s& Bt, const double* v, const double* t, double* r, std::vector<double>& out, hipStream_t s) {
+  hip_check(vec_residual(Bt.R, v, t, r, Bt.d_chunks.p, Bt.nchunks, Bt.partn.p, s), "norm");
+  hip_check(vec_reduce(Bt.R, Bt.partn.p, 1, Bt.nchunks, Bt.d_cbeg.p, Bt.ns, Bt.nrm2.p, 1, nullptr, 0, s), "reduce");
+  out.resize(Bt.ns);
+  hip_check(hipMemcpyAsync(out.data(), Bt.nrm2.p, Bt.ns * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+  hip_check(hipStreamSynchronize(s), "sync");
+}
+
+cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* uin, const cpm_solve_opts& o,
+                      cpm_solve_stats* stats, hipStream_t st) {
+  const int m = o.restart;
+  if (m < 1 || m > kMaxRestart) fail(CPM_ERR_ARG, "restart must be in 1..64");
+  if (!(o.rtol >= 0) || !(o.atol >= 0)) fail(CPM_ERR_ARG, "tolerances must be >= 0");
+  if (o.max_it < 1) fail(CPM_ERR_ARG, "max_it must be >= 1");
+  if (o.mode != CPM_MODE_FP64 && o.mode != CPM_MODE_MIXED_IR) fail(CPM_ERR_ARG, "bad mode");
+  if (o.mode == CPM_MODE_MIXED_IR && Bt.any_pc && !Bt.pc_fp32)
+    fail(CPM_ERR_ARG, "MIXED_IR needs FP32 preconditioners");
+  if (o.mode == CPM_MODE_MIXED_IR && !(o.inner_rtol > 0 && o.inner_rtol < 1)) fail(CPM_ERR_ARG, "inner_rtol in (0,1)");
+  if (Bt.any_pc && (Bt.pc_transpose != 0) != (o.transpose != 0))
+    fail(CPM_ERR_ARG, "preconditioner transpose flag does not match the solve");
+  for (int i = 0; i < Bt.ni; ++i)
+    if (!fin[i] || !uin[i]) fail(CPM_ERR_ARG, "null vector");
+  ensure_workspace(Bt, m);
+  const int R = Bt.R, ns = Bt.ns;
+  const size_t Ns = (size_t)Bt.Ntot * R;
+  const bool tr = o.transpose != 0;
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  hip_check(hipEventRecord(e0, st), "event");
+  for (int i = 0; i < Bt.ni; ++i) {
+    const size_t bytes = (size_t)(Bt.off[i + 1] - Bt.off[i]) * R * sizeof(double);
+    hip_check(hipMemcpyAsync(Bt.f.p + Bt.off[i] * R, fin[i], bytes, hipMemcpyDeviceToDevice, st), "copy f");
+    hip_check(hipMemcpyAsync(Bt.x.p + Bt.off[i] * R, uin[i], bytes, hipMemcpyDeviceToDevice, st), "copy u");
+  }
+  std::vector<double> fn2, b2;
+  norms2(Bt, Bt.f.p, nullptr, nullptr, fn2, st);
+  batch_apply(Bt, Bt.x.p, Bt.t.p, tr, st);
+  norms2(Bt, Bt.f.p, Bt.t.p, Bt.r.p, b2, st);
+  std::vector<double> fn(ns), beta(ns), tol(ns), best(ns);
+  std::vector<int> done(ns, 0), its(ns, 0), cycles(ns, 0), stall(ns, 0), stat(ns, CPM_OK);
+  std::vector<int32_t> zero_sys(ns, 0);
+  bool any_zero = false;
+  for (int s = 0; s < ns; ++s) {
+    fn[s] = std::sqrt(fn2[s]);
+    beta[s] = std::sqrt(b2[s]);
+    tol[s] = std::max(o.rtol * fn[s], o.atol);
+    best[s] = beta[s];
+    if (!std::isfinite(beta[s]) || !std::isfinite(fn[s])) { done[s] = 1; stat[s] = CPM_NOT_CONVERGED; }
+    else if (fn[s] == 0.0) { done[s] = 1; zero_sys[s] = 1; any_zero = true; beta[s] = 0; }
+    else if (beta[s] <= tol[s]) done[s] = 1;
+  }
+  if (any_zero) {  // f = 0: the solution is 0
+    std::vector<double> zs(ns, 0.0);
+    hip_check(hipMemcpy(Bt.scale.p, zs.data(), ns * sizeof(double), hipMemcpyHostToDevice), "upload");
+    hip_check(hipMemcpy(Bt.act.p, zero_sys.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice), "upload");
+    hip_check(vec_scale(R, Bt.x.p, Bt.x.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.scale.p, st), "zero");
+  }
+  GmresState S = state_of(Bt, m);
+  const double* Zb = Bt.any_pc ? Bt.Z.p : Bt.V.p;
+  double ms_pc = 0, ms_ap = 0;
+  int n_pc = 0, n_ap = 2;
+  std::vector<hipEvent_t> pev, aev;
+  if (o.profile) {
+    pev.resize(2 * m);
+    aev.resize(2 * m);
+    for (auto& e : pev) hip_check(hipEventCreate(&e), "event");
+    for (auto& e : aev) hip_check(hipEventCreate(&e), "event");
+  }
+  std::vector<int32_t> act(ns), steps(ns), bad(ns);
+  std::vector<double> tin(ns);
+  for (;;) {
+    int nact = 0;
+    for (int s = 0; s < ns; ++s) {
+      act[s] = (!done[s] && its[s] < o.max_it) ? 1 : 0;
+      nact += act[s];
+      double t = tol[s];
+      if (o.mode == CPM_MODE_MIXED_IR) t = std::max(tol[s], o.inner_rtol * beta[s]);
+      tin[s] = t;
+    }
+    if (nact == 0) break;
+    hip_check(hipMemcpyAsync(Bt.act.p, act.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, st), "upload");
+    hip_check(hipMemcpyAsync(Bt.tol_in.p, tin.data(), ns * sizeof(double), hipMemcpyHostToDevice, st), "upload");
+    hip_check(hipMemcpyAsync(Bt.beta.p, beta.data(), ns * sizeof(double), hipMemcpyHostToDevice, st), "upload");
+    hip_check(hipMemsetAsync(Bt.bad.p, 0, ns * sizeof(int32_t), st), "memset");
+    hip_check(gmres_cycle_init(S, ns, st), "cycle init");
+    hip_check(vec_scale(R, Bt.r.p, Bt.V.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.scale.p, st), "v0");
+    int jdone = 0;
+    for (int j = 0; j < m; ++j) {
+      double* Vj = Bt.V.p + (size_t)j * Ns;
+      double* Zj = Bt.any_pc ? Bt.Z.p + (size_t)j * Ns : Vj;
+      if (o.profile) hip_check(hipEventRecord(pev[2 * j], st), "event");
+      if (Bt.any_pc) batch_precond(Bt, Vj, Zj, st);
+      if (o.profile) hip_check(hipEventRecord(pev[2 * j + 1], st), "event");
+      if (Bt.any_pc) ++n_pc;
+      if (o.profile) hip_check(hipEventRecord(aev[2 * j], st), "event");
+      batch_apply(Bt, Zj, Bt.w.p, tr, st);
+      if (o.profile) hip_check(hipEventRecord(aev[2 * j + 1], st), "event");
+      ++n_ap;
+      hip_check(gmres_zero_col(S, ns, st), "zero col");
+      for (int pass = 0; pass < 2; ++pass) {
+        hip_check(vec_dots(R, Bt.V.p, Ns, j + 1, Bt.w.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.part.p, st), "dots");
+        hip_check(vec_reduce(R, Bt.part.p, j + 1, Bt.nchunks, Bt.d_cbeg.p, ns, Bt.hv.p, m + 1, Bt.hcol.p, m + 1, st),
+                  "reduce");
+        hip_check(vec_update(R, Bt.V.p, Ns, j + 1, Bt.w.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.hv.p, m + 1,
+                             pass == 1 ? Bt.partn.p : nullptr, st),
+                  "update");
+      }
+      hip_check(vec_reduce(R, Bt.partn.p, 1, Bt.nchunks, Bt.d_cbeg.p, ns, Bt.nrm2.p, 1, nullptr, 0, st), "reduce");
+      hip_check(gmres_givens(S, j, ns, st), "givens");
+      hip_check(vec_scale(R, Bt.w.p, Bt.V.p + (size_t)(j + 1) * Ns, Bt.d_chunks.p, Bt.nchunks, Bt.act.p,
+                          Bt.scale.p, st),
+                "scale");
+      hip_check(hipMemcpyAsync(&Bt.h_nact[j & 1], Bt.n_active.p, sizeof(int32_t), hipMemcpyDeviceToHost, st), "poll");
+      hip_check(hipEventRecord(Bt.ev[j & 1], st), "event");
+      jdone = j + 1;
+      if (j >= 1) {
+        hip_check(hipEventSynchronize(Bt.ev[(j - 1) & 1]), "poll");
+        if (Bt.h_nact[(j - 1) & 1] == 0) break;
+      }
+    }
+    (void)jdone;
+    hip_check(gmres_hsolve(S, ns, st), "hsolve");
+    hip_check(vec_xupdate(R, Bt.x.p, Zb, Ns, Bt.d_chunks.p, Bt.nchunks, Bt.steps.p, Bt.y.p, m, st), "xupdate");
+    batch_apply(Bt, Bt.x.p, Bt.t.p, tr, st);
+    ++n_ap;
+    norms2(Bt, Bt.f.p, Bt.t.p, Bt.r.p, b2, st);  // synchronises
+    hip_check(hipMemcpy(steps.data(), Bt.steps.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost), "steps");
+    hip_check(hipMemcpy(bad.data(), Bt.bad.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost), "bad");
+    if (o.profile) {
+      for (int j = 0; j < jdone; ++j) {
+        float a = 0, b = 0;
+        if (Bt.any_pc && hipEventElapsedTime(&a, pev[2 * j], pev[2 * j + 1]) == hipSuccess) ms_pc += a;
+        if (hipEventElapsedTime(&b, aev[2 * j], aev[2 * j + 1]) == hipSuccess) ms_ap += b;
+      }
+    }
+    for (int s = 0; s < ns; ++s) {
+      if (!act[s]) continue;
+      its[s] += steps[s];
+      cycles[s]++;
+      beta[s] = std::sqrt(b2[s]);
+      if (bad[s] || !std::isfinite(beta[s])) { done[s] = 1; stat[s] = CPM_NOT_CONVERGED; continue; }
+      if (beta[s] <= tol[s]) { done[s] = 1; continue; }
+      if (beta[s] < 0.99 * best[s]) { best[s] = beta[s]; stall[s] = 0; }
+      else if (++stall[s] >= std::max(1, o.stagnation_cycles)) { done[s] = 1; stat[s] = CPM_NOT_CONVERGED; }
+      if (!done[s] && its[s] >= o.max_it) { done[s] = 1; stat[s] = CPM_NOT_CONVERGED; }
+    }
+  }
+  for (int i = 0; i < Bt.ni; ++i) {
+    const size_t bytes = (size_t)(Bt.off[i + 1] - Bt.off[i]) * R * sizeof(double);
+    hip_check(hipMemcpyAsync(uin[i], Bt.x.p + Bt.off[i] * R, bytes, hipMemcpyDeviceToDevice, st), "copy u");
+  }
+  hip_check(hipEventRecord(e1, st), "event");
+  hip_check(hipEventSynchronize(e1), "sync");
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (auto& e : pev) (void)hipEventDestroy(e);
+  for (auto& e : aev) (void)hipEventDestroy(e);
+  bool pc_err = false;
+  for (auto* pc : Bt.pcs)
+    if (pc && precond_take_error(pc)) pc_err = true;
+  if (pc_err) fail(CPM_ERR_DEVICE, "preconditioner wait limit expired (dependency schedule broken)");
+  cpm_status ret = CPM_OK;
+  for (int s = 0; s < ns; ++s) {
+    if (!done[s] || stat[s] != CPM_OK) { stat[s] = CPM_NOT_CONVERGED; ret = CPM_NOT_CONVERGED; }
+    if (stats) {
+      cpm_solve_stats& q = stats[s];
+      std::memset(&q, 0, sizeof(q));
+      q.iterations = its[s];
+      q.restarts = cycles[s];
+      q.converged = stat[s] == CPM_OK ? 1 : 0;
+      q.status = stat[s];
+      q.relres = fn[s] > 0 ? beta[s] / fn[s] : 0.0;
+      q.ms_total = ms;
+      q.ms_precond = ms_pc;
+      q.ms_apply = ms_ap;
+      q.n_precond = n_pc;
+      q.n_apply = n_ap;
+    }
+  }
+  if (ret != CPM_OK) set_error("solver stopped before reaching the tolerance");
+  return ret;
+}
+
+std::atomic<int64_t> g_serial{1};
+
+}  // namespace
+
+namespace cpm {
+int64_t next_serial() { return g_serial.fetch_add(1); }
+}  // namespace cpm
+
+cpm_status cpm_solve_opts_default(cpm_solve_opts* o) {
+  if (!o) { set_error("null argument"); return CPM_ERR_ARG; }
+  std::memset(o, 0, sizeof(*o));
+  o->restart = 30;
+  o->rtol = 1e-10;
+  o->atol = 0.0;
+  o->max_it = 10000;
+  o->mode = CPM_MODE_FP64;
+  o->inner_rtol = 1e-4;
+  o->stagnation_cycles = 50;
+  return CPM_OK;
+}
+
+cpm_status cpm_solve(const cpm_operator* op, const cpm_precond* pc, const double* f, double* u, int32_t nrhs,
+                     const cpm_solve_opts* opts, cpm_solve_stats* stats, void* stream) {
+  try {
+    if (!op || !f || !u || !opts) fail(CPM_ERR_ARG, "null argument");
+    if (f == u) fail(CPM_ERR_ARG, "f and u must not alias");
+    if (opts->use_graph) fail(CPM_ERR_ARG, "use_graph is not available for single solves");
+    auto& cache = op->solve_cache;
+    const int64_t key = pc ? pc->serial : 0;
+    if (!cache || cache->R != nrhs || op->solve_cache_key != key) {
+      cache.reset();
+      auto Bt = std::make_shared<cpm_batch_s>();
+      const cpm_operator_s* o1 = op;
+      const cpm_precond_s* p1 = pc;
+      build_batch(*Bt, 1, &o1, &p1, nrhs);
+      cache = Bt;
+      op->solve_cache_key = key;
+    }
+    const double* fa[1] = {f};
+    double* ua[1] = {u};
+    std::vector<cpm_solve_stats> st(nrhs);
+    cpm_status r = solve_impl(*cache, fa, ua, *opts, st.data(), (hipStream_t)stream);
+    if (stats) {
+      // one stats record per call: the worst right-hand side
+      int w = 0;
+      for (int q = 1; q < nrhs; ++q)
+        if (st[q].relres > st[w].relres || !st[q].converged) w = q;
+      *stats = st[w];
+      for (int q = 0; q < nrhs; ++q) stats->iterations = std::max(stats->iterations, st[q].iterations);
+    }
+    return r;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed in cpm_solve");
+    return CPM_ERR_OOM;
+  }
+}
+
+cpm_status cpm_batch_create(int32_t n, const cpm_operator* const* ops, const cpm_precond* const* pcs,
+                            const int32_t* nrhs, cpm_batch** out) {
+  try {
+    if (!ops || !out || n < 1) fail(CPM_ERR_ARG, "bad argument");
+    *out = nullptr;
+    int R = nrhs ? nrhs[0] : 1;
+    for (int i = 0; i < n; ++i)
+      if (nrhs && nrhs[i] != R) fail(CPM_ERR_ARG, "all instances of a batch need the same nrhs");
+    auto Bt = std::make_unique<cpm_batch_s>();
+    build_batch(*Bt, n, ops, pcs, R);
+    *out = Bt.release();
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed in cpm_batch_create");
+    return CPM_ERR_OOM;
+  }
+}
+
+cpm_status cpm_batch_solve(cpm_batch* b, const double* const* f, double* const* u, const cpm_solve_opts* opts,
+                           cpm_solve_stats* stats, void* stream) {
+  try {
+    if (!b || !f || !u || !opts) fail(CPM_ERR_ARG, "null argument");
+    if (opts->use_graph) fail(CPM_ERR_ARG, "use_graph is not available yet");
+    return solve_impl(*b, f, u, *opts, stats, (hipStream_t)stream);
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed in cpm_batch_solve");
+    return CPM_ERR_OOM;
+  }
+}
+
+cpm_status cpm_batch_apply(cpm_batch* b, const double* const* x, double* const* y, void* stream) {
+  try {
+    if (!b || !x || !y) fail(CPM_ERR_ARG, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    ensure_workspace(*b, 1);
+    for (int i = 0; i < b->ni; ++i) {
+      if (!x[i] || !y[i]) fail(CPM_ERR_ARG, "null vector");
+      const size_t bytes = (size_t)(b->off[i + 1] - b->off[i]) * b->R * sizeof(double);
+      hip_check(hipMemcpyAsync(b->x.p + b->off[i] * b->R, x[i], bytes, hipMemcpyDeviceToDevice, st), "copy");
+    }
+    batch_apply(*b, b->x.p, b->t.p, false, st);
+    for (int i = 0; i < b->ni; ++i) {
+      const size_t bytes = (size_t)(b->off[i + 1] - b->off[i]) * b->R * sizeof(double);
+      hip_check(hipMemcpyAsync(y[i], b->t.p + b->off[i] * b->R, bytes, hipMemcpyDeviceToDevice, st), "copy");
+    }
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
+void cpm_batch_destroy(cpm_batch* b) { delete b; }

@@ -1,0 +1,155 @@
+"""GPU FGMRES parity: solutions against the oracle (paper Sec. 4.1.1, GMRES).
+
+Bars: FP64 path, solution within 1e-10 relative of the oracle's direct solve
+(solved to rtol 1e-12 so that the GMRES stopping error stays below it); the
+true residual of the GPU iterate, recomputed with the oracle's assembled A,
+meets the requested tolerance; mixed path (FP32 preconditioner + FP64 outer
+refinement) reaches 1e-8 by the same oracle residual.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+from oracle import krylov
+from paper_2110_06322_amd import _capi, cpm, inputs
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def test_config1_unpreconditioned_gmres():
+    """2-D unit circle, h = 0.05, p = 2, c = 1, f = 2 sin(theta(cp)), GMRES(30) to 1e-10."""
+    lb = G.lib_band("circle", (1.0,), 2, 0.05, 2)
+    ob, E, O, A, P = G.oracle("circle", (1.0,), 2, 0.05, 2, 1.0)
+    keys, pos = G.mapping(lb, ob)
+    op = cpm.Operator(lb, 1.0)
+    _, cp, _ = lb.export()
+    f = 2.0 * inputs.circle_sin(cp[:lb.n_active])
+    u, st = cpm.solve(op, _t(f), rtol=1e-10, restart=30)
+    assert st["converged"] and st["relres"] <= 1e-10
+    fo = 2.0 * inputs.circle_sin(ob.cp_active)
+    res = np.linalg.norm(fo - A @ u.cpu().numpy()[np.argsort(pos)]) / np.linalg.norm(fo)
+    assert res <= 1e-10 * 1.01
+    xo, info = krylov.fgmres(A, fo, restart=30, rtol=1e-10)
+    assert abs(st["iterations"] - info["iters"]) <= max(3, 0.05 * info["iters"])
+    ud, _ = cpm.solve(op, _t(f), rtol=1e-12, restart=30)
+    ue = np.linalg.solve(A.toarray(), fo)[pos]
+    assert np.abs(ud.cpu().numpy() - ue).max() <= 1e-10 * np.abs(ue).max()
+    # manufactured solution sin(theta): O(h) accuracy for p = 2 (reported)
+    err = np.abs(u.cpu().numpy() - inputs.circle_sin(cp[:lb.n_active])).max()
+    assert err < 0.01
+
+
+@pytest.mark.parametrize("pc_kind", ["ras", "oras"])
+def test_preconditioned_solve_small_sphere(pc_kind):
+    lb = G.lib_band("sphere", (1.0,), 3, 0.1, 3)
+    ob, E, O, A, P = G.oracle("sphere", (1.0,), 3, 0.1, 3, 1.0)
+    keys, pos = G.mapping(lb, ob)
+    op = cpm.Operator(lb, 1.0)
+    pc = cpm.Precond(op, kind=pc_kind, n_parts=8)
+    _, cp, _ = lb.export()
+    f = 21.0 * inputs.sphere_y4(cp[:lb.n_active], 2)
+    u, st = cpm.solve(op, _t(f), pc=pc, rtol=1e-12)
+    assert st["converged"], st
+    fo = 21.0 * inputs.sphere_y4(ob.cp_active, 2)
+    ue = spla.spsolve(A.tocsc(), fo)[pos]
+    assert np.abs(u.cpu().numpy() - ue).max() <= 1e-10 * np.abs(ue).max()
+    # preconditioning helps relative to plain GMRES
+    _, st0 = cpm.solve(op, _t(f), rtol=1e-12)
+    if pc_kind == "ras":
+        assert st["iterations"] < st0["iterations"]
+
+
+def test_mixed_precision_refinement_reaches_1e8():
+    lb = G.lib_band("torus", (1.0, 0.4), 3, 0.05, 3)
+    ob, E, O, A, P = G.oracle("torus", (1.0, 0.4), 3, 0.05, 3, 2.0)
+    keys, pos = G.mapping(lb, ob)
+    op = cpm.Operator(lb, 2.0)
+    pc32 = cpm.Precond(op, kind="ras", n_parts=16, precision="fp32")
+    pc64 = cpm.Precond(op, kind="ras", n_parts=16, precision="fp64")
+    f = G.field(keys, 17)
+    um, sm = cpm.solve(op, _t(f), pc=pc32, rtol=1e-8, mode="mixed", inner_rtol=1e-4)
+    ud, sd = cpm.solve(op, _t(f), pc=pc64, rtol=1e-8)
+    assert sm["converged"] and sd["converged"]
+    fo = G.field(ob.active_keys, 17)
+    inv = np.argsort(pos)
+    for u in (um, ud):
+        res = np.linalg.norm(fo - A @ u.cpu().numpy()[inv]) / np.linalg.norm(fo)
+        assert res <= 1e-8 * 1.01
+    ue = spla.spsolve(A.tocsc(), fo)[pos]
+    err_m = np.abs(um.cpu().numpy() - ue).max() / np.abs(ue).max()
+    print(f"mixed vs oracle {err_m:.2e}, iterations mixed {sm['iterations']} fp64 {sd['iterations']}")
+    assert err_m <= 1e-6
+
+
+def test_multi_rhs_solve_matches_single_and_is_deterministic():
+    lb = G.lib_band("torus", (1.0, 0.4), 3, 0.05, 3)
+    op = cpm.Operator(lb, 3.0)
+    pc = cpm.Precond(op, kind="ras", n_parts=16, precision="fp32")
+    keys = lb.active_keys
+    F = np.stack([G.field(keys, 40 + r) for r in range(4)], axis=1)
+    U, st = cpm.solve(op, _t(F).reshape(-1), pc=pc, nrhs=4, rtol=1e-9, mode="mixed")
+    U = U.cpu().numpy().reshape(-1, 4)
+    U2, _ = cpm.solve(op, _t(F).reshape(-1), pc=pc, nrhs=4, rtol=1e-9, mode="mixed")
+    assert np.array_equal(U, U2.cpu().numpy().reshape(-1, 4))
+    for r in range(4):
+        u1, s1 = cpm.solve(op, _t(F[:, r]), pc=pc, rtol=1e-9, mode="mixed")
+        assert np.abs(u1.cpu().numpy() - U[:, r]).max() <= 1e-14 * np.abs(U[:, r]).max() + 1e-300
+
+
+def test_failure_modes():
+    lb = G.lib_band("sphere", (1.0,), 3, 0.1, 3)
+    op = cpm.Operator(lb, 1.0)
+    keys = lb.active_keys
+    f = G.field(keys, 1)
+    bad = f.copy()
+    bad[3] = math.nan
+    _, st = cpm.solve(op, _t(bad), rtol=1e-8)
+    assert not st["converged"] and st["status"] == 6
+    _, st = cpm.solve(op, _t(f), rtol=1e-12, max_it=1)
+    assert not st["converged"] and st["iterations"] == 1
+    _, st = cpm.solve(op, _t(f), rtol=0.0, max_it=200, stagnation_cycles=3)
+    assert not st["converged"]
+    z, st = cpm.solve(op, _t(np.zeros_like(f)), u=_t(f.copy()), rtol=1e-8)
+    assert st["converged"] and float(z.abs().max()) == 0.0
+    with pytest.raises(_capi.CpmError) as e:
+        cpm.solve(op, _t(f), restart=0)
+    assert e.value.status == "CPM_ERR_ARG"
+    pc64 = cpm.Precond(op, kind="ras", n_parts=4)
+    with pytest.raises(_capi.CpmError) as e:
+        cpm.solve(op, _t(f), pc=pc64, mode="mixed")
+    assert e.value.status == "CPM_ERR_ARG"
+
+
+def test_config2_oras_fp64_and_mixed():
+    """Unit sphere, h = 0.02, p = 3, c = 1, f = 21 Y_4 (seed 2), 64 ORAS boxes, overlap 2h."""
+    lb = G.lib_band("sphere", (1.0,), 3, 0.02, 3)
+    ob, E, O, A, P = G.oracle("sphere", (1.0,), 3, 0.02, 3, 1.0)
+    keys, pos = G.mapping(lb, ob)
+    inv = np.argsort(pos)
+    op = cpm.Operator(lb, 1.0)
+    _, cp, _ = lb.export()
+    Y = inputs.sphere_y4(cp[:lb.n_active], 2)
+    f = 21.0 * Y
+    fo = 21.0 * inputs.sphere_y4(ob.cp_active, 2)
+    out = {}
+    for name, prec, mode in [("fp64", "fp64", "fp64"), ("mixed", "fp32", "mixed")]:
+        pc = cpm.Precond(op, kind="oras", n_parts=64, precision=prec)
+        u, st = cpm.solve(op, _t(f), pc=pc, rtol=1e-8, mode=mode, max_it=20000)
+        print(name, st, flush=True)
+        assert st["converged"], st
+        res = np.linalg.norm(fo - A @ u.cpu().numpy()[inv]) / np.linalg.norm(fo)
+        assert res <= 1e-8 * 1.01
+        out[name] = u.cpu().numpy()
+        # the discrete solution approximates the surface harmonic
+        assert np.abs(out[name] - Y).max() < 0.05 * np.abs(Y).max()
+    d = np.abs(out["fp64"] - out["mixed"]).max() / np.abs(out["fp64"]).max()
+    print(f"mixed vs fp64 difference {d:.2e}")
