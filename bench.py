@@ -1,0 +1,193 @@
+"""Benchmark of the CPM hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): unit sphere,
+grid h = 0.02 on [-2,2]^3, p = 3 (64-point extension stencil), c = 1,
+f = 21 Y with Y a seeded combination of degree-4 spherical harmonics, (O)RAS
+with 64 box subdomains and overlap 2h. One step = one pass of the whole hot
+path over that input: a mixed-precision solve to 1e-8 (FP32 subdomain
+solves inside FP64 FGMRES with iterative refinement), which runs the
+extension + stabilized operator apply, the Schwarz apply and the Krylov core.
+The FP64 solve of the same system is timed beside it.
+
+Reported: metric value = operator-apply throughput (active nodes per second)
+of the fused apply kernel, timed with HIP events on the stream the kernel runs
+on inside the timed region; `roofline` for that kernel (algorithmic bytes
+per active node = 8 (x) + 8 (y) + 8 d (1 + N_G/N_A) (closest points));
+`solve` = time to 1e-8, mixed vs FP64; `cpu_baseline` = the CPU oracle on a
+bounded sample (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--apply-reps", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--subsolver", default=os.environ.get("CPM_BENCH_SUBSOLVER", "ilu0"))
+    ap.add_argument("--pc", default=os.environ.get("CPM_BENCH_PC", "oras"))
+    return ap.parse_args()
+
+
+def cpu_baseline(seconds_budget=20.0):
+    """The CPU oracle's assembled operator applied to a vector, on the same workload, FP64.
+
+    Sample: the oracle assembles A for the full config-2 band (not timed) and
+    times repeated SciPy CSR matvecs for about the budget; reported as active
+    nodes per second. SciPy's sparse matvec runs on one core.
+    """
+    import numpy as np
+
+    from oracle import band as OB, operator as OO, surfaces as OS
+    from paper_2110_06322_amd import inputs
+    h, p, d = 0.02, 3, 3
+    bd = OB.build_band(OS.make_cp("sphere", (1.0,)), d, h, p, [-2.0] * 3, [2.0] * 3,
+                       inputs.ruuth_merriman_gamma(d, p, h))
+    A = OO.assemble_A(bd, 1.0)
+    x = inputs.normal(1, 0, bd.active_keys)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        A @ x
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > seconds_budget:
+            break
+    return {"value": round(bd.n_active * reps / el / 1e9, 5), "unit": "Gnodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} SciPy CSR matvecs of the assembled FP64 operator (sphere h=0.02, p=3, "
+                      f"N_A={bd.n_active}) in {el:.1f} s"}
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2110_06322_amd import _capi, cpm, inputs
+    if not os.path.exists(_capi.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    h, p, d, c = 0.02, 3, 3, 1.0
+    t0 = time.perf_counter()
+    band = cpm.Band("sphere", (1.0,), d, h, p)
+    op = cpm.Operator(band, c)
+    t_band = time.perf_counter() - t0
+    _, cp, _ = band.export()
+    nA, nG = band.n_active, band.n_ghost
+    f = torch.tensor(21.0 * inputs.sphere_y4(cp[:nA], 2), dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    pc32 = cpm.Precond(op, kind=a.pc, n_parts=64, overlap=2.0, precision="fp32", subsolver=a.subsolver)
+    t_pc32 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pc64 = cpm.Precond(op, kind=a.pc, n_parts=64, overlap=2.0, precision="fp64", subsolver=a.subsolver)
+    t_pc64 = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    u = torch.zeros_like(f)
+    x = torch.tensor(inputs.normal(1, 0, band.active_keys), dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+
+    def step(mode, pc, profile=False):
+        u.zero_()
+        _, st = cpm.solve(op, f, pc=pc, u=u, rtol=1e-8, mode=mode, max_it=20000, profile=profile)
+        return st
+
+    for _ in range(a.warmup):
+        step("mixed", pc32, True)
+    torch.cuda.synchronize()
+    # ---- timed region: K steps; the apply and Schwarz kernels are timed with HIP
+    # events on the solver's stream inside each step
+    t_start = time.perf_counter()
+    stats = [step("mixed", pc32, True) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_step = t_total * 1e3 / a.steps
+    solve_ms = float(np.mean([s["ms_total"] for s in stats]))
+    ms_apply = float(sum(s["ms_apply"] for s in stats) / max(1, sum(s["n_apply"] for s in stats)))
+    ms_pc = float(sum(s["ms_precond"] for s in stats) / max(1, sum(s["n_precond"] for s in stats)))
+    # FP64 solve of the same system (comparison leg, after the timed steps)
+    st64 = [step("fp64", pc64) for _ in range(max(1, min(3, a.steps)))]
+    solve64_ms = float(np.mean([s["ms_total"] for s in st64]))
+    # standalone apply (outside the timed steps): many back-to-back launches
+    for _ in range(10):
+        op.apply(x, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(a.apply_reps):
+        op.apply(x, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_apply_alone = e0.elapsed_time(e1) / a.apply_reps
+    gnodes = nA / (ms_apply * 1e-3) / 1e9
+    b_alg = 16.0 + 8.0 * d * (1.0 + nG / nA)
+    achieved = b_alg * nA / (ms_apply * 1e-3) / 1e9
+    pci = pc32.info
+    # Schwarz apply algorithmic bytes: FP32 values + 16-bit columns per stored entry,
+    # row pointers (2 x 8 B), input index, output index and FP64 r/z per local row
+    b_pc = pci.total_nnz * (4 + 2) + pci.total_rows * (8 + 8 + 4 + 4 + 8 + 8) + 4 * pci.total_rows
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "apply_traffic_sphere_h0.02.json")
+    if os.path.exists(tfile):
+        try:
+            traffic = json.load(open(tfile)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": "CPM apply Gnodes/s (%HBM peak); ORAS-GMRES time to 1e-8, mixed vs FP64",
+        "value": round(gnodes, 3),
+        "unit": "Gnodes/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "unit sphere h=0.02 on [-2,2]^3, p=3, c=1, f=21*Y4 (seed 2), "
+                               f"{a.pc.upper()} 64 boxes overlap 2h, local {a.subsolver}",
+                   "n_active": nA, "n_ghost": nG, "n_band": band.n_band},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_apply_tile<3,3,1>", "bytes_per_node": round(b_alg, 2)},
+        "solve": {"mixed_ms": round(solve_ms, 3), "fp64_ms": round(solve64_ms, 3),
+                  "speedup_mixed": round(solve64_ms / solve_ms, 3) if solve_ms > 0 else None,
+                  "iters_mixed": int(stats[-1]["iterations"]), "iters_fp64": int(st64[-1]["iterations"]),
+                  "relres_mixed": stats[-1]["relres"], "relres_fp64": st64[-1]["relres"],
+                  "converged": bool(stats[-1]["converged"] and st64[-1]["converged"])},
+        "setup_s": {"band_and_operator": round(t_band, 3), "precond_fp32": round(t_pc32, 3),
+                    "precond_fp64": round(t_pc64, 3)},
+        "apply_ms": round(ms_apply, 5),
+        "apply_standalone": {"ms": round(ms_apply_alone, 5),
+                             "gnodes_per_s": round(nA / (ms_apply_alone * 1e-3) / 1e9, 3),
+                             "frac": round(b_alg * nA / (ms_apply_alone * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline_precond": {"bound": "hbm", "kernel": "k_schwarz<float,1>", "ms": round(ms_pc, 5),
+                             "achieved": round(b_pc / (ms_pc * 1e-3) / 1e9, 1) if ms_pc > 0 else None,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(b_pc / (ms_pc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms_pc > 0 else None,
+                             "bytes_per_launch": int(b_pc), "max_levels": int(pci.max_levels)},
+    }
+    if not a.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

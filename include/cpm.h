@@ -225,10 +225,10 @@ typedef struct {
   int32_t status;         /* cpm_status of this system */
   double relres;          /* true |f - A u| / |f| at exit */
   double ms_total;        /* wall time of the solve (hipEvent) */
-  double ms_precond;      /* time in the preconditioner kernels (0 unless profiled) */
-  double ms_apply;        /* time in the operator kernels (0 unless profiled) */
-  int32_t n_precond;      /* preconditioner applications */
-  int32_t n_apply;        /* operator applications */
+  double ms_precond;      /* profiled: total time of the timed preconditioner launches, else 0 */
+  double ms_apply;        /* profiled: total time of the timed operator launches, else 0 */
+  int32_t n_precond;      /* preconditioner applications (profiled: the timed ones) */
+  int32_t n_apply;        /* operator applications (profiled: the timed ones, one per Arnoldi step) */
 } cpm_solve_stats;
 
 cpm_status cpm_solve_opts_default(cpm_solve_opts* opts);

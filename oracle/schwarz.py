@@ -15,8 +15,14 @@ Readings (the paper fixes none of these discretely):
     coordinate; cp < s goes to the first child, cp >= s to the second;
   * overlap: Omega_j = active nodes whose cp lies in box_j grown by N_O h in
     every axis (closed);
-  * local order: ascending linear grid key; local matrix = rows and columns
-    of A in Omega_j on A's structural pattern (zero weights kept);
+  * local matrix: rows and columns of A in Omega_j (gathered in ascending
+    grid key) on A's structural pattern (zero weights kept), then permuted to
+    reverse Cuthill-McKee order (George & Liu, "Computer Solution of Large
+    Sparse Positive Definite Systems", 1981) of its symmetrized graph: start
+    at the unvisited node of least degree, visit each node's unvisited
+    neighbours by (degree, key position), reverse the whole sequence. The
+    ordering decides whether ILU(0) is usable on these non-diagonally
+    dominant matrices (lexicographic order stagnates; RCM does not);
   * Robin (ORAS): on row i of Omega_j with dropped couplings
     s_i = sum_{k not in Omega_j} a_ik, the diagonal becomes a_ii + s_i/(1 + alpha_i h),
     alpha_i = alpha_cross if the dropped k are owned by >= 2 other
@@ -78,6 +84,42 @@ def overlap_sets(cp, boxes_lo, boxes_hi, delta, keys):
     return out
 
 
+def rcm_order(Aloc: sp.csr_matrix) -> np.ndarray:
+    """Reverse Cuthill-McKee permutation of the symmetrized pattern of Aloc.
+
+    perm[q] = row of Aloc placed at position q. Ties: least degree, then
+    smallest index; each connected component starts at its least-degree node.
+    """
+    S = sp.csr_matrix((np.ones(Aloc.nnz), Aloc.indices, Aloc.indptr), shape=Aloc.shape)
+    G = sp.csr_matrix(S + S.T)
+    G.setdiag(0)
+    G.eliminate_zeros()
+    n = G.shape[0]
+    deg = np.diff(G.indptr)
+    key = deg.astype(np.int64) * (n + 1) + np.arange(n)     # (degree, index)
+    visited = np.zeros(n, dtype=bool)
+    order = []
+    by_key = np.argsort(key, kind="stable")
+    nxt = 0
+    while len(order) < n:
+        while visited[by_key[nxt]]:
+            nxt += 1
+        s0 = int(by_key[nxt])
+        visited[s0] = True
+        queue = [s0]
+        head = 0
+        while head < len(queue):
+            v = queue[head]
+            head += 1
+            nb = G.indices[G.indptr[v]:G.indptr[v + 1]]
+            nb = nb[~visited[nb]]
+            nb = nb[np.argsort(key[nb], kind="stable")]
+            visited[nb] = True
+            queue.extend(int(u) for u in nb)
+        order.extend(queue)
+    return np.array(order[::-1], dtype=np.int64)
+
+
 def ilu0(Aloc: sp.csr_matrix):
     """ILU(0), IKJ form (Saad, Alg. 10.4) on the stored pattern of Aloc.
 
@@ -128,8 +170,9 @@ class Schwarz:
     boxes_lo: np.ndarray
     boxes_hi: np.ndarray
     omegas: list
-    local: list = field(default_factory=list)     # local matrices (after Robin change)
-    factors: list = field(default_factory=list)   # (L, U) or ('lu', splu)
+    local: list = field(default_factory=list)     # local matrices (after Robin change), key order
+    factors: list = field(default_factory=list)   # (L, U) of the RCM-permuted matrix, or splu
+    perms: list = field(default_factory=list)     # RCM permutation per subdomain (ILU(0))
     subsolver: str = "ilu0"
 
     def apply(self, r: np.ndarray) -> np.ndarray:
@@ -140,9 +183,11 @@ class Schwarz:
             rl = r[idx].astype(np.float64)
             if self.subsolver == "ilu0":
                 L, U = self.factors[j]
-                y = spla.spsolve_triangular(L + sp.identity(L.shape[0], format="csr"), rl,
+                perm = self.perms[j]
+                y = spla.spsolve_triangular(L + sp.identity(L.shape[0], format="csr"), rl[perm],
                                             lower=True, unit_diagonal=True)
-                zl = spla.spsolve_triangular(U, y, lower=False)
+                zl = np.empty_like(rl)
+                zl[perm] = spla.spsolve_triangular(U, y, lower=False)
             else:
                 zl = self.factors[j].solve(rl)
             own = self.owner[idx] == j
@@ -172,6 +217,7 @@ def build_schwarz(A: sp.csr_matrix, pattern: sp.csr_matrix, cp: np.ndarray, keys
         if only is not None and j not in only:
             S.local.append(None)
             S.factors.append(None)
+            S.perms.append(None)
             continue
         Aj = sp.csr_matrix(A[idx][:, idx])
         Aj.sort_indices()
@@ -194,7 +240,12 @@ def build_schwarz(A: sp.csr_matrix, pattern: sp.csr_matrix, cp: np.ndarray, keys
                 Aj.data[dpos] = Aj.data[dpos] + s_i / (1.0 + a * h)
         S.local.append(Aj)
         if subsolver == "ilu0":
-            S.factors.append(ilu0(Aj))
+            perm = rcm_order(Aj)
+            Ap = sp.csr_matrix(Aj[perm][:, perm])
+            Ap.sort_indices()
+            S.perms.append(perm)
+            S.factors.append(ilu0(Ap))
         else:
+            S.perms.append(None)
             S.factors.append(spla.splu(sp.csc_matrix(Aj)))
     return S

@@ -8,6 +8,7 @@ import ctypes as C
 from dataclasses import dataclass
 
 import numpy as np
+import torch
 
 from . import _capi
 from ._capi import check, lib
@@ -20,7 +21,6 @@ MODE = {"fp64": 0, "mixed": 1}
 
 
 def _torch():
-    import torch
     return torch
 
 
@@ -299,3 +299,40 @@ class Batch:
                 lib().cpm_batch_destroy(self._h)
         except Exception:
             pass
+
+
+class CPMSolve(torch.autograd.Function):
+    """u = A(c)^-1 f as a differentiable function of (f, c).
+
+    A(c) = c I + K with K independent of c, so for a loss L(u) with
+    g = dL/du: A^T lambda = g, dL/df = lambda, dL/dc = -lambda . u.
+    Forward and backward both run GPU FGMRES; the backward solve uses A^T and
+    a preconditioner built on A^T when one is given. Call as
+    CPMSolve.apply(f, c, op, pc, pc_T, opts) with c a 0-d tensor.
+    """
+
+    @staticmethod
+    def forward(ctx, f, c, op, pc=None, pc_T=None, opts=None):
+        opts = opts or SolveOptions(rtol=1e-12)
+        cval = float(c)
+        if op.c != cval:
+            op.set_shift(cval)
+        u, st = solve(op, f.detach().contiguous(), pc=pc, opts=opts)
+        if not st["converged"]:
+            raise RuntimeError(f"forward solve did not converge: {st}")
+        ctx.save_for_backward(u)
+        ctx.op, ctx.pc_T, ctx.opts = op, pc_T, opts
+        ctx.c_meta = (c.device, c.dtype) if torch.is_tensor(c) else (u.device, u.dtype)
+        return u
+
+    @staticmethod
+    def backward(ctx, g):
+        (u,) = ctx.saved_tensors
+        o = ctx.opts
+        ot = SolveOptions(restart=o.restart, rtol=o.rtol, atol=o.atol, max_it=o.max_it, mode="fp64",
+                          transpose=True, stagnation_cycles=o.stagnation_cycles)
+        lam, st = solve(ctx.op, g.contiguous(), pc=ctx.pc_T, opts=ot)
+        if not st["converged"]:
+            raise RuntimeError(f"adjoint solve did not converge: {st}")
+        gc = -torch.dot(lam, u)
+        return lam, gc.reshape(()).to(device=ctx.c_meta[0], dtype=ctx.c_meta[1]), None, None, None, None

@@ -248,26 +248,77 @@ bool dense_lu(int n, std::vector<double>& a, std::vector<int32_t>& perm) {
   return true;
 }
 
-// longest dependency chain of the lower (forward) or upper (backward) triangular solve
-int levels(int n, const std::vector<int64_t>& ptr, const std::vector<uint16_t>& col, bool lower) {
-  std::vector<int> lev(n, 0);
-  int mx = 0;
-  if (lower) {
-    for (int i = 0; i < n; ++i) {
-      int l = 0;
-      for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) l = std::max(l, lev[col[e]] + 1);
-      lev[i] = l;
-      mx = std::max(mx, l);
-    }
-  } else {
-    for (int i = n - 1; i >= 0; --i) {
-      int l = 0;
-      for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) l = std::max(l, lev[col[e]] + 1);
-      lev[i] = l;
-      mx = std::max(mx, l);
+// Reverse Cuthill-McKee order of the symmetrized pattern (George & Liu 1981):
+// each component starts at its unvisited node of least (degree, index);
+// unvisited neighbours are queued by (degree, index); the sequence is reversed.
+std::vector<int32_t> rcm_order(int n, const std::vector<int64_t>& ptr, const std::vector<int32_t>& col) {
+  std::vector<int64_t> cnt(n + 1, 0);
+  for (int i = 0; i < n; ++i)
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e)
+      if (col[e] != i) { cnt[i + 1]++; cnt[col[e] + 1]++; }
+  for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int32_t> adj(cnt[n]);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int i = 0; i < n; ++i)
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e)
+      if (col[e] != i) { adj[fill[i]++] = col[e]; adj[fill[col[e]]++] = i; }
+  std::vector<int64_t> aptr(n + 1, 0);
+  std::vector<int32_t> a2;
+  a2.reserve(adj.size());
+  for (int i = 0; i < n; ++i) {
+    std::sort(adj.begin() + cnt[i], adj.begin() + cnt[i + 1]);
+    auto last = std::unique(adj.begin() + cnt[i], adj.begin() + cnt[i + 1]);
+    a2.insert(a2.end(), adj.begin() + cnt[i], last);
+    aptr[i + 1] = (int64_t)a2.size();
+  }
+  std::vector<int64_t> deg(n);
+  for (int i = 0; i < n; ++i) deg[i] = aptr[i + 1] - aptr[i];
+  auto less = [&](int a, int b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; };
+  std::vector<int32_t> by(n);
+  std::iota(by.begin(), by.end(), 0);
+  std::sort(by.begin(), by.end(), less);
+  std::vector<char> vis(n, 0);
+  std::vector<int32_t> order;
+  order.reserve(n);
+  size_t nxt = 0;
+  std::vector<int32_t> nb;
+  while ((int)order.size() < n) {
+    while (vis[by[nxt]]) ++nxt;
+    size_t head = order.size();
+    order.push_back(by[nxt]);
+    vis[by[nxt]] = 1;
+    while (head < order.size()) {
+      int v = order[head++];
+      nb.clear();
+      for (int64_t e = aptr[v]; e < aptr[v + 1]; ++e)
+        if (!vis[a2[e]]) nb.push_back(a2[e]);
+      std::sort(nb.begin(), nb.end(), less);
+      for (int u : nb) { vis[u] = 1; order.push_back(u); }
     }
   }
-  return mx + 1;
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+// rows in increasing dependency level (a topological order of the sweep)
+std::vector<uint16_t> schedule(int n, const std::vector<int64_t>& ptr, const std::vector<uint16_t>& col, bool lower,
+                               int& nlev) {
+  std::vector<int> lev(n, 0);
+  nlev = 0;
+  for (int t = 0; t < n; ++t) {
+    int i = lower ? t : n - 1 - t;
+    int l = 0;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) l = std::max(l, lev[col[e]] + 1);
+    lev[i] = l;
+    nlev = std::max(nlev, l + 1);
+  }
+  std::vector<uint16_t> s(n);
+  std::iota(s.begin(), s.end(), 0);
+  std::stable_sort(s.begin(), s.end(), [&](uint16_t a, uint16_t b) {
+    if (lev[a] != lev[b]) return lev[a] < lev[b];
+    return lower ? a < b : a > b;
+  });
+  return s;
 }
 
 }  // namespace
@@ -404,21 +455,39 @@ void build_schwarz_host(const cpm_band_s& B, double c, const cpm_precond_opts& o
         }
         sub.nnz = (int64_t)col.size();
         if (o.subsolver == CPM_SUB_ILU0) {
+          // reverse Cuthill-McKee order, then ILU(0) of the permuted matrix
+          std::vector<int32_t> perm = rcm_order(n, ptr, col);
+          std::vector<int32_t> inv(n);
+          for (int q = 0; q < n; ++q) inv[perm[q]] = q;
+          std::vector<int64_t> pptr(n + 1, 0);
+          std::vector<int32_t> pcol;
+          std::vector<double> pval;
+          pcol.reserve(col.size());
+          pval.reserve(val.size());
+          std::vector<std::pair<int32_t, double>> row;
+          for (int q = 0; q < n; ++q) {
+            const int src = perm[q];
+            row.clear();
+            for (int64_t e = ptr[src]; e < ptr[src + 1]; ++e) row.push_back({inv[col[e]], val[e]});
+            std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+            for (auto& r : row) { pcol.push_back(r.first); pval.push_back(r.second); }
+            pptr[q + 1] = (int64_t)pcol.size();
+          }
           std::vector<int64_t> dpos;
-          if (!ilu0(n, ptr, col, val, dpos)) {
+          if (!ilu0(n, pptr, pcol, pval, dpos)) {
 #pragma omp atomic write
             pivot_fail = true;
           }
-          sub.perm.resize(n);
-          std::iota(sub.perm.begin(), sub.perm.end(), 0);
+          sub.perm = perm;
+          sub.operm = perm;
           sub.lptr.assign(n + 1, 0);
           sub.uptr.assign(n + 1, 0);
           sub.dinv.assign(n, 0.0);
           for (int q = 0; q < n; ++q) {
-            for (int64_t e = ptr[q]; e < ptr[q + 1]; ++e) {
-              if (col[e] < q) { sub.lcol.push_back((uint16_t)col[e]); sub.lval.push_back(val[e]); }
-              else if (col[e] > q) { sub.ucol.push_back((uint16_t)col[e]); sub.uval.push_back(val[e]); }
-              else sub.dinv[q] = 1.0 / val[e];
+            for (int64_t e = pptr[q]; e < pptr[q + 1]; ++e) {
+              if (pcol[e] < q) { sub.lcol.push_back((uint16_t)pcol[e]); sub.lval.push_back(pval[e]); }
+              else if (pcol[e] > q) { sub.ucol.push_back((uint16_t)pcol[e]); sub.uval.push_back(pval[e]); }
+              else sub.dinv[q] = 1.0 / pval[e];
             }
             sub.lptr[q + 1] = (int64_t)sub.lcol.size();
             sub.uptr[q + 1] = (int64_t)sub.ucol.size();
@@ -432,6 +501,8 @@ void build_schwarz_host(const cpm_band_s& B, double c, const cpm_precond_opts& o
 #pragma omp atomic write
             pivot_fail = true;
           }
+          sub.operm.resize(n);
+          std::iota(sub.operm.begin(), sub.operm.end(), 0);
           sub.lptr.assign(n + 1, 0);
           sub.uptr.assign(n + 1, 0);
           sub.dinv.assign(n, 0.0);
@@ -443,7 +514,10 @@ void build_schwarz_host(const cpm_band_s& B, double c, const cpm_precond_opts& o
             sub.uptr[q + 1] = (int64_t)sub.ucol.size();
           }
         }
-        sub.levels = std::max(levels(n, sub.lptr, sub.lcol, true), levels(n, sub.uptr, sub.ucol, false));
+        int ll = 0, lu = 0;
+        sub.schedL = schedule(n, sub.lptr, sub.lcol, true, ll);
+        sub.schedU = schedule(n, sub.uptr, sub.ucol, false, lu);
+        sub.levels = std::max(ll, lu);
         for (int q = 0; q < n; ++q) local[om[q]] = -1;
       } catch (const Error& e) {
 #pragma omp critical

@@ -14,7 +14,9 @@ struct SchwarzHost {
     int64_t nnz = 0;
     int levels = 0;
     std::vector<int32_t> rows;     // global active indices of Omega_j, local order
-    std::vector<int32_t> perm;     // input slot q takes local row perm[q] (pivoting; identity for ILU)
+    std::vector<int32_t> perm;     // input slot q takes local row perm[q] (key order)
+    std::vector<int32_t> operm;    // solution slot q is local row operm[q]
+    std::vector<uint16_t> schedL, schedU;  // level-ordered rows of the forward / backward sweeps
     std::vector<int64_t> lptr, uptr;
     std::vector<uint16_t> lcol, ucol;
     std::vector<double> lval, uval, dinv;
@@ -43,7 +45,9 @@ struct DevPC {
   int32_t fp32;                 // values (lval, uval, dinv) are float
   const DevSub* subs;
   const int32_t* in_idx;        // global node feeding input slot q
-  const int32_t* out_idx;       // global node of local row q, bit 31 set when owned
+  const int32_t* out_idx;       // global node of solution slot q, bit 31 set when owned
+  const uint16_t* schedL;       // per subdomain (at row_off): forward sweep row order
+  const uint16_t* schedU;       //   backward sweep row order
   const int64_t* lptr;
   const int64_t* uptr;
   const uint16_t* lcol;
@@ -70,7 +74,7 @@ struct cpm_precond_s {
   cpm::DevBuf<cpm::DevSub> d_subs;
   cpm::DevBuf<int32_t> d_in, d_out, d_err;
   cpm::DevBuf<int64_t> d_lptr, d_uptr;
-  cpm::DevBuf<uint16_t> d_lcol, d_ucol;
+  cpm::DevBuf<uint16_t> d_lcol, d_ucol, d_schL, d_schU;
   cpm::DevBuf<char> d_lval, d_uval, d_dinv;
   cpm::DevBuf<cpm::WorkItem> d_work;
   std::vector<cpm::WorkItem> h_work;

@@ -1,12 +1,12 @@
 // (O)RAS preconditioner apply, z = sum_j Rt_j^T U_j^-1 L_j^-1 R_j r (paper Sec. 2.2,
 // restricted recombination on the disjoint pieces): one workgroup per
 // subdomain (and instance). The local vector lives in LDS; both triangular
-// solves run without barriers: wavefront w takes rows w, w+16, ... in
-// dependency order (forward: ascending, backward: descending), one lane per
-// stored entry, waits on per-row completion flags (LDS acquire/release), and
-// publishes its row after a fixed-order wavefront reduction. The smallest
-// unfinished row always has all its inputs, so the sweep always advances; a
-// bounded wait sets an error flag instead of spinning forever. Only rows the
+// solves run without barriers: wavefront w takes positions w, w+16, ... of a
+// level schedule (a topological order of the sweep), one lane per stored
+// entry, waits on per-row completion flags (LDS acquire/release), and
+// publishes its row after a fixed-order wavefront reduction. The earliest
+// unfinished schedule position always has all its inputs, so the sweep always
+// advances; a bounded wait sets an error flag instead of spinning forever. Only rows the
 // subdomain owns are written back: no two workgroups write the same entry.
 #include <hip/hip_runtime.h>
 
@@ -34,6 +34,81 @@ __device__ __forceinline__ bool wait_flag(int* f, int level, int32_t* err) {
     }
   }
   return true;
+}
+
+// One triangular sweep. The rows follow a level schedule (a topological order
+// of the sweep's dependencies); wavefront `wave` takes schedule positions
+// wave, wave+nw, ...; the pointers and first 64 entries of its next row are
+// loaded while the current row waits for its inputs.
+template <class T, int NRHS, bool BACKWARD>
+__device__ __forceinline__ void sweep(int n, int wave, int nw, int lane, const uint16_t* __restrict__ sched,
+                                      const int64_t* __restrict__ ptr,
+                                      const uint16_t* __restrict__ col, const T* __restrict__ val,
+                                      const T* __restrict__ dinv, T* xv, int* done, int32_t* err) {
+  constexpr int LEVEL = BACKWARD ? 2 : 1;
+  int i = 0;
+  auto row_of = [&](int it) { const int pos = wave + it * nw; return pos < n ? (int)sched[pos] : 0; };
+  int q = row_of(0);
+  bool valid = wave < n;
+  int64_t b = 0, e = 0;
+  int k = -1;
+  T v = (T)0, dq = (T)0;
+  if (valid) {
+    b = ptr[q];
+    e = ptr[q + 1];
+    if (b + lane < e) { k = col[b + lane]; v = val[b + lane]; }
+    if (BACKWARD) dq = dinv[q];
+  }
+  while (valid) {
+    // prefetch the next row of this wavefront
+    const int qn = row_of(i + 1);
+    const bool nvalid = wave + (i + 1) * nw < n;
+    int64_t bn = 0, en = 0;
+    T dn = (T)0;
+    if (nvalid) {
+      bn = ptr[qn];
+      en = ptr[qn + 1];
+      if (BACKWARD) dn = dinv[qn];
+    }
+    T acc[NRHS];
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) acc[r] = (T)0;
+    if (k >= 0) {
+      wait_flag(&done[k], LEVEL, err);
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) acc[r] += v * xv[k * NRHS + r];
+    }
+    for (int64_t t = b + 64 + lane; t < e; t += 64) {   // rows longer than a wavefront
+      const int kk = col[t];
+      const T vv = val[t];
+      wait_flag(&done[kk], LEVEL, err);
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) acc[r] += vv * xv[kk * NRHS + r];
+    }
+    int kn = -1;
+    T vn = (T)0;
+    if (nvalid && bn + lane < en) { kn = col[bn + lane]; vn = val[bn + lane]; }
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) acc[r] = wave_sum(acc[r]);
+    if (lane == 0) {
+      if (BACKWARD) {
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) xv[q * NRHS + r] = (xv[q * NRHS + r] - acc[r]) * dq;
+      } else {
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) xv[q * NRHS + r] -= acc[r];
+      }
+      __hip_atomic_store(&done[q], LEVEL, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    q = qn;
+    valid = nvalid;
+    b = bn;
+    e = en;
+    k = kn;
+    v = vn;
+    dq = dn;
+    ++i;
+  }
 }
 
 template <class T, int NRHS>
@@ -68,50 +143,12 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz(const DevPC* __rest
   __syncthreads();
 
   // forward: y_q = r_q - sum_{k<q} l_qk y_k (unit lower triangle)
-  for (int q = wave; q < n; q += nw) {
-    const int64_t b = lp[q], e = lp[q + 1];
-    T acc[NRHS];
-#pragma unroll
-    for (int r = 0; r < NRHS; ++r) acc[r] = (T)0;
-    for (int64_t t = b + lane; t < e; t += 64) {
-      const int k = P.lcol[t];
-      const T v = lv[t];
-      wait_flag(&done[k], 1, P.error_flag);
-#pragma unroll
-      for (int r = 0; r < NRHS; ++r) acc[r] += v * xv[k * NRHS + r];
-    }
-#pragma unroll
-    for (int r = 0; r < NRHS; ++r) acc[r] = wave_sum(acc[r]);
-    if (lane == 0) {
-#pragma unroll
-      for (int r = 0; r < NRHS; ++r) xv[q * NRHS + r] -= acc[r];
-      __hip_atomic_store(&done[q], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-  }
+  sweep<T, NRHS, false>(n, wave, nw, lane, P.schedL + sub.row_off, lp, P.lcol, lv, nullptr, xv, done,
+                        P.error_flag);
   __syncthreads();
-
   // backward: z_q = (y_q - sum_{k>q} u_qk z_k) / u_qq
-  for (int q = n - 1 - wave; q >= 0; q -= nw) {
-    const int64_t b = up[q], e = up[q + 1];
-    T acc[NRHS];
-#pragma unroll
-    for (int r = 0; r < NRHS; ++r) acc[r] = (T)0;
-    for (int64_t t = b + lane; t < e; t += 64) {
-      const int k = P.ucol[t];
-      const T v = uv[t];
-      wait_flag(&done[k], 2, P.error_flag);
-#pragma unroll
-      for (int r = 0; r < NRHS; ++r) acc[r] += v * xv[k * NRHS + r];
-    }
-#pragma unroll
-    for (int r = 0; r < NRHS; ++r) acc[r] = wave_sum(acc[r]);
-    if (lane == 0) {
-      const T dq = di[q];
-#pragma unroll
-      for (int r = 0; r < NRHS; ++r) xv[q * NRHS + r] = (xv[q * NRHS + r] - acc[r]) * dq;
-      __hip_atomic_store(&done[q], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-  }
+  sweep<T, NRHS, true>(n, wave, nw, lane, P.schedU + sub.row_off, up, P.ucol, uv, di, xv, done,
+                       P.error_flag);
   __syncthreads();
 
   for (int q = tid; q < n; q += blockDim.x) {

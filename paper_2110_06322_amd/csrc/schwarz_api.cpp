@@ -66,7 +66,7 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     std::vector<DevSub> subs(np);
     std::vector<int32_t> in_idx, out_idx;
     std::vector<int64_t> lptr, uptr;
-    std::vector<uint16_t> lcol, ucol;
+    std::vector<uint16_t> lcol, ucol, schL, schU;
     int64_t row_off = 0, loff = 0, uoff = 0;
     for (int j = 0; j < np; ++j) {
       const auto& s = H.subs[j];
@@ -76,9 +76,11 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
       subs[j].pad = 0;
       for (int q = 0; q < s.n; ++q) {
         in_idx.push_back(s.rows[s.perm[q]]);
-        int32_t g = s.rows[q];
+        int32_t g = s.rows[s.operm[q]];
         out_idx.push_back(H.owner[g] == j ? (int32_t)(g | 0x80000000u) : g);
       }
+      schL.insert(schL.end(), s.schedL.begin(), s.schedL.end());
+      schU.insert(schU.end(), s.schedU.begin(), s.schedU.end());
       for (int q = 0; q <= s.n; ++q) {
         lptr.push_back(loff + s.lptr[q]);
         uptr.push_back(uoff + s.uptr[q]);
@@ -100,6 +102,8 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     pc->d_uptr.upload(uptr);
     pc->d_lcol.upload(lcol);
     pc->d_ucol.upload(ucol);
+    pc->d_schL.upload(schL);
+    pc->d_schU.upload(schU);
     const bool fp32 = opts->precision == CPM_PREC_FP32;
     if (fp32) upload_values<float>(pc.get());
     else upload_values<double>(pc.get());
@@ -115,6 +119,9 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
       std::vector<double>().swap(s.uval);
       std::vector<double>().swap(s.dinv);
       std::vector<int32_t>().swap(s.perm);
+      std::vector<int32_t>().swap(s.operm);
+      std::vector<uint16_t>().swap(s.schedL);
+      std::vector<uint16_t>().swap(s.schedU);
     }
     DevPC& P = pc->P;
     std::memset(&P, 0, sizeof(P));
@@ -127,6 +134,8 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     P.uptr = pc->d_uptr.p;
     P.lcol = pc->d_lcol.p;
     P.ucol = pc->d_ucol.p;
+    P.schedL = pc->d_schL.p;
+    P.schedU = pc->d_schU.p;
     P.lval = pc->d_lval.p;
     P.uval = pc->d_uval.p;
     P.dinv = pc->d_dinv.p;

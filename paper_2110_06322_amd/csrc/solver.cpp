@@ -267,7 +267,7 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
   GmresState S = state_of(Bt, m);
   const double* Zb = Bt.any_pc ? Bt.Z.p : Bt.V.p;
   double ms_pc = 0, ms_ap = 0;
-  int n_pc = 0, n_ap = 2;
+  int n_pc = 0, n_ap = 2, n_pc_t = 0, n_ap_t = 0;
   std::vector<hipEvent_t> pev, aev;
   if (o.profile) {
     pev.resize(2 * m);
@@ -338,8 +338,8 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
     if (o.profile) {
       for (int j = 0; j < jdone; ++j) {
         float a = 0, b = 0;
-        if (Bt.any_pc && hipEventElapsedTime(&a, pev[2 * j], pev[2 * j + 1]) == hipSuccess) ms_pc += a;
-        if (hipEventElapsedTime(&b, aev[2 * j], aev[2 * j + 1]) == hipSuccess) ms_ap += b;
+        if (Bt.any_pc && hipEventElapsedTime(&a, pev[2 * j], pev[2 * j + 1]) == hipSuccess) { ms_pc += a; ++n_pc_t; }
+        if (hipEventElapsedTime(&b, aev[2 * j], aev[2 * j + 1]) == hipSuccess) { ms_ap += b; ++n_ap_t; }
       }
     }
     for (int s = 0; s < ns; ++s) {
@@ -384,8 +384,8 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
       q.ms_total = ms;
       q.ms_precond = ms_pc;
       q.ms_apply = ms_ap;
-      q.n_precond = n_pc;
-      q.n_apply = n_ap;
+      q.n_precond = o.profile ? n_pc_t : n_pc;
+      q.n_apply = o.profile ? n_ap_t : n_ap;
     }
   }
   if (ret != CPM_OK) set_error("solver stopped before reaching the tolerance");

@@ -172,3 +172,31 @@ def test_gray_scott_uniform_state_follows_reaction_ode():
     # (1, 0) is a fixed point
     u1, v1 = reaction.imex_step(su, sv, np.ones(n), np.zeros(n), F, k, mu, dt)
     assert np.abs(u1 - 1).max() < 1e-10 and np.abs(v1).max() < 1e-12
+
+
+def test_rcm_textbook_cases():
+    """Reverse Cuthill-McKee: a path graph given in shuffled order comes back as a path
+    (bandwidth 1), starting from a least-degree end; a shuffled banded matrix regains a
+    narrow band; the result is always a permutation."""
+    rng = np.random.default_rng(3)
+    n = 40
+    P = sp.diags([np.ones(n - 1), np.ones(n), np.ones(n - 1)], [-1, 0, 1], format="csr")
+    q = rng.permutation(n)
+    Pq = sp.csr_matrix(P[q][:, q])
+    perm = schwarz.rcm_order(Pq)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    B = sp.csr_matrix(Pq[perm][:, perm])
+    rows, cols = B.nonzero()
+    assert np.abs(rows - cols).max() == 1
+    # banded (bandwidth 5) random pattern, shuffled
+    n = 200
+    M = sp.random(n, n, density=1.0, random_state=1, format="csr")
+    M = sp.csr_matrix(sp.triu(sp.tril(M, 5), -5) + sp.identity(n))
+    q = rng.permutation(n)
+    Mq = sp.csr_matrix(M[q][:, q])
+    r0, c0 = Mq.nonzero()
+    perm = schwarz.rcm_order(Mq)
+    r1, c1 = sp.csr_matrix(Mq[perm][:, perm]).nonzero()
+    assert np.abs(r1 - c1).max() <= 12 < np.abs(r0 - c0).max()
+    # the empty graph: least (degree, index) order reversed
+    assert np.array_equal(schwarz.rcm_order(sp.identity(5, format="csr")), np.arange(5)[::-1])
