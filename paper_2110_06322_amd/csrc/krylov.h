@@ -38,6 +38,7 @@ struct GmresState {
   int32_t* act;     // [ns]
   int32_t* steps;   // [ns]
   int32_t* bad;     // [ns]
+  int32_t* budget;  // [ns]  Arnoldi steps this system may still take (max_it cap)
   int32_t* n_active;
 };
 

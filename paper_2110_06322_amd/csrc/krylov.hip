@@ -8,6 +8,11 @@
 
 #include "krylov.h"
 
+// Vector kernels are bandwidth-bound: keep multiply and add separate so that
+// every right-hand-side count rounds identically (a batch of R systems
+// reproduces each solo solve bit for bit).
+#pragma clang fp contract(off)
+
 namespace cpm {
 
 constexpr int kVecThreads = 256;
@@ -266,7 +271,8 @@ __global__ void k_givens(GmresState S, int j, int ns) {
     S.est[s] = est;
     bool finite = isfinite(hn) && isfinite(est) && isfinite(den);
     if (!finite) S.bad[s] = 1;
-    if (!finite || est <= S.tol_in[s] || hn == 0.0 || den == 0.0 || j + 1 >= m) S.act[s] = 0;
+    if (!finite || est <= S.tol_in[s] || hn == 0.0 || den == 0.0 || j + 1 >= m || j + 1 >= S.budget[s])
+      S.act[s] = 0;
     else alive = 1;
   }
   // count active systems (fixed order)

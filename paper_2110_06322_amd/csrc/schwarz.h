@@ -34,22 +34,24 @@ void operator_row(const cpm_band_s& B, double c, int64_t i, std::vector<int32_t>
 
 // One subdomain as the kernel sees it (offsets into the preconditioner's packed arrays).
 struct DevSub {
-  int64_t row_off;   // into in_idx / out_idx / dinv (n entries)
-  int64_t ptr_off;   // into lptr / uptr (n + 1 entries)
+  int64_t row_off;   // into in_idx / out_idx / dinv / recL / recU (n entries)
+  int64_t lbase;     // first stored entry of the subdomain in lcol / lval
+  int64_t ubase;     // first stored entry in ucol / uval
   int32_t n;
   int32_t pad;
 };
 
+// One row of a triangular sweep, in schedule order: local row (bits 48..63),
+// stored entries (bits 32..47), offset of its first entry from the subdomain's
+// entry base (bits 0..31). Entries are stored in schedule order.
 struct DevPC {
   int32_t nparts;
   int32_t fp32;                 // values (lval, uval, dinv) are float
   const DevSub* subs;
   const int32_t* in_idx;        // global node feeding input slot q
   const int32_t* out_idx;       // global node of solution slot q, bit 31 set when owned
-  const uint16_t* schedL;       // per subdomain (at row_off): forward sweep row order
-  const uint16_t* schedU;       //   backward sweep row order
-  const int64_t* lptr;
-  const int64_t* uptr;
+  const uint64_t* recL;         // per subdomain (at row_off): forward sweep records
+  const uint64_t* recU;         //   backward sweep records
   const uint16_t* lcol;
   const uint16_t* ucol;
   const void* lval;
@@ -73,8 +75,8 @@ struct cpm_precond_s {
   cpm::DevBuf<cpm::DevPC> d_pc;
   cpm::DevBuf<cpm::DevSub> d_subs;
   cpm::DevBuf<int32_t> d_in, d_out, d_err;
-  cpm::DevBuf<int64_t> d_lptr, d_uptr;
-  cpm::DevBuf<uint16_t> d_lcol, d_ucol, d_schL, d_schU;
+  cpm::DevBuf<uint64_t> d_recL, d_recU;
+  cpm::DevBuf<uint16_t> d_lcol, d_ucol;
   cpm::DevBuf<char> d_lval, d_uval, d_dinv;
   cpm::DevBuf<cpm::WorkItem> d_work;
   std::vector<cpm::WorkItem> h_work;

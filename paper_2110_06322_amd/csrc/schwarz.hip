@@ -36,39 +36,73 @@ __device__ __forceinline__ bool wait_flag(int* f, int level, int32_t* err) {
   return true;
 }
 
-// One triangular sweep. The rows follow a level schedule (a topological order
-// of the sweep's dependencies); wavefront `wave` takes schedule positions
-// wave, wave+nw, ...; the pointers and first 64 entries of its next row are
-// loaded while the current row waits for its inputs.
+// Wavefront sum into lane 63 with DPP: inclusive scan inside each 16-lane row
+// (row_shr 1, 2, 4, 8), then the row totals are carried by row_bcast15 and
+// row_bcast31. Fixed order, no LDS traffic.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xf, true);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xf, true);
+  return __hiloint2double(h2, l2);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xf, true));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_any(double v) { return dpp_d<CTRL, ROWMASK>(v); }
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_any(float v) { return dpp_f<CTRL, ROWMASK>(v); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum_to_63(T v) {
+  v += dpp_any<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_any<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_any<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_any<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_any<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_any<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;                      // lane 63 holds the wavefront total
+}
+
+// One triangular sweep. Rows follow a level schedule (a topological order of
+// the sweep's dependencies); wavefront `wave` takes schedule positions wave,
+// wave+nw, .... Each position has a 64-bit record (row, length, entry offset)
+// and its entries are stored in schedule order; the record two positions
+// ahead and the entries one position ahead are loaded while the current row
+// waits for its inputs.
 template <class T, int NRHS, bool BACKWARD>
-__device__ __forceinline__ void sweep(int n, int wave, int nw, int lane, const uint16_t* __restrict__ sched,
-                                      const int64_t* __restrict__ ptr,
+__device__ __forceinline__ void sweep(int n, int wave, int nw, int lane, const uint64_t* __restrict__ rec,
                                       const uint16_t* __restrict__ col, const T* __restrict__ val,
                                       const T* __restrict__ dinv, T* xv, int* done, int32_t* err) {
   constexpr int LEVEL = BACKWARD ? 2 : 1;
-  int i = 0;
-  auto row_of = [&](int it) { const int pos = wave + it * nw; return pos < n ? (int)sched[pos] : 0; };
-  int q = row_of(0);
-  bool valid = wave < n;
-  int64_t b = 0, e = 0;
+  int pos = wave;
+  if (pos >= n) return;
+  uint64_t r0 = rec[pos];
+  uint64_t r1 = pos + nw < n ? rec[pos + nw] : 0ull;
   int k = -1;
   T v = (T)0, dq = (T)0;
-  if (valid) {
-    b = ptr[q];
-    e = ptr[q + 1];
-    if (b + lane < e) { k = col[b + lane]; v = val[b + lane]; }
-    if (BACKWARD) dq = dinv[q];
+  {
+    const int len = (int)((r0 >> 32) & 0xffff);
+    const int64_t off = (int64_t)(r0 & 0xffffffffull);
+    if (lane < len) { k = col[off + lane]; v = val[off + lane]; }
+    if (BACKWARD) dq = dinv[(int)(r0 >> 48)];
   }
-  while (valid) {
-    // prefetch the next row of this wavefront
-    const int qn = row_of(i + 1);
-    const bool nvalid = wave + (i + 1) * nw < n;
-    int64_t bn = 0, en = 0;
-    T dn = (T)0;
-    if (nvalid) {
-      bn = ptr[qn];
-      en = ptr[qn + 1];
-      if (BACKWARD) dn = dinv[qn];
+  for (;;) {
+    const int q = (int)(r0 >> 48);
+    const int len = (int)((r0 >> 32) & 0xffff);
+    const int64_t off = (int64_t)(r0 & 0xffffffffull);
+    const bool has1 = pos + nw < n;
+    // prefetch: record two ahead, entries of the next row
+    const uint64_t r2 = pos + 2 * nw < n ? rec[pos + 2 * nw] : 0ull;
+    int kn = -1;
+    T vn = (T)0, dn = (T)0;
+    if (has1) {
+      const int len1 = (int)((r1 >> 32) & 0xffff);
+      const int64_t off1 = (int64_t)(r1 & 0xffffffffull);
+      if (lane < len1) { kn = col[off1 + lane]; vn = val[off1 + lane]; }
+      if (BACKWARD) dn = dinv[(int)(r1 >> 48)];
     }
     T acc[NRHS];
 #pragma unroll
@@ -78,19 +112,16 @@ __device__ __forceinline__ void sweep(int n, int wave, int nw, int lane, const u
 #pragma unroll
       for (int r = 0; r < NRHS; ++r) acc[r] += v * xv[k * NRHS + r];
     }
-    for (int64_t t = b + 64 + lane; t < e; t += 64) {   // rows longer than a wavefront
-      const int kk = col[t];
-      const T vv = val[t];
+    for (int t = 64 + lane; t < len; t += 64) {   // rows longer than a wavefront
+      const int kk = col[off + t];
+      const T vv = val[off + t];
       wait_flag(&done[kk], LEVEL, err);
 #pragma unroll
       for (int r = 0; r < NRHS; ++r) acc[r] += vv * xv[kk * NRHS + r];
     }
-    int kn = -1;
-    T vn = (T)0;
-    if (nvalid && bn + lane < en) { kn = col[bn + lane]; vn = val[bn + lane]; }
 #pragma unroll
-    for (int r = 0; r < NRHS; ++r) acc[r] = wave_sum(acc[r]);
-    if (lane == 0) {
+    for (int r = 0; r < NRHS; ++r) acc[r] = wave_sum_to_63(acc[r]);
+    if (lane == 63) {
       if (BACKWARD) {
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) xv[q * NRHS + r] = (xv[q * NRHS + r] - acc[r]) * dq;
@@ -100,14 +131,13 @@ __device__ __forceinline__ void sweep(int n, int wave, int nw, int lane, const u
       }
       __hip_atomic_store(&done[q], LEVEL, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    q = qn;
-    valid = nvalid;
-    b = bn;
-    e = en;
+    if (!has1) break;
+    pos += nw;
+    r0 = r1;
+    r1 = r2;
     k = kn;
     v = vn;
     dq = dn;
-    ++i;
   }
 }
 
@@ -126,10 +156,8 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz(const DevPC* __rest
   const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id(), nw = blockDim.x >> 6;
   const int32_t* in_idx = P.in_idx + sub.row_off;
   const int32_t* out_idx = P.out_idx + sub.row_off;
-  const int64_t* lp = P.lptr + sub.ptr_off;
-  const int64_t* up = P.uptr + sub.ptr_off;
-  const T* lv = reinterpret_cast<const T*>(P.lval);
-  const T* uv = reinterpret_cast<const T*>(P.uval);
+  const T* lv = reinterpret_cast<const T*>(P.lval) + sub.lbase;
+  const T* uv = reinterpret_cast<const T*>(P.uval) + sub.ubase;
   const T* di = reinterpret_cast<const T*>(P.dinv) + sub.row_off;
   const double* rb = rin + P.vec_off * NRHS;
   double* zb = zout + P.vec_off * NRHS;
@@ -143,11 +171,11 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz(const DevPC* __rest
   __syncthreads();
 
   // forward: y_q = r_q - sum_{k<q} l_qk y_k (unit lower triangle)
-  sweep<T, NRHS, false>(n, wave, nw, lane, P.schedL + sub.row_off, lp, P.lcol, lv, nullptr, xv, done,
+  sweep<T, NRHS, false>(n, wave, nw, lane, P.recL + sub.row_off, P.lcol + sub.lbase, lv, nullptr, xv, done,
                         P.error_flag);
   __syncthreads();
   // backward: z_q = (y_q - sum_{k>q} u_qk z_k) / u_qq
-  sweep<T, NRHS, true>(n, wave, nw, lane, P.schedU + sub.row_off, up, P.ucol, uv, di, xv, done,
+  sweep<T, NRHS, true>(n, wave, nw, lane, P.recU + sub.row_off, P.ucol + sub.ubase, uv, di, xv, done,
                        P.error_flag);
   __syncthreads();
 

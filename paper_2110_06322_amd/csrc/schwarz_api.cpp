@@ -24,23 +24,9 @@ cpm_status cpm_precond_opts_default(cpm_precond_opts* o) {
 namespace {
 
 template <class T>
-void pack_values(const std::vector<SchwarzHost::Sub>& subs, bool lower, std::vector<T>& out) {
-  size_t tot = 0;
-  for (auto& s : subs) tot += lower ? s.lval.size() : s.uval.size();
-  out.resize(tot);
-  size_t o = 0;
-  for (auto& s : subs) {
-    const auto& v = lower ? s.lval : s.uval;
-    for (double x : v) out[o++] = (T)x;
-  }
-}
-
-template <class T>
-void upload_values(cpm_precond_s* pc) {
+void upload_values(cpm_precond_s* pc, const std::vector<double>& lval, const std::vector<double>& uval) {
   const auto& subs = pc->host.subs;
-  std::vector<T> lv, uv, dv;
-  pack_values(subs, true, lv);
-  pack_values(subs, false, uv);
+  std::vector<T> lv(lval.begin(), lval.end()), uv(uval.begin(), uval.end()), dv;
   for (auto& s : subs)
     for (double x : s.dinv) dv.push_back((T)x);
   pc->d_lval.upload(reinterpret_cast<const char*>(lv.data()), lv.size() * sizeof(T));
@@ -65,13 +51,15 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     const int np = H.nparts;
     std::vector<DevSub> subs(np);
     std::vector<int32_t> in_idx, out_idx;
-    std::vector<int64_t> lptr, uptr;
-    std::vector<uint16_t> lcol, ucol, schL, schU;
-    int64_t row_off = 0, loff = 0, uoff = 0;
+    std::vector<uint64_t> recL, recU;
+    std::vector<uint16_t> lcol, ucol;
+    std::vector<double> lval, uval;
+    int64_t row_off = 0;
     for (int j = 0; j < np; ++j) {
       const auto& s = H.subs[j];
       subs[j].row_off = row_off;
-      subs[j].ptr_off = row_off + j;
+      subs[j].lbase = (int64_t)lcol.size();
+      subs[j].ubase = (int64_t)ucol.size();
       subs[j].n = s.n;
       subs[j].pad = 0;
       for (int q = 0; q < s.n; ++q) {
@@ -79,16 +67,27 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
         int32_t g = s.rows[s.operm[q]];
         out_idx.push_back(H.owner[g] == j ? (int32_t)(g | 0x80000000u) : g);
       }
-      schL.insert(schL.end(), s.schedL.begin(), s.schedL.end());
-      schU.insert(schU.end(), s.schedU.begin(), s.schedU.end());
-      for (int q = 0; q <= s.n; ++q) {
-        lptr.push_back(loff + s.lptr[q]);
-        uptr.push_back(uoff + s.uptr[q]);
+      // entries re-stored in schedule order, one 64-bit record per scheduled row
+      for (int lower = 1; lower >= 0; --lower) {
+        const auto& sched = lower ? s.schedL : s.schedU;
+        const auto& ptr = lower ? s.lptr : s.uptr;
+        const auto& cs = lower ? s.lcol : s.ucol;
+        const auto& vs = lower ? s.lval : s.uval;
+        auto& oc = lower ? lcol : ucol;
+        auto& ov = lower ? lval : uval;
+        auto& rec = lower ? recL : recU;
+        const int64_t base = lower ? subs[j].lbase : subs[j].ubase;
+        for (int t = 0; t < s.n; ++t) {
+          const int row = sched[t];
+          const int64_t b = ptr[row], e = ptr[row + 1];
+          if (e - b > 65535) fail(CPM_ERR_ARG, "row too long for the sweep record");
+          const uint64_t off = (uint64_t)((int64_t)oc.size() - base);
+          if (off > 0xffffffffull) fail(CPM_ERR_ARG, "subdomain factors too large");
+          rec.push_back(((uint64_t)row << 48) | ((uint64_t)(e - b) << 32) | off);
+          oc.insert(oc.end(), cs.begin() + b, cs.begin() + e);
+          ov.insert(ov.end(), vs.begin() + b, vs.begin() + e);
+        }
       }
-      lcol.insert(lcol.end(), s.lcol.begin(), s.lcol.end());
-      ucol.insert(ucol.end(), s.ucol.begin(), s.ucol.end());
-      loff += (int64_t)s.lcol.size();
-      uoff += (int64_t)s.ucol.size();
       row_off += s.n;
       pc->max_rows = std::max(pc->max_rows, s.n);
       pc->max_levels = std::max(pc->max_levels, s.levels);
@@ -98,15 +97,13 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     pc->d_subs.upload(subs);
     pc->d_in.upload(in_idx);
     pc->d_out.upload(out_idx);
-    pc->d_lptr.upload(lptr);
-    pc->d_uptr.upload(uptr);
+    pc->d_recL.upload(recL);
+    pc->d_recU.upload(recU);
     pc->d_lcol.upload(lcol);
     pc->d_ucol.upload(ucol);
-    pc->d_schL.upload(schL);
-    pc->d_schU.upload(schU);
     const bool fp32 = opts->precision == CPM_PREC_FP32;
-    if (fp32) upload_values<float>(pc.get());
-    else upload_values<double>(pc.get());
+    if (fp32) upload_values<float>(pc.get(), lval, uval);
+    else upload_values<double>(pc.get(), lval, uval);
     int32_t zero = 0;
     pc->d_err.upload(&zero, 1);
     // release the host factors; keep partition and row lists for export
@@ -130,12 +127,10 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     P.subs = pc->d_subs.p;
     P.in_idx = pc->d_in.p;
     P.out_idx = pc->d_out.p;
-    P.lptr = pc->d_lptr.p;
-    P.uptr = pc->d_uptr.p;
+    P.recL = pc->d_recL.p;
+    P.recU = pc->d_recU.p;
     P.lcol = pc->d_lcol.p;
     P.ucol = pc->d_ucol.p;
-    P.schedL = pc->d_schL.p;
-    P.schedU = pc->d_schU.p;
     P.lval = pc->d_lval.p;
     P.uval = pc->d_uval.p;
     P.dinv = pc->d_dinv.p;

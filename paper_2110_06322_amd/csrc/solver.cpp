@@ -48,7 +48,7 @@ struct cpm_batch_s {
   int m_alloc = 0;
   DevBuf<double> V, Z, w, r, t, f, x, part, partn, zT;
   DevBuf<double> H, g, cs, sn, y, hcol, hv, nrm2, beta, scale, tol_in, est;
-  DevBuf<int32_t> act, steps, bad, n_active;
+  DevBuf<int32_t> act, steps, bad, budget, n_active;
   int32_t* h_nact = nullptr;   // pinned [2]
   hipEvent_t ev[2] = {nullptr, nullptr};
   ~cpm_batch_s() {
@@ -167,6 +167,7 @@ void ensure_workspace(cpm_batch_s& Bt, int m) {
   Bt.act.alloc(ns);
   Bt.steps.alloc(ns);
   Bt.bad.alloc(ns);
+  Bt.budget.alloc(ns);
   Bt.n_active.alloc(1);
 }
 
@@ -177,6 +178,7 @@ GmresState state_of(cpm_batch_s& Bt, int m) {
   S.H = Bt.H.p; S.g = Bt.g.p; S.cs = Bt.cs.p; S.sn = Bt.sn.p; S.y = Bt.y.p;
   S.hcol = Bt.hcol.p; S.hv = Bt.hv.p; S.nrm2 = Bt.nrm2.p; S.beta = Bt.beta.p; S.scale = Bt.scale.p;
   S.tol_in = Bt.tol_in.p; S.est = Bt.est.p; S.act = Bt.act.p; S.steps = Bt.steps.p; S.bad = Bt.bad.p;
+  S.budget = Bt.budget.p;
   S.n_active = Bt.n_active.p;
   return S;
 }
@@ -275,7 +277,7 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
     for (auto& e : pev) hip_check(hipEventCreate(&e), "event");
     for (auto& e : aev) hip_check(hipEventCreate(&e), "event");
   }
-  std::vector<int32_t> act(ns), steps(ns), bad(ns);
+  std::vector<int32_t> act(ns), steps(ns), bad(ns), budget(ns);
   std::vector<double> tin(ns);
   for (;;) {
     int nact = 0;
@@ -285,8 +287,10 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
       double t = tol[s];
       if (o.mode == CPM_MODE_MIXED_IR) t = std::max(tol[s], o.inner_rtol * beta[s]);
       tin[s] = t;
+      budget[s] = std::max(0, o.max_it - its[s]);
     }
     if (nact == 0) break;
+    hip_check(hipMemcpyAsync(Bt.budget.p, budget.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, st), "upload");
     hip_check(hipMemcpyAsync(Bt.act.p, act.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, st), "upload");
     hip_check(hipMemcpyAsync(Bt.tol_in.p, tin.data(), ns * sizeof(double), hipMemcpyHostToDevice, st), "upload");
     hip_check(hipMemcpyAsync(Bt.beta.p, beta.data(), ns * sizeof(double), hipMemcpyHostToDevice, st), "upload");

@@ -1,0 +1,36 @@
+"""Short, profiler-friendly driver: a fixed number of operator applies on one
+workload and a device-to-device copy of known size (the copy calibrates the
+hardware byte counters against a kernel whose traffic is exactly known).
+
+Usage: python -m paper_2110_06322_amd.profile_apply [sphere|torus] [h] [reps]
+"""
+from __future__ import annotations
+
+import sys
+
+import torch
+
+from . import cpm, inputs
+
+
+def main():
+    kind = sys.argv[1] if len(sys.argv) > 1 else "sphere"
+    h = float(sys.argv[2]) if len(sys.argv) > 2 else 0.02
+    reps = int(sys.argv[3]) if len(sys.argv) > 3 else 20
+    params = (1.0,) if kind == "sphere" else (1.0, 0.4)
+    band = cpm.Band(kind, params, 3, h, 3)
+    op = cpm.Operator(band, 1.0)
+    x = torch.tensor(inputs.normal(1, 0, band.active_keys), dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        op.apply(x, out=y)
+    a = torch.zeros(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")  # 64 MiB
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"{kind} h={h}: N_A={band.n_active} N_G={band.n_ghost} applies={reps}; copy 64 MiB x4", flush=True)
+
+
+if __name__ == "__main__":
+    main()

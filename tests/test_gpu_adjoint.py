@@ -2,7 +2,7 @@
 
 Loss L = |u - u_t|^2 with u = A(c)^-1 f. L is exactly quadratic in f, so
 central differences in f are exact for any step: the step is large
-(max(1, |f|_inf)) and only the solver tolerance (1e-12) limits agreement.
+(max(1, |f|_inf)) and only the solver tolerance (1e-11, near this system's attainable residual) limits agreement.
 For c, central differences with step 1e-4 c. Bar: 1e-6 relative (north-star
 target) against max(|g|, 1e-3 |lambda|_inf); the dense/direct oracle
 adjoint at 1e-9 on a band small enough for a direct solve.
@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
-def _loss(op, f, c, ut, pc, pcT, rtol=1e-12):
+def _loss(op, f, c, ut, pc, pcT, rtol=1e-11):
     fv = f.clone().requires_grad_(True)
     cv = torch.tensor(c, dtype=torch.float64, requires_grad=True)
     u = cpm.CPMSolve.apply(fv, cv, op, pc, pcT, cpm.SolveOptions(rtol=rtol, max_it=50000))

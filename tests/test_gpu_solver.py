@@ -102,7 +102,9 @@ def test_multi_rhs_solve_matches_single_and_is_deterministic():
     assert np.array_equal(U, U2.cpu().numpy().reshape(-1, 4))
     for r in range(4):
         u1, s1 = cpm.solve(op, _t(F[:, r]), pc=pc, rtol=1e-9, mode="mixed")
-        assert np.abs(u1.cpu().numpy() - U[:, r]).max() <= 1e-14 * np.abs(U[:, r]).max() + 1e-300
+        d = np.abs(u1.cpu().numpy() - U[:, r]).max() / np.abs(U[:, r]).max()
+        print(f"rhs {r}: multi vs single {d:.2e}")
+        assert d <= 1e-14
 
 
 def test_failure_modes():
