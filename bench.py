@@ -70,6 +70,25 @@ def cpu_baseline(seconds_budget=20.0):
                       f"N_A={bd.n_active}) in {el:.1f} s"}
 
 
+def measured_traffic():
+    """HBM bytes per apply launch from the committed counter summary, or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "k_apply_tile_sphere_h0.02_counters.md")
+    src = os.path.join(ROOT, "paper_2110_06322_amd", "csrc", "apply.hip")
+    if not os.path.exists(f):
+        return None
+    vals = {}
+    for line in open(f):
+        if ":" in line and line.split(":")[0].strip() in ("traffic_bytes_per_launch", "kernel_source_sha256_16"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if vals.get("kernel_source_sha256_16") != sha:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -141,13 +160,7 @@ def main():
     # Schwarz apply algorithmic bytes: FP32 values + 16-bit columns per stored entry,
     # row pointers (2 x 8 B), input index, output index and FP64 r/z per local row
     b_pc = pci.total_nnz * (4 + 2) + pci.total_rows * (8 + 8 + 4 + 4 + 8 + 8) + 4 * pci.total_rows
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "apply_traffic_sphere_h0.02.json")
-    if os.path.exists(tfile):
-        try:
-            traffic = json.load(open(tfile)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic()
     out = {
         "metric": "CPM apply Gnodes/s (%HBM peak); ORAS-GMRES time to 1e-8, mixed vs FP64",
         "value": round(gnodes, 3),
