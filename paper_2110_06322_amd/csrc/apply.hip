@@ -13,7 +13,8 @@
 // occupancy mask), evaluates every extension row the tile's stencils need
 // (tile nodes plus the face halo) into an LDS box, then applies the
 // (2d+1)-point stencil from LDS. Every extension row is read from HBM once
-// per tile that needs it and no intermediate vector goes back to HBM.
+// per tile that needs it and no intermediate vector goes back to HBM. The
+// per-tile lists (jobs, footprint bricks) are built once on the host.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -244,34 +245,28 @@ constexpr int vbox_doubles() {
   return (D == 3 ? W * W * W : W * W) * NRHS;
 }
 
-template <int D> constexpr int kNbrBricks = D == 3 ? 64 : 16;   // tile bricks grown by one brick
-template <int D> constexpr int kMaxJobs = D == 3 ? 512 + 6 * 64 : 256 + 4 * 16;
-
-// LDS bytes of the fused apply besides the footprint U
+// LDS bytes of the fused apply besides the footprint U: the box of extension values
 template <int D>
 constexpr size_t tile_lds_extra() {
-  return (size_t)vbox_doubles<D, 1>() * 8 + (size_t)kNbrBricks<D> * 24 + (size_t)kMaxFootprintBricks * 16 +
-         (size_t)kMaxJobs<D> * 6 + 16;
+  return (size_t)vbox_doubles<D, 1>() * 8;
 }
 
-// Fused y = A x over the tiles of one or more instances. Per tile:
-//  A. brick directories into LDS, in parallel: the tile's brick neighbourhood
-//     (masks and offsets of the 2^d tile bricks grown by one brick) and the
-//     non-empty bricks overlapping the interpolation footprint;
-//  B. a compacted job list: every band node of the tile and every outward
-//     face neighbour of an active boundary node needs its extension row;
-//  then per right-hand side:
+// Fused y = A x over the tiles of one or more instances. The host lists, per
+// tile, its extension-row jobs (node, slot in the LDS box V), the Sigma_A
+// bricks overlapping its interpolation footprint and its own bricks, so a tile
+// costs two dependent HBM levels (records, then data). The closest points of
+// a thread's jobs and the x values of its stencil rows are fetched before the
+// footprint is staged. Per right-hand side:
 //  C. stage the footprint of x into LDS (one wavefront per brick, lane = node);
-//  D. evaluate the jobs' extension rows into the LDS box V;
+//  D. evaluate the jobs' extension rows into V;
 //  E. (2d+1)-point stencil from V for the tile's active nodes.
 template <int D, int P, int NRHS>
 __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ insts,
                                                     const WorkItem* __restrict__ work, int nwork, int ucap,
                                                     const double* __restrict__ x, double* __restrict__ y) {
   extern __shared__ double smem[];
+  constexpr int NT = 512, NW = NT / 64;
   constexpr int T = kTile<D>, E = kEdge<D>, SH = kShift<D>;
-  constexpr int NBR = kNbrBricks<D>, MFB = kMaxFootprintBricks;
-  constexpr int FACE = D == 3 ? T * T : T;
   constexpr int W = T + 2;
   constexpr int S0 = D == 3 ? W * W : W, S1 = D == 3 ? W : 1, S2 = 1;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -279,113 +274,69 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
   const WorkItem wi = work[w];
   const DevInst& I = insts[wi.inst];
   const DevTile& tile = I.tiles[wi.idx];
-  int flo[3], fdim[3], org[3];
+  int flo[3], fdim[3], blo[3] = {0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < 3; ++k) { flo[k] = tile.flo[k]; fdim[k] = tile.fdim[k]; org[k] = tile.origin[k]; }
-  const int fcnt = tile.fb_cnt;
-  double* U = smem;
-  double* V = U + ucap;
-  uint64_t* nbA = (uint64_t*)(V + vbox_doubles<D, 1>());
-  uint64_t* nbG = nbA + NBR;
-  uint64_t* fdM = nbG + NBR;
-  int32_t* nbOA = (int32_t*)(fdM + MFB);
-  int32_t* nbOG = nbOA + NBR;
-  int32_t* fdO = nbOG + NBR;
-  int32_t* fdR = fdO + MFB;
-  int32_t* jobJ = fdR + MFB;
-  int16_t* jobV = (int16_t*)(jobJ + kMaxJobs<D>);
-  int* njob = (int*)(jobV + kMaxJobs<D> + 2);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
-  const int nwaves = blockDim.x >> 6;
-  const double* xb = x + I.vec_off * NRHS;
-  double* yb = y + I.vec_off * NRHS;
-
-  // ---- A. directories
-  if (tid < NBR) {
-    int rel[3] = {D == 3 ? tid / 16 - 1 : tid / 4 - 1, D == 3 ? (tid / 4) % 4 - 1 : tid % 4 - 1,
-                  D == 3 ? tid % 4 - 1 : 0};
-    int g0[3] = {0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < D; ++k) g0[k] = org[k] + rel[k] * E;
-    int id = brick_at<D>(I, g0);
-    nbA[tid] = id >= 0 ? I.maskA[id] : 0ull;
-    nbG[tid] = id >= 0 ? I.maskG[id] : 0ull;
-    nbOA[tid] = id >= 0 ? I.offA[id] : 0;
-    nbOG[tid] = id >= 0 ? I.offG[id] : 0;
-  }
-  int blo[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k) { flo[k] = tile.flo[k]; fdim[k] = tile.fdim[k]; }
 #pragma unroll
   for (int k = 0; k < D; ++k) blo[k] = flo[k] >> SH;
-  for (int t = tid; t < fcnt; t += blockDim.x) {
-    int id = I.fbricks[tile.fb_off + t];
-    fdM[t] = I.maskA[id];
-    fdO[t] = I.offA[id];
-    int r0 = I.bcoord[id * 3] - blo[0], r1 = I.bcoord[id * 3 + 1] - blo[1];
-    int r2 = D == 3 ? I.bcoord[id * 3 + 2] - blo[2] : 0;
-    fdR[t] = (r0 << 16) | (r1 << 8) | r2;
-  }
-  if (tid == 0) *njob = 0;
-  __syncthreads();
+  const int fcnt = tile.fb_cnt, nj = tile.job_cnt;
+  const FootBrick* fb = I.fbrec + tile.fb_off;
+  const Job* jl = I.jobs + tile.job_off;
+  double* U = smem;
+  double* V = U + ucap;
+  const int tid = threadIdx.x, lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double* xb = x + I.vec_off * NRHS;
+  double* yb = y + I.vec_off * NRHS;
+  int l[3];
+  local_of<D>(lane, l);
 
-  // ---- B. job list (order is irrelevant: every job owns its V slot)
-  for (int q = wave; q < (1 << D); q += nwaves) {
-    int sub[3] = {D == 3 ? (q >> 2) : (q >> 1), D == 3 ? ((q >> 1) & 1) : (q & 1), D == 3 ? (q & 1) : 0};
-    int nbi = D == 3 ? (sub[0] + 1) * 16 + (sub[1] + 1) * 4 + (sub[2] + 1) : (sub[0] + 1) * 4 + (sub[1] + 1);
-    uint64_t mA = nbA[nbi], mG = nbG[nbi];
-    if (!(((mA | mG) >> lane) & 1ull)) continue;
-    int j = ((mA >> lane) & 1ull) ? nbOA[nbi] + mbcnt64(mA) : I.nA + nbOG[nbi] + mbcnt64(mG);
-    int l[3];
-    local_of<D>(lane, l);
+  // jobs of this thread (at most two: a tile has at most 2^d*64 band nodes plus its face halo)
+  int slot0 = -1, slot1 = -1;
+  double cp0[3] = {0, 0, 0}, cp1[3] = {0, 0, 0};
+  if (tid < nj) {
+    const Job j = jl[tid];
+    slot0 = j.slot;
+    load_cp<D>(I, j.node, cp0);
+  }
+  if (tid + NT < nj) {
+    const Job j = jl[tid + NT];
+    slot1 = j.slot;
+    load_cp<D>(I, j.node, cp1);
+  }
+  // stencil row of this thread: wavefront = tile brick, lane = node
+  uint64_t mS = 0;
+  int row = 0, vi = 0;
+  double xi[NRHS];
+  if (wave < (1 << D)) {
+    mS = tile.mA[wave];
+    row = tile.oA[wave] + mbcnt64(mS);
+    const int sub[3] = {D == 3 ? (wave >> 2) : (wave >> 1), D == 3 ? ((wave >> 1) & 1) : (wave & 1),
+                        D == 3 ? (wave & 1) : 0};
+    int ll[3] = {l[0] + sub[0] * E, l[1] + sub[1] * E, l[2] + sub[2] * E};
+    vi = vbox_index<D, 1>(ll);
+  }
+  const bool has_row = (mS >> lane) & 1ull;
+  if (has_row) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) l[k] += sub[k] * E;
-    int pos = atomicAdd(njob, 1);
-    jobJ[pos] = j;
-    jobV[pos] = (int16_t)vbox_index<D, 1>(l);
+    for (int r = 0; r < NRHS; ++r) xi[r] = xb[(int64_t)row * NRHS + r];
   }
-  for (int q = tid; q < 2 * D * FACE; q += blockDim.x) {
-    int f = q / FACE, ps = q % FACE;
-    int axis = f >> 1, side = f & 1;
-    int l[3] = {0, 0, 0};
-    int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-    l[axis] = side ? T - 1 : 0;
-    l[a1] = D == 3 ? ps / T : ps;
-    if (D == 3) l[a2] = ps % T;
-    int nbi = D == 3 ? ((l[0] >> SH) + 1) * 16 + ((l[1] >> SH) + 1) * 4 + ((l[2] >> SH) + 1)
-                     : ((l[0] >> SH) + 1) * 4 + ((l[1] >> SH) + 1);
-    int bit = bit_of<D>(l[0] & (E - 1), l[1] & (E - 1), D == 3 ? (l[2] & (E - 1)) : 0);
-    if (!((nbA[nbi] >> bit) & 1ull)) continue;
-    l[axis] += side ? 1 : -1;
-    int nbo = D == 3 ? (((l[0] + E) >> SH)) * 16 + (((l[1] + E) >> SH)) * 4 + (((l[2] + E) >> SH))
-                     : (((l[0] + E) >> SH)) * 4 + (((l[1] + E) >> SH));
-    int bo = bit_of<D>(l[0] & (E - 1), l[1] & (E - 1), D == 3 ? (l[2] & (E - 1)) : 0);
-    uint64_t mA = nbA[nbo], mG = nbG[nbo];
-    int j;
-    if ((mA >> bo) & 1ull) j = nbOA[nbo] + popc_below(mA, bo);
-    else if ((mG >> bo) & 1ull) j = I.nA + nbOG[nbo] + popc_below(mG, bo);
-    else continue;  // cannot happen on a closed band
-    int pos = atomicAdd(njob, 1);
-    jobJ[pos] = j;
-    jobV[pos] = (int16_t)vbox_index<D, 1>(l);
-  }
-  __syncthreads();
-  const int nj = *njob;
 
+#pragma unroll 1
   for (int r = 0; r < NRHS; ++r) {
     // ---- C. stage the footprint of x (8 bricks per wavefront in flight)
-    int l[3];
-    local_of<D>(lane, l);
-    for (int q0 = wave; q0 < fcnt; q0 += 8 * nwaves) {
+#pragma unroll 1
+    for (int q0 = wave; q0 < fcnt; q0 += 8 * NW) {
       double val[8];
       int slot[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int q = q0 + u * nwaves;
+        const int q = q0 + u * NW;
         slot[u] = -1;
         if (q < fcnt) {
-          const uint64_t m = fdM[q];
-          if ((m >> lane) & 1ull) {
-            const int rp = fdR[q];
-            const int rel[3] = {rp >> 16, (rp >> 8) & 255, rp & 255};
+          const FootBrick rec = fb[q];
+          if ((rec.mask >> lane) & 1ull) {
+            const int rel[3] = {rec.rel >> 16, (rec.rel >> 8) & 255, rec.rel & 255};
             int li = 0;
             bool inside = true;
 #pragma unroll
@@ -396,7 +347,7 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
             }
             if (inside) {
               slot[u] = li;
-              val[u] = xb[(int64_t)(fdO[q] + mbcnt64(m)) * NRHS + r];
+              val[u] = xb[(int64_t)(rec.off + mbcnt64(rec.mask)) * NRHS + r];
             }
           }
         }
@@ -406,35 +357,24 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
         if (slot[u] >= 0) U[slot[u]] = val[u];
     }
     __syncthreads();
-    // ---- D. extension rows (the next job's closest point is fetched ahead)
-    {
-      int q = tid;
-      double cpn[3] = {0, 0, 0};
-      if (q < nj) load_cp<D>(I, jobJ[q], cpn);
-      for (; q < nj; q += blockDim.x) {
-        double cp[3] = {cpn[0], cpn[1], cpn[2]};
-        const int qn = q + blockDim.x;
-        if (qn < nj) load_cp<D>(I, jobJ[qn], cpn);
-        double out[1];
-        erow_lds<D, P, 1>(I, cp, U, flo, fdim, out);
-        V[jobV[q]] = out[0];
-      }
+    // ---- D. extension rows
+    if (slot0 >= 0) {
+      double out[1];
+      erow_lds<D, P, 1>(I, cp0, U, flo, fdim, out);
+      V[slot0] = out[0];
+    }
+    if (slot1 >= 0) {
+      double out[1];
+      erow_lds<D, P, 1>(I, cp1, U, flo, fdim, out);
+      V[slot1] = out[0];
     }
     __syncthreads();
     // ---- E. stencil
-    for (int q = wave; q < (1 << D); q += nwaves) {
-      int sub[3] = {D == 3 ? (q >> 2) : (q >> 1), D == 3 ? ((q >> 1) & 1) : (q & 1), D == 3 ? (q & 1) : 0};
-      int nbi = D == 3 ? (sub[0] + 1) * 16 + (sub[1] + 1) * 4 + (sub[2] + 1) : (sub[0] + 1) * 4 + (sub[1] + 1);
-      uint64_t mA = nbA[nbi];
-      if (!((mA >> lane) & 1ull)) continue;
-      int i = nbOA[nbi] + mbcnt64(mA);
-      int ll[3] = {l[0] + sub[0] * E, l[1] + sub[1] * E, l[2] + sub[2] * E};
-      const int vi = vbox_index<D, 1>(ll);
+    if (has_row) {
       double s = V[vi - S0] + V[vi + S0];
       s += V[vi - S1] + V[vi + S1];
       if (D == 3) s += V[vi - S2] + V[vi + S2];
-      const int64_t e = (int64_t)i * NRHS + r;
-      yb[e] = I.diag * xb[e] - I.inv_h2 * s;
+      yb[(int64_t)row * NRHS + r] = I.diag * xi[r] - I.inv_h2 * s;
     }
     if (r + 1 < NRHS) __syncthreads();
   }
@@ -446,7 +386,7 @@ template <int D, int P, int NRHS>
 __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restrict__ insts,
                                                         const WorkItem* __restrict__ work, int nwork,
                                                         const double* __restrict__ x, double* __restrict__ y) {
-  constexpr int NB = D == 3 ? 8 : 4;
+  constexpr int NB = D == 3 ? 8 : 4, E = kEdge<D>;
   const int w = blockIdx.x;
   if (w >= nwork) return;
   const WorkItem wi = work[w];
@@ -454,16 +394,15 @@ __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restric
   const DevTile& tile = I.tiles[wi.idx];
   const int wave = threadIdx.x >> 6, lane = lane_id();
   for (int q = wave; q < NB; q += (blockDim.x >> 6)) {
-    int id = tile.brick[q];
-    if (id < 0) continue;
-    uint64_t mA = I.maskA[id];
+    const uint64_t mA = tile.mA[q];
     if (!((mA >> lane) & 1ull)) continue;
-    int i = I.offA[id] + mbcnt64(mA);
+    const int i = tile.oA[q] + mbcnt64(mA);
+    const int sub[3] = {D == 3 ? (q >> 2) : (q >> 1), D == 3 ? ((q >> 1) & 1) : (q & 1), D == 3 ? (q & 1) : 0};
     int l[3];
     local_of<D>(lane, l);
     int g[3] = {0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < D; ++k) g[k] = I.bcoord[id * 3 + k] * kEdge<D> + l[k];
+    for (int k = 0; k < D; ++k) g[k] = tile.origin[k] + sub[k] * E + l[k];
     double s[NRHS];
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) s[r] = 0.0;

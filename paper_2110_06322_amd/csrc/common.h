@@ -60,11 +60,8 @@ hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* z
                           hipStream_t s);
 
 inline int vbox_nodes(int d) { return d == 3 ? 10 * 10 * 10 : 18 * 18; }
-// LDS of the fused apply besides the footprint (kept equal to tile_lds_extra<D>() in apply.hip)
-inline size_t tile_lds_extra_bytes(int d) {
-  const size_t nbr = d == 3 ? 64 : 16, jobs = d == 3 ? 512 + 6 * 64 : 256 + 4 * 16;
-  return (size_t)vbox_nodes(d) * 8 + nbr * 24 + (size_t)kMaxFootprintBricks * 16 + jobs * 6 + 16;
-}
+// LDS of the fused apply besides the footprint: the tile's box of extension values
+inline size_t tile_lds_extra_bytes(int d) { return (size_t)vbox_nodes(d) * 8; }
 constexpr size_t kApplyLdsBytes = 64 * 1024;
 
 }  // namespace cpm
@@ -79,7 +76,8 @@ struct cpm_operator_s {
   cpm::DevBuf<uint64_t> d_maskA, d_maskG;
   cpm::DevBuf<int32_t> d_offA, d_offG, d_bcoord, d_bmap, d_bptr, d_brows;
   cpm::DevBuf<cpm::DevTile> d_tiles;
-  cpm::DevBuf<int32_t> d_fbricks;
+  cpm::DevBuf<cpm::FootBrick> d_fbrec;
+  cpm::DevBuf<cpm::Job> d_jobs;
   std::vector<cpm::DevTile> tiles;          // host copy
   std::vector<int32_t> tile_fvol;           // footprint nodes per tile
   cpm::DevBuf<cpm::WorkItem> d_work, d_fb;      // (instance 0, tile) lists: LDS path / fallback

@@ -9,14 +9,29 @@ namespace cpm {
 // Sigma_A first (0..nA-1) then Sigma_G (nA..nA+nG-1).
 struct DevTile {
   int32_t origin[3];   // node coordinates of the tile's lower corner
-  int32_t brick[8];    // brick ids (-1 when absent); 3-D index bx*4+by*2+bz, 2-D bx*2+by
   int32_t flo[3];      // LDS footprint of the tile's interpolation cubes: lower corner
   int32_t fdim[3];     //   and extent (node units)
-  int32_t fb_off;      // non-empty bricks overlapping the footprint: fbricks[fb_off .. fb_off+fb_cnt)
+  int32_t fb_off;      // footprint brick records fbrec[fb_off .. fb_off+fb_cnt)
   int32_t fb_cnt;
+  int32_t job_off;     // extension-row jobs jobs[job_off .. job_off+job_cnt)
+  int32_t job_cnt;
+  int32_t oA[8];       // the tile's bricks (3-D index bx*4+by*2+bz, 2-D bx*2+by):
+  uint64_t mA[8];      //   first Sigma_A index and Sigma_A occupancy (0 when absent)
 };
 
-constexpr int kMaxFootprintBricks = 256;
+// a Sigma_A brick overlapping a tile's footprint
+struct FootBrick {
+  uint64_t mask;       // Sigma_A occupancy
+  int32_t off;         // first Sigma_A index of the brick
+  int32_t rel;         // brick position relative to the footprint's first brick: x<<16 | y<<8 | z
+};
+
+// an extension row a tile evaluates: node index (Sigma_A then Sigma_G) and its slot in
+// the tile's LDS box of edge T+2 (tile nodes and the face halo)
+struct Job {
+  int32_t node;
+  int32_t slot;
+};
 
 struct DevInst {
   int32_t d, p, nA, nG;
@@ -31,7 +46,8 @@ struct DevInst {
   const int32_t* bmap;      // dense brick map over [bm_lo, bm_lo+bm_dim), -1 = none
   int32_t bm_lo[3], bm_dim[3];
   const DevTile* tiles;
-  const int32_t* fbricks;   // per-tile footprint brick lists
+  const FootBrick* fbrec;   // per-tile footprint brick records
+  const Job* jobs;          // per-tile extension-row jobs
   int32_t ntiles;
   int32_t nbricks;
   // transpose: extension rows bucketed by their cube's lower-corner node (an active node)

@@ -23,11 +23,15 @@ void local_of(int d, int bit, int* l) {
   else { l[0] = bit >> 3; l[1] = bit & 7; l[2] = 0; }
 }
 
-// Tiles (2^d bricks) and the bounding box of every interpolation cube a tile evaluates.
+// Tiles (2^d bricks): the jobs (extension rows the tile's stencils need: every
+// band node of the tile plus the outward face neighbours of its active
+// boundary nodes, each with its slot in the tile's LDS box), the bounding box
+// of their interpolation cubes (the LDS footprint) and the Sigma_A bricks
+// overlapping that footprint.
 void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<int32_t>& fvol,
-                 std::vector<int32_t>& fbricks) {
+                 std::vector<FootBrick>& fbrec, std::vector<Job>& jobs) {
   bool orphan = false;
-  const int d = B.d, E = brick_edge(d), T = 2 * E, P = B.p;
+  const int d = B.d, E = brick_edge(d), T = 2 * E, P = B.p, W = T + 2;
   const int64_t nb = B.nbricks();
   std::vector<int64_t> start;
   for (int64_t i = 0; i < nb; ++i) {
@@ -41,23 +45,29 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
   const int64_t nt = (int64_t)start.size() - 1;
   tiles.assign(nt, DevTile{});
   fvol.assign(nt, 0);
-  std::vector<std::vector<int32_t>> fb(nt);
+  std::vector<std::vector<FootBrick>> fb(nt);
+  std::vector<std::vector<Job>> jb(nt);
+  auto slot_of = [&](const int* l) {   // tile-local coordinates in [-1, T] -> LDS box slot
+    return d == 3 ? ((l[0] + 1) * W + (l[1] + 1)) * W + (l[2] + 1) : (l[0] + 1) * W + (l[1] + 1);
+  };
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t t = 0; t < nt; ++t) {
     DevTile& tl = tiles[t];
-    for (int q = 0; q < 8; ++q) tl.brick[q] = -1;
+    for (int q = 0; q < 8; ++q) { tl.oA[q] = 0; tl.mA[q] = 0; }
     for (int k = 0; k < 3; ++k) tl.origin[k] = 0;
     for (int k = 0; k < d; ++k) tl.origin[k] = (B.bcoord[start[t] * 3 + k] >> 1) * T;
     int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
-    auto grow = [&](int64_t node) {
+    auto add_job = [&](int64_t node, const int* l) {
       int32_t b[3];
       base_of(B, &B.cp[node * d], b);
       for (int k = 0; k < d; ++k) { lo[k] = std::min(lo[k], b[k]); hi[k] = std::max(hi[k], b[k] + P); }
+      jb[t].push_back(Job{(int32_t)node, (int32_t)slot_of(l)});
     };
     for (int64_t i = start[t]; i < start[t + 1]; ++i) {
       int sub = 0;
       for (int k = 0; k < d; ++k) sub = sub * 2 + (B.bcoord[i * 3 + k] & 1);
-      tl.brick[sub] = (int32_t)i;
+      tl.oA[sub] = B.offA[i];
+      tl.mA[sub] = B.maskA[i];
       for (int set = 0; set < 2; ++set) {
         uint64_t m = set == 0 ? B.maskA[i] : B.maskG[i];
         int64_t base = set == 0 ? B.offA[i] : B.nA + B.offG[i];
@@ -66,25 +76,27 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
           int bit = __builtin_ctzll(m);
           m &= m - 1;
           int64_t node = base + j++;
-          grow(node);
-          if (set != 0) continue;
-          // face halo: outward neighbours of active nodes on the tile boundary
           int l[3];
           local_of(d, bit, l);
-          int32_t g[3] = {0, 0, 0};
-          for (int k = 0; k < d; ++k) g[k] = B.bcoord[i * 3 + k] * E + l[k];
+          int lt[3] = {0, 0, 0};
+          for (int k = 0; k < d; ++k) lt[k] = B.bcoord[i * 3 + k] * E + l[k] - tl.origin[k];
+          add_job(node, lt);
+          if (set != 0) continue;
+          // face halo: outward neighbours of active nodes on the tile boundary
           for (int k = 0; k < d; ++k)
             for (int s = -1; s <= 1; s += 2) {
-              int32_t gn[3] = {g[0], g[1], g[2]};
-              gn[k] += s;
-              if ((gn[k] - tl.origin[k]) >= 0 && (gn[k] - tl.origin[k]) < T) continue;
+              int ln[3] = {lt[0], lt[1], lt[2]};
+              ln[k] += s;
+              if (ln[k] >= 0 && ln[k] < T) continue;
+              int32_t gn[3] = {0, 0, 0};
+              for (int q = 0; q < d; ++q) gn[q] = tl.origin[q] + ln[q];
               int64_t nn = B.lookup(gn);
               if (nn < 0) {
 #pragma omp atomic write
                 orphan = true;
                 continue;
               }
-              grow(nn);
+              add_job(nn, ln);
             }
         }
       }
@@ -97,7 +109,7 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
       vol *= tl.fdim[k];
     }
     fvol[t] = (int32_t)std::min<int64_t>(vol, INT32_MAX);
-    // non-empty Sigma_A bricks overlapping the footprint
+    // Sigma_A bricks overlapping the footprint
     const int sh = brick_shift(d);
     int32_t b0[3] = {0, 0, 0}, b1[3] = {0, 0, 0};
     for (int k = 0; k < d; ++k) { b0[k] = lo[k] >> sh; b1[k] = hi[k] >> sh; }
@@ -115,16 +127,22 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
           int64_t bi = d == 3 ? ((int64_t)rel[0] * B.bm_dim[1] + rel[1]) * B.bm_dim[2] + rel[2]
                               : (int64_t)rel[0] * B.bm_dim[1] + rel[1];
           int32_t id = B.bmap[bi];
-          if (id >= 0 && B.maskA[id]) fb[t].push_back(id);
+          if (id < 0 || !B.maskA[id]) continue;
+          const int32_t r0 = x - b0[0], r1 = yv - b0[1], r2 = d == 3 ? z - b0[2] : 0;
+          fb[t].push_back(FootBrick{B.maskA[id], B.offA[id], (r0 << 16) | (r1 << 8) | r2});
         }
-    tl.fb_cnt = (int32_t)fb[t].size();
-  }
-  fbricks.clear();
-  for (int64_t t = 0; t < nt; ++t) {
-    tiles[t].fb_off = (int32_t)fbricks.size();
-    fbricks.insert(fbricks.end(), fb[t].begin(), fb[t].end());
   }
   if (orphan) fail(CPM_ERR_BAND, "active node without a band neighbour");
+  fbrec.clear();
+  jobs.clear();
+  for (int64_t t = 0; t < nt; ++t) {
+    tiles[t].fb_off = (int32_t)fbrec.size();
+    tiles[t].fb_cnt = (int32_t)fb[t].size();
+    tiles[t].job_off = (int32_t)jobs.size();
+    tiles[t].job_cnt = (int32_t)jb[t].size();
+    fbrec.insert(fbrec.end(), fb[t].begin(), fb[t].end());
+    jobs.insert(jobs.end(), jb[t].begin(), jb[t].end());
+  }
 }
 
 // Extension rows bucketed by their cube's lower corner (an active node).
@@ -170,9 +188,11 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     const cpm_band_s& B = *op->band;
     const int d = B.d;
     const int64_t n = B.nodes();
-    std::vector<int32_t> fbricks;
-    build_tiles(B, op->tiles, op->tile_fvol, fbricks);
-    op->d_fbricks.upload(fbricks);
+    std::vector<FootBrick> fbrec;
+    std::vector<Job> jobs;
+    build_tiles(B, op->tiles, op->tile_fvol, fbrec, jobs);
+    op->d_fbrec.upload(fbrec);
+    op->d_jobs.upload(jobs);
     std::vector<int32_t> bptr, brows;
     build_buckets(B, bptr, brows);
     // SoA closest points
@@ -201,7 +221,8 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     I.offA = op->d_offA.p; I.offG = op->d_offG.p;
     I.bcoord = op->d_bcoord.p; I.bmap = op->d_bmap.p;
     I.tiles = op->d_tiles.p;
-    I.fbricks = op->d_fbricks.p;
+    I.fbrec = op->d_fbrec.p;
+    I.jobs = op->d_jobs.p;
     I.ntiles = (int32_t)op->tiles.size();
     I.nbricks = (int32_t)B.nbricks();
     I.bucket_ptr = op->d_bptr.p; I.bucket_rows = op->d_brows.p;
@@ -209,16 +230,15 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     op->d_inst.upload(&I, 1);
     // work lists: tiles whose footprint fits the LDS budget, the rest take the slow path
     const int cap = (int)((kApplyLdsBytes - tile_lds_extra_bytes(d)) / sizeof(double));
+    const int max_jobs = d == 3 ? 8 * 64 + 6 * 64 : 4 * 64 + 4 * 16;
     std::vector<WorkItem> fast, slow;
     int ucap = 0;
     for (size_t t = 0; t < op->tiles.size(); ++t) {
       bool has_active = false;
-      for (int q = 0; q < 8; ++q) {
-        int id = op->tiles[t].brick[q];
-        if (id >= 0 && B.maskA[id]) has_active = true;
-      }
+      for (int q = 0; q < 8; ++q)
+        if (op->tiles[t].mA[q]) has_active = true;
       if (!has_active) continue;
-      if (op->tile_fvol[t] <= cap && op->tiles[t].fb_cnt <= kMaxFootprintBricks) {
+      if (op->tile_fvol[t] <= cap && op->tiles[t].job_cnt <= max_jobs) {
         fast.push_back(WorkItem{0, (int32_t)t});
         ucap = std::max(ucap, op->tile_fvol[t]);
       } else {
