@@ -178,6 +178,10 @@ def build_band(cpfun, d, h, p, lo, hi, gamma, periodic=(), prefilter=None,
         ghost = np.setdiff1d(np.unique(cand), active, assume_unique=True)
         allk = np.concatenate([active, ghost])
         cps, _ = cp_of(allk)
+        if not np.isfinite(cps).all():
+            # a node of Sigma_A u Sigma_G on the medial axis: cp is not unique (Sec. 2.1
+            # assumes h small enough that the band stays clear of it)
+            raise ValueError("a band node has no unique closest point; refine h")
         need = np.unique(_cubes(cps, lo, h, p, shape, periodic))
         missing = np.setdiff1d(need, active, assume_unique=True)
         if missing.size == 0:

@@ -48,12 +48,24 @@ def cp_ellipsoid(x: np.ndarray, axes) -> np.ndarray:
     t > -min a_k^2. The root is bracketed by [-amin^2 + amin |x_min|,
     -amin^2 + |(a_k x_k)|] (amin the smallest semi-axis, x_min its coordinate)
     and found by bisection until the midpoint no longer moves.
+
+    A point whose coordinates along every smallest axis vanish and whose
+    G = sum over the other axes of (a_k x_k / (a_k^2 - amin^2))^2 is below 1
+    has no root above -amin^2: it lies on the medial set, where the closest
+    point is not unique (two mirror points). Such points get NaN.
     """
     a = np.asarray(axes, dtype=np.float64)
     a2 = a * a
     kmin = int(np.argmin(a))
     amin = a[kmin]
     ax = x * a[None, :]
+    small = a == amin
+    on_min_axis = (x[:, small] != 0.0).any(axis=1)
+    G = np.zeros(x.shape[0])
+    for k in np.flatnonzero(~small):
+        rk = ax[:, k] / (a2[k] - a2[kmin])
+        G = G + rk * rk
+    medial = ~on_min_axis & (G < 1.0)
     nrm = np.sqrt(ax[:, 0] * ax[:, 0] + ax[:, 1] * ax[:, 1] + ax[:, 2] * ax[:, 2])
     lo = -a2[kmin] + amin * np.abs(x[:, kmin])
     hi = -a2[kmin] + nrm
@@ -73,7 +85,9 @@ def cp_ellipsoid(x: np.ndarray, axes) -> np.ndarray:
         lo = np.where(zero, mid, lo)
         hi = np.where(zero, mid, hi)
     t = 0.5 * (lo + hi)
-    return a2[None, :] * x / (a2[None, :] + t[:, None])
+    y = a2[None, :] * x / (a2[None, :] + t[:, None])
+    y[medial] = np.nan
+    return y
 
 
 def cp_line(x: np.ndarray, y0: float) -> np.ndarray:

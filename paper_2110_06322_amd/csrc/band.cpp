@@ -14,8 +14,10 @@
 // contraction), so independent implementations agree bit for bit.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <climits>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <numeric>
 
@@ -62,6 +64,25 @@ void closest_point(const Surface& s, int d, const double* x, double* cp) {
       for (int k = 1; k < 3; ++k)
         if (a[k] < a[kmin]) kmin = k;
       double ax[3] = {x[0] * a[0], x[1] * a[1], x[2] * a[2]};
+      // Zero coordinates along every smallest axis and sum over the other axes of
+      // (a_k x_k / (a_k^2 - amin^2))^2 below 1: F has no root above -amin^2 and the
+      // point lies on the medial set, where two mirror closest points exist. NaN.
+      {
+        bool on_min_axis = false;
+        double frest = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          if (x[k] == 0.0) continue;
+          if (a[k] == a[kmin]) on_min_axis = true;
+          else {
+            double r = ax[k] / (a2[k] - a2[kmin]);
+            frest += r * r;
+          }
+        }
+        if (!on_min_axis && frest < 1.0) {
+          cp[0] = cp[1] = cp[2] = std::numeric_limits<double>::quiet_NaN();
+          return;
+        }
+      }
       double nrm = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
       double lo = -a2[kmin] + a[kmin] * std::fabs(x[kmin]);
       double hi = -a2[kmin] + nrm;
@@ -252,6 +273,7 @@ cpm_status cpm_band_build(const cpm_surface* surface, int32_t d, double h, int32
     // ---- pass 2: band nodes; mark their interpolation cubes into Sigma_A
     int64_t nband = 0;
     bool outside = false;
+    double bad_x[3] = {0, 0, 0}, bad_cp[3] = {0, 0, 0};
     const int cube = 1 << 0;
     (void)cube;
     const int P1 = p + 1;
@@ -300,12 +322,21 @@ cpm_status cpm_band_build(const cpm_surface* surface, int32_t d, double h, int32
         if (!(std::sqrt(s) <= thr)) continue;
         ++nband;
         if (!mark_cube(cpv, F.A)) {
-#pragma omp atomic write
-          outside = true;
+#pragma omp critical(cpm_band_outside)
+          if (!outside) {
+            outside = true;
+            for (int k = 0; k < 3; ++k) { bad_x[k] = k < d ? x[k] : 0.0; bad_cp[k] = k < d ? cpv[k] : 0.0; }
+          }
         }
       }
     }
-    if (outside) fail(CPM_ERR_BAND, "an interpolation cube leaves the grid box");
+    if (outside) {
+      char msg[256];
+      std::snprintf(msg, sizeof msg,
+                    "an interpolation cube leaves the grid box (node x = (%g, %g, %g), cp = (%g, %g, %g))",
+                    bad_x[0], bad_x[1], bad_x[2], bad_cp[0], bad_cp[1], bad_cp[2]);
+      fail(CPM_ERR_BAND, msg);
+    }
 
     // ---- Sigma_G and the closure check
     int iters = 0;
@@ -349,7 +380,7 @@ cpm_status cpm_band_build(const cpm_surface* surface, int32_t d, double h, int32
       if (outside) fail(CPM_ERR_BAND, "a ghost node leaves the grid box");
       // closure: the cube of every node of Sigma_A u Sigma_G must lie in Sigma_A
       std::vector<uint64_t> add(fsize, 0ull);
-      bool bad = false;
+      bool bad = false, degenerate = false;
 #pragma omp parallel for schedule(dynamic, 1024)
       for (int64_t fi = 0; fi < fsize; ++fi) {
         uint64_t m = F.A[fi] | F.G[fi];
@@ -364,11 +395,26 @@ cpm_status cpm_band_build(const cpm_surface* surface, int32_t d, double h, int32
           double x[3], cpv[3];
           for (int k = 0; k < d; ++k) x[k] = G.lo[k] + (b[k] * G.E + l[k]) * h;
           closest_point(S, d, x, cpv);
-          if (!mark_cube(cpv, add)) {
+          bool finite = true;
+          for (int k = 0; k < d; ++k) finite = finite && std::isfinite(cpv[k]);
+          if (!finite) {
+#pragma omp critical(cpm_band_degenerate)
+            if (!degenerate) {
+              degenerate = true;
+              for (int k = 0; k < 3; ++k) bad_x[k] = k < d ? x[k] : 0.0;
+            }
+          } else if (!mark_cube(cpv, add)) {
 #pragma omp atomic write
             bad = true;
           }
         }
+      }
+      if (degenerate) {
+        char msg[256];
+        std::snprintf(msg, sizeof msg,
+                      "the band node x = (%g, %g, %g) has no unique closest point (the band reaches the medial "
+                      "axis; refine h)", bad_x[0], bad_x[1], bad_x[2]);
+        fail(CPM_ERR_BAND, msg);
       }
       if (bad) fail(CPM_ERR_BAND, "an interpolation cube leaves the grid box");
       bool grew = false;

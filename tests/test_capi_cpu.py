@@ -96,6 +96,17 @@ def test_band_errors():
         assert e.value.status == "CPM_ERR_ARG"
 
 
+def test_band_reaching_the_medial_axis_is_rejected_by_both():
+    """A coarse band around a flat ellipsoid covers its centre node, whose closest
+    point is not unique: library and oracle both refuse to build it."""
+    axes, box = (1.2410195721651176, 1.0657296288514941, 0.6753029137923193), ((-2.5,) * 3, (2.5,) * 3)
+    with pytest.raises(_capi.CpmError) as e:
+        cpm.Band("ellipsoid", axes, 3, 0.1, 3, lo=box[0], hi=box[1])
+    assert e.value.status == "CPM_ERR_BAND" and "closest point" in str(e.value)
+    with pytest.raises(ValueError):
+        C.band("ellipsoid", axes, 3, 0.1, 3, box)
+
+
 def test_gamma_default_matches_formula():
     b = cpm.Band("sphere", (1.0,), 3, 0.1, 3)
     assert abs(b.gamma - inputs.ruuth_merriman_gamma(3, 3, 0.1)) < 1e-15

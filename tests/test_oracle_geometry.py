@@ -70,6 +70,29 @@ def test_ellipsoid_cp_property_and_sphere_case():
     assert np.abs(cps - surfaces.cp_sphere(x, (0, 0, 0), 1.0)).max() < 1e-14
 
 
+def test_ellipsoid_cp_near_and_on_the_medial_set():
+    """Interior points beside the plane of the smallest axis have their closest
+    point off that plane (brute force decides); points on the plane inside the
+    medial set have two mirror closest points and get NaN; points on the plane
+    outside it keep a unique closest point in the plane."""
+    axes = (1.2410195721651176, 1.0657296288514941, 0.6753029137923193)
+    a = np.array(axes)
+    near = np.array([[0.1, -0.3, 1e-6], [0.0, -0.4, -1e-4], [0.3, 0.2, 1e-3], [-0.2, 0.0, 2e-3]])
+    onplane_medial = np.array([[0.0, -0.4, 0.0], [0.1, 0.0, 0.0], [0.0, 0.0, 0.0], [0.3, 0.2, 0.0]])
+    onplane_unique = np.array([[0.0, 0.9, 0.0], [1.1, 0.0, 0.0], [1.5, 0.5, 0.0]])
+    u = rng.uniform(0, 1, (2, 200000))
+    th = np.arccos(1 - 2 * u[0])
+    ph = 2 * math.pi * u[1]
+    S = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 1) * a
+    for x in (near, onplane_unique):
+        cp = surfaces.cp_ellipsoid(x, axes)
+        assert np.allclose(((cp / a) ** 2).sum(1), 1.0, atol=1e-13)
+        dmin = np.linalg.norm(x[:, None, :] - S[None], axis=2).min(axis=1)
+        dcp = np.linalg.norm(x - cp, axis=1)
+        assert (dcp <= dmin + 1e-12).all() and (dcp >= dmin - 2e-3).all()
+    assert np.isnan(surfaces.cp_ellipsoid(onplane_medial, axes)).all()
+
+
 @pytest.mark.parametrize("kind,params,d,h,p,area", [
     ("circle", (1.0,), 2, 0.05, 2, None),
     ("circle", (1.0,), 2, 0.025, 3, None),
