@@ -88,32 +88,34 @@ __device__ __forceinline__ void lagrange(double s, double* w) {
   }
 }
 
-// cube corner b and per-axis weights of the extension row of closest point cp
+// cube corner b and per-axis weights of the extension row whose closest point
+// in grid units is t = (cp - lo)/h
 template <int D, int P>
-__device__ __forceinline__ void erow_weights(const DevInst& I, const double* cp, int* b, double (*w)[P + 1]) {
+__device__ __forceinline__ void erow_weights(const double* t, int* b, double (*w)[P + 1]) {
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    double t = (cp[k] - I.lo[k]) / I.h;
-    double bf = floor(t - (P - 1) * 0.5);
+    double bf = floor(t[k] - (P - 1) * 0.5);
     b[k] = (int)bf;
-    lagrange<P>(t - bf, w[k]);
+    lagrange<P>(t[k] - bf, w[k]);
   }
 }
 
+// closest point of node j in grid units (precomputed on the host with an IEEE division)
 template <int D>
-__device__ __forceinline__ void load_cp(const DevInst& I, int j, double* cp) {
+__device__ __forceinline__ void load_tcp(const DevInst& I, int j, double* t) {
   const int n = I.nA + I.nG;
 #pragma unroll
-  for (int k = 0; k < D; ++k) cp[k] = I.cp[(int64_t)k * n + j];
+  for (int k = 0; k < D; ++k) t[k] = I.tcp[(int64_t)k * n + j];
 }
 
-// Extension row evaluated with per-node index lookups into a global vector
+// Extension row (closest point cp given in grid units) evaluated with per-node
+// index lookups into a global vector
 // (slow path: test hook and tiles whose footprint does not fit in LDS).
 template <int D, int P, int NRHS>
 __device__ void erow_global(const DevInst& I, const double* cp, const double* __restrict__ x, double* out) {
   int b[3] = {0, 0, 0};
   double w[D][P + 1];
-  erow_weights<D, P>(I, cp, b, w);
+  erow_weights<D, P>(cp, b, w);
 #pragma unroll
   for (int r = 0; r < NRHS; ++r) out[r] = 0.0;
   if (D == 3) {
@@ -164,7 +166,7 @@ __device__ __forceinline__ void erow_lds(const DevInst& I, const double* cp, con
                                          const int* flo, const int* fdim, double* out) {
   int b[3] = {0, 0, 0};
   double w[D][P + 1];
-  erow_weights<D, P>(I, cp, b, w);
+  erow_weights<D, P>(cp, b, w);
 #pragma unroll
   for (int r = 0; r < NRHS; ++r) out[r] = 0.0;
   if (D == 3) {
@@ -226,7 +228,7 @@ __global__ void __launch_bounds__(256) k_extend(DevInst I, const double* __restr
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= I.nA + I.nG) return;
   double cp[3], out[1];
-  load_cp<D>(I, j, cp);
+  load_tcp<D>(I, j, cp);
   erow_global<D, P, 1>(I, cp, u, out);
   v[j] = out[0];
 }
@@ -297,12 +299,12 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
   if (tid < nj) {
     const Job j = jl[tid];
     slot0 = j.slot;
-    load_cp<D>(I, j.node, cp0);
+    load_tcp<D>(I, j.node, cp0);
   }
   if (tid + NT < nj) {
     const Job j = jl[tid + NT];
     slot1 = j.slot;
-    load_cp<D>(I, j.node, cp1);
+    load_tcp<D>(I, j.node, cp1);
   }
   // stencil row of this thread: wavefront = tile brick, lane = node
   uint64_t mS = 0;
@@ -413,7 +415,7 @@ __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restric
         int j = node_at<D>(I, gn);
         if (j < 0) continue;  // cannot happen on a closed band
         double cp[3], out[NRHS];
-        load_cp<D>(I, j, cp);
+        load_tcp<D>(I, j, cp);
         erow_global<D, P, NRHS>(I, cp, x, out);
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) s[r] += out[r];
@@ -486,14 +488,13 @@ __global__ void __launch_bounds__(256) k_ET(DevInst I, const double* __restrict_
     for (int e = I.bucket_ptr[bnode]; e < I.bucket_ptr[bnode + 1]; ++e) {
       int j = I.bucket_rows[e];
       double cp[3];
-      load_cp<D>(I, j, cp);
+      load_tcp<D>(I, j, cp);
       double wgt = 1.0;
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        double t = (cp[q] - I.lo[q]) / I.h;
-        double bf = floor(t - (P - 1) * 0.5);
+        double bf = floor(cp[q] - (P - 1) * 0.5);
         double wl[P + 1];
-        lagrange<P>(t - bf, wl);
+        lagrange<P>(cp[q] - bf, wl);
         wgt *= wl[a[q]];
       }
 #pragma unroll

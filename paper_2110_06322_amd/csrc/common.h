@@ -72,7 +72,7 @@ struct cpm_operator_s {
   double c = 1.0;
   cpm::DevInst I{};                         // device pointers, vec_off = 0
   cpm::DevBuf<cpm::DevInst> d_inst;
-  cpm::DevBuf<double> d_cp;
+  cpm::DevBuf<double> d_tcp;   // closest points in grid units, SoA
   cpm::DevBuf<uint64_t> d_maskA, d_maskG;
   cpm::DevBuf<int32_t> d_offA, d_offG, d_bcoord, d_bmap, d_bptr, d_brows;
   cpm::DevBuf<cpm::DevTile> d_tiles;

@@ -37,7 +37,7 @@ struct DevInst {
   int32_t d, p, nA, nG;
   double h, inv_h2, diag;   // diag = c + 2d/h^2
   double lo[3];
-  const double* cp;         // SoA [d][nA+nG]
+  const double* tcp;        // closest points in grid units (cp - lo)/h, SoA [d][nA+nG]
   const uint64_t* maskA;
   const uint64_t* maskG;
   const int32_t* offA;

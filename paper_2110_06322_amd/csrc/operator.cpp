@@ -198,8 +198,8 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     // SoA closest points
     std::vector<double> cps(n * d);
     for (int64_t j = 0; j < n; ++j)
-      for (int k = 0; k < d; ++k) cps[k * n + j] = B.cp[j * d + k];
-    op->d_cp.upload(cps);
+      for (int k = 0; k < d; ++k) cps[k * n + j] = (B.cp[j * d + k] - B.lo[k]) / B.h;
+    op->d_tcp.upload(cps);
     op->d_maskA.upload(B.maskA);
     op->d_maskG.upload(B.maskG);
     op->d_offA.upload(B.offA);
@@ -216,7 +216,7 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     I.inv_h2 = 1.0 / (B.h * B.h);
     I.diag = c + 2.0 * d / (B.h * B.h);
     for (int k = 0; k < 3; ++k) { I.lo[k] = B.lo[k]; I.bm_lo[k] = B.bm_lo[k]; I.bm_dim[k] = B.bm_dim[k]; }
-    I.cp = op->d_cp.p;
+    I.tcp = op->d_tcp.p;
     I.maskA = op->d_maskA.p; I.maskG = op->d_maskG.p;
     I.offA = op->d_offA.p; I.offG = op->d_offG.p;
     I.bcoord = op->d_bcoord.p; I.bmap = op->d_bmap.p;
