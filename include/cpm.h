@@ -263,6 +263,17 @@ cpm_status cpm_batch_apply(cpm_batch* batch, const double* const* x, double* con
 void cpm_batch_destroy(cpm_batch* batch);
 
 /* ---------------------------------------------------------------------
+ * Reaction-diffusion (Sec. 1, eq. rdsys; Sec. 4.1.5, eq. grayscott):
+ * IMEX-Euler right-hand sides of the Gray-Scott system, the reaction taken
+ * explicitly and the diffusion implicitly:
+ *   fu = (u/dt - u v^2 + F (1 - u)) / mu_u,  fv = (v/dt + u v^2 - (F + k) v) / mu_v,
+ * so that (1/(mu dt) - Lap_S^h) w^{n+1} = fw advances each species.
+ * u, v, fu, fv: device [n]; fu/fv may not alias u/v. Asynchronous on stream.
+ * ------------------------------------------------------------------- */
+cpm_status cpm_gray_scott_rhs(int64_t n, const double* u, const double* v, double F, double k, double dt,
+                              double mu_u, double mu_v, double* fu, double* fv, void* stream);
+
+/* ---------------------------------------------------------------------
  * Misc
  * ------------------------------------------------------------------- */
 const char* cpm_last_error(void);

@@ -91,6 +91,7 @@ SIGNATURES = [
     ("cpm_batch_solve", I32, [P, C.POINTER(P), C.POINTER(P), C.POINTER(SolveOpts), C.POINTER(SolveStats), P]),
     ("cpm_batch_apply", I32, [P, C.POINTER(P), C.POINTER(P), P]),
     ("cpm_batch_destroy", None, [P]),
+    ("cpm_gray_scott_rhs", I32, [I64, P, P, D, D, D, D, D, P, P, P]),
     ("cpm_last_error", C.c_char_p, []),
     ("cpm_version", I32, []),
     ("cpm_device_count", I32, []),

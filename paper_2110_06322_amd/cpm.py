@@ -308,11 +308,13 @@ class CPMSolve(torch.autograd.Function):
     g = dL/du: A^T lambda = g, dL/df = lambda, dL/dc = -lambda . u.
     Forward and backward both run GPU FGMRES; the backward solve uses A^T and
     a preconditioner built on A^T when one is given. Call as
-    CPMSolve.apply(f, c, op, pc, pc_T, opts) with c a 0-d tensor.
+    CPMSolve.apply(f, c, op, pc, pc_T, opts, adjoint_rtol) with c a 0-d tensor;
+    adjoint_rtol (default opts.rtol) sets the A^T solve's tolerance, since the
+    attainable residual of either solve is about eps |A| |u| / |f|.
     """
 
     @staticmethod
-    def forward(ctx, f, c, op, pc=None, pc_T=None, opts=None):
+    def forward(ctx, f, c, op, pc=None, pc_T=None, opts=None, adjoint_rtol=None):
         opts = opts or SolveOptions(rtol=1e-12)
         cval = float(c)
         if op.c != cval:
@@ -322,6 +324,7 @@ class CPMSolve(torch.autograd.Function):
             raise RuntimeError(f"forward solve did not converge: {st}")
         ctx.save_for_backward(u)
         ctx.op, ctx.pc_T, ctx.opts = op, pc_T, opts
+        ctx.adjoint_rtol = opts.rtol if adjoint_rtol is None else float(adjoint_rtol)
         ctx.c_meta = (c.device, c.dtype) if torch.is_tensor(c) else (u.device, u.dtype)
         return u
 
@@ -329,10 +332,10 @@ class CPMSolve(torch.autograd.Function):
     def backward(ctx, g):
         (u,) = ctx.saved_tensors
         o = ctx.opts
-        ot = SolveOptions(restart=o.restart, rtol=o.rtol, atol=o.atol, max_it=o.max_it, mode="fp64",
+        ot = SolveOptions(restart=o.restart, rtol=ctx.adjoint_rtol, atol=o.atol, max_it=o.max_it, mode="fp64",
                           transpose=True, stagnation_cycles=o.stagnation_cycles)
         lam, st = solve(ctx.op, g.contiguous(), pc=ctx.pc_T, opts=ot)
         if not st["converged"]:
             raise RuntimeError(f"adjoint solve did not converge: {st}")
         gc = -torch.dot(lam, u)
-        return lam, gc.reshape(()).to(device=ctx.c_meta[0], dtype=ctx.c_meta[1]), None, None, None, None
+        return lam, gc.reshape(()).to(device=ctx.c_meta[0], dtype=ctx.c_meta[1]), None, None, None, None, None

@@ -158,6 +158,23 @@ def batch_instances(seed: int = 3, n_each: int = 16, hs=(0.04, 0.02, 0.01)):
     return out
 
 
+def surface_extent(kind: str, params) -> float:
+    """Largest coordinate magnitude on the surface (centred at the origin)."""
+    if kind in ("circle", "sphere"):
+        return float(params[0])
+    if kind == "torus":
+        return float(params[0] + params[1])
+    return float(max(params))
+
+
+def domain_box(kind: str, params, d: int, h: float, p: int):
+    """Grid box [-L, L]^d: L = 2 unless the band and its interpolation cubes
+    need more room, then the next multiple of 1/2."""
+    need = surface_extent(kind, params) + ruuth_merriman_gamma(d, p, h) + (p + 1) * h
+    L = max(2.0, math.ceil(2.0 * need) / 2.0)
+    return (-L,) * d, (L,) * d
+
+
 def n_subdomains_for(n_active: int, lo: int = 32, hi: int = 512) -> int:
     """clamp(2^round(log2(N_A/2048)), lo, hi)."""
     k = int(round(math.log2(max(n_active, 1) / 2048.0)))

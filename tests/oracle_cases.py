@@ -23,8 +23,8 @@ def band(kind: str, params: tuple, d: int, h: float, p: int, box=None):
 
 
 @functools.lru_cache(maxsize=None)
-def matrices(kind: str, params: tuple, d: int, h: float, p: int, c: float):
-    bd = band(kind, params, d, h, p)
+def matrices(kind: str, params: tuple, d: int, h: float, p: int, c: float, box=None):
+    bd = band(kind, params, d, h, p, box)
     E = O.assemble_E(bd)
     Om = O.assemble_O(bd)
     A = O.assemble_A(bd, c, E, Om)

@@ -2,7 +2,11 @@
 
 Loss L = |u - u_t|^2 with u = A(c)^-1 f. L is exactly quadratic in f, so
 central differences in f are exact for any step: the step is large
-(max(1, |f|_inf)) and only the solver tolerance (1e-11, near this system's attainable residual) limits agreement.
+(max(1, |f|_inf)) and only the solver tolerances limit agreement: forward 1e-11,
+adjoint 5e-11. The attainable relative residual, about eps |A| |u| / |f| with
+|A| ~ 2d/h^2, is near 1e-11 for A and 2.5e-11 to 3e-11 for A^T at h = 0.01;
+with the adjoint at 1e-10 the worst of the 16 nodes already misses the bar by
+a factor 1.2, the error scaling with the adjoint tolerance.
 For c, central differences with step 1e-4 c. Bar: 1e-6 relative (north-star
 target) against max(|g|, 1e-3 |lambda|_inf); the dense/direct oracle
 adjoint at 1e-9 on a band small enough for a direct solve.
@@ -19,10 +23,10 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
-def _loss(op, f, c, ut, pc, pcT, rtol=1e-11):
+def _loss(op, f, c, ut, pc, pcT, rtol=1e-11, adjoint_rtol=5e-11):
     fv = f.clone().requires_grad_(True)
     cv = torch.tensor(c, dtype=torch.float64, requires_grad=True)
-    u = cpm.CPMSolve.apply(fv, cv, op, pc, pcT, cpm.SolveOptions(rtol=rtol, max_it=50000))
+    u = cpm.CPMSolve.apply(fv, cv, op, pc, pcT, cpm.SolveOptions(rtol=rtol, max_it=50000), adjoint_rtol)
     L = ((u - ut) ** 2).sum()
     L.backward()
     return float(L), fv.grad.detach(), float(cv.grad)
