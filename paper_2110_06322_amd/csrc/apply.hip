@@ -17,6 +17,11 @@
 // per-tile lists (jobs, footprint bricks) are built once on the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "device.h"
 
 namespace cpm {
@@ -160,56 +165,58 @@ __device__ void erow_global(const DevInst& I, const double* cp, const double* __
   }
 }
 
-// Extension row evaluated from the LDS footprint U ([f0][f1][f2][NRHS]).
-template <int D, int P, int NRHS>
-__device__ __forceinline__ void erow_lds(const DevInst& I, const double* cp, const double* U,
-                                         const int* flo, const int* fdim, double* out) {
+// Extension row evaluated from the LDS footprint box U (node (x, y, z) of the
+// grid at U[x*s0 + y*s1 + z - fbase]; 2-D: U[x*s0 + y - fbase]).
+template <int D, int P>
+__device__ __forceinline__ double erow_lds(const double* t, const double* U, int s0, int s1, int fbase) {
   int b[3] = {0, 0, 0};
   double w[D][P + 1];
-  erow_weights<D, P>(cp, b, w);
-#pragma unroll
-  for (int r = 0; r < NRHS; ++r) out[r] = 0.0;
-  if (D == 3) {
-    const int s1 = fdim[2], s0 = fdim[1] * fdim[2];
-    const int base = (b[0] - flo[0]) * s0 + (b[1] - flo[1]) * s1 + (b[2] - flo[2]);
+  erow_weights<D, P>(t, b, w);
+  double out = 0.0;
+  if constexpr (D == 3) {
+    const int base = b[0] * s0 + b[1] * s1 + b[2] - fbase;
 #pragma unroll
     for (int a0 = 0; a0 <= P; ++a0) {
-      double acc1[NRHS];
-#pragma unroll
-      for (int r = 0; r < NRHS; ++r) acc1[r] = 0.0;
+      double acc1 = 0.0;
 #pragma unroll
       for (int a1 = 0; a1 <= P; ++a1) {
-        const double* col = U + (base + a0 * s0 + a1 * s1) * NRHS;
-        double acc2[NRHS];
+        const double* col = U + base + a0 * s0 + a1 * s1;
+        double acc2 = 0.0;
 #pragma unroll
-        for (int r = 0; r < NRHS; ++r) acc2[r] = 0.0;
-#pragma unroll
-        for (int a2 = 0; a2 <= P; ++a2)
-#pragma unroll
-          for (int r = 0; r < NRHS; ++r) acc2[r] += w[2][a2] * col[a2 * NRHS + r];
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r) acc1[r] += w[1][a1] * acc2[r];
+        for (int a2 = 0; a2 <= P; ++a2) acc2 += w[2][a2] * col[a2];
+        acc1 += w[1][a1] * acc2;
       }
-#pragma unroll
-      for (int r = 0; r < NRHS; ++r) out[r] += w[0][a0] * acc1[r];
+      out += w[0][a0] * acc1;
     }
   } else {
-    const int s0 = fdim[1];
-    const int base = (b[0] - flo[0]) * s0 + (b[1] - flo[1]);
+    const int base = b[0] * s0 + b[1] - fbase;
 #pragma unroll
     for (int a0 = 0; a0 <= P; ++a0) {
-      const double* col = U + (base + a0 * s0) * NRHS;
-      double acc1[NRHS];
+      const double* col = U + base + a0 * s0;
+      double acc1 = 0.0;
 #pragma unroll
-      for (int r = 0; r < NRHS; ++r) acc1[r] = 0.0;
-#pragma unroll
-      for (int a1 = 0; a1 <= P; ++a1)
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r) acc1[r] += w[1][a1] * col[a1 * NRHS + r];
-#pragma unroll
-      for (int r = 0; r < NRHS; ++r) out[r] += w[0][a0] * acc1[r];
+      for (int a1 = 0; a1 <= P; ++a1) acc1 += w[1][a1] * col[a1];
+      out += w[0][a0] * acc1;
     }
   }
+  return out;
+}
+
+// (2d+1)-point stencil row from the LDS box of extension values (slot vi)
+template <int D>
+__device__ __forceinline__ double stencil_row(const double* V, int vi, double diag, double inv_h2, double xi) {
+  constexpr int W = (D == 3 ? 8 : 16) + 2;
+  constexpr int S0 = D == 3 ? W * W : W, S1 = D == 3 ? W : 1, S2 = 1;
+  double s = V[vi - S0] + V[vi + S0];
+  s += V[vi - S1] + V[vi + S1];
+  if (D == 3) s += V[vi - S2] + V[vi + S2];
+  return diag * xi - inv_h2 * s;
+}
+
+// LDS offset of lane (node l of a brick) inside a footprint box with strides s0, s1
+template <int D>
+__device__ __forceinline__ int lane_box_offset(const int* l, int s0, int s1) {
+  return D == 3 ? l[0] * s0 + l[1] * s1 + l[2] : l[0] * s0 + l[1];
 }
 
 // Work item w of n for block i so that consecutive work items run on the same
@@ -253,9 +260,10 @@ constexpr size_t tile_lds_extra() {
   return (size_t)vbox_doubles<D, 1>() * 8;
 }
 
-// Fused y = A x over the tiles of one or more instances. The host lists, per
-// tile, its extension-row jobs (node, slot in the LDS box V), the Sigma_A
-// bricks overlapping its interpolation footprint and its own bricks, so a tile
+// Fused y = A x over the tiles of one or more instances, one workgroup per
+// tile (used for several right-hand sides). The host lists, per tile, its
+// extension-row jobs (node, slot in the LDS box V), the Sigma_A bricks inside
+// its brick-aligned interpolation footprint box and its own bricks, so a tile
 // costs two dependent HBM levels (records, then data). The closest points of
 // a thread's jobs and the x values of its stencil rows are fetched before the
 // footprint is staged. Per right-hand side:
@@ -268,19 +276,13 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
                                                     const double* __restrict__ x, double* __restrict__ y) {
   extern __shared__ double smem[];
   constexpr int NT = 512, NW = NT / 64;
-  constexpr int T = kTile<D>, E = kEdge<D>, SH = kShift<D>;
-  constexpr int W = T + 2;
-  constexpr int S0 = D == 3 ? W * W : W, S1 = D == 3 ? W : 1, S2 = 1;
+  constexpr int E = kEdge<D>;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   if (w >= nwork) return;
   const WorkItem wi = work[w];
   const DevInst& I = insts[wi.inst];
   const DevTile& tile = I.tiles[wi.idx];
-  int flo[3], fdim[3], blo[3] = {0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < 3; ++k) { flo[k] = tile.flo[k]; fdim[k] = tile.fdim[k]; }
-#pragma unroll
-  for (int k = 0; k < D; ++k) blo[k] = flo[k] >> SH;
+  const int s0 = tile.fstr[0], s1 = tile.fstr[1], fbase = tile.fbase;
   const int fcnt = tile.fb_cnt, nj = tile.job_cnt;
   const FootBrick* fb = I.fbrec + tile.fb_off;
   const Job* jl = I.jobs + tile.job_off;
@@ -292,6 +294,7 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
   double* yb = y + I.vec_off * NRHS;
   int l[3];
   local_of<D>(lane, l);
+  const int loff = lane_box_offset<D>(l, s0, s1);
 
   // jobs of this thread (at most two: a tile has at most 2^d*64 band nodes plus its face halo)
   int slot0 = -1, slot1 = -1;
@@ -338,19 +341,8 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
         if (q < fcnt) {
           const FootBrick rec = fb[q];
           if ((rec.mask >> lane) & 1ull) {
-            const int rel[3] = {rec.rel >> 16, (rec.rel >> 8) & 255, rec.rel & 255};
-            int li = 0;
-            bool inside = true;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-              const int o = ((blo[k] + rel[k]) << SH) + l[k] - flo[k];
-              inside = inside && o >= 0 && o < fdim[k];
-              li = li * fdim[k] + o;
-            }
-            if (inside) {
-              slot[u] = li;
-              val[u] = xb[(int64_t)(rec.off + mbcnt64(rec.mask)) * NRHS + r];
-            }
+            slot[u] = rec.lds + loff;
+            val[u] = xb[(int64_t)(rec.off + mbcnt64(rec.mask)) * NRHS + r];
           }
         }
       }
@@ -360,25 +352,189 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
     }
     __syncthreads();
     // ---- D. extension rows
-    if (slot0 >= 0) {
-      double out[1];
-      erow_lds<D, P, 1>(I, cp0, U, flo, fdim, out);
-      V[slot0] = out[0];
-    }
-    if (slot1 >= 0) {
-      double out[1];
-      erow_lds<D, P, 1>(I, cp1, U, flo, fdim, out);
-      V[slot1] = out[0];
-    }
+    if (slot0 >= 0) V[slot0] = erow_lds<D, P>(cp0, U, s0, s1, fbase);
+    if (slot1 >= 0) V[slot1] = erow_lds<D, P>(cp1, U, s0, s1, fbase);
     __syncthreads();
     // ---- E. stencil
-    if (has_row) {
-      double s = V[vi - S0] + V[vi + S0];
-      s += V[vi - S1] + V[vi + S1];
-      if (D == 3) s += V[vi - S2] + V[vi + S2];
-      yb[(int64_t)row * NRHS + r] = I.diag * xi[r] - I.inv_h2 * s;
-    }
+    if (has_row) yb[(int64_t)row * NRHS + r] = stencil_row<D>(V, vi, I.diag, I.inv_h2, xi[r]);
     if (r + 1 < NRHS) __syncthreads();
+  }
+}
+
+// ---- pipelined single-right-hand-side apply
+//
+// A persistent workgroup walks the tiles of one contiguous range (the work
+// list is split into 8 ranges, one per XCD, so tiles that share footprint
+// data run on the same L2). Three tiles are in flight per workgroup: while
+// the extension rows of tile k are evaluated, the gathered data of tile k+1
+// (closest points of its jobs, its footprint of x, its stencil x values) and
+// the lists of tile k+2 (jobs, footprint brick records) are in transit.
+
+// uniform per-tile values (the footprint record dwords are spread over lanes)
+struct PipeRec {
+  int inst, s0, s1, fbase, fb_off, fb_cnt, job_off, job_cnt, oA;
+  uint64_t mA;
+};
+
+template <int D>
+__device__ __forceinline__ PipeRec pipe_rec(const DevInst* __restrict__ insts, const WorkItem* __restrict__ work,
+                                            int w, int wave) {
+  const WorkItem wi = work[w];
+  const DevTile& T = insts[wi.inst].tiles[wi.idx];
+  PipeRec R;
+  R.inst = wi.inst;
+  R.s0 = T.fstr[0];
+  R.s1 = T.fstr[1];
+  R.fbase = T.fbase;
+  R.fb_off = T.fb_off;
+  R.fb_cnt = T.fb_cnt;
+  R.job_off = T.job_off;
+  R.job_cnt = T.job_cnt;
+  R.oA = wave < (1 << D) ? T.oA[wave] : 0;
+  R.mA = wave < (1 << D) ? T.mA[wave] : 0ull;
+  return R;
+}
+
+// lists of one tile held by one thread: up to two jobs and one dword of the
+// wavefront's footprint brick records (lane 4u+f holds dword f of record wave+8u)
+struct PipeList {
+  int node0, slot0, node1, slot1;
+  uint32_t fbw;
+};
+
+template <int D>
+__device__ __forceinline__ PipeList pipe_list(const DevInst* __restrict__ insts, const PipeRec& R, int tid, int wave,
+                                              int lane) {
+  const DevInst& I = insts[R.inst];
+  PipeList L;
+  L.node0 = 0; L.slot0 = -1; L.node1 = 0; L.slot1 = -1; L.fbw = 0;
+  if (tid < R.job_cnt) {
+    const Job j = I.jobs[R.job_off + tid];
+    L.node0 = j.node;
+    L.slot0 = j.slot;
+  }
+  if (tid + 512 < R.job_cnt) {
+    const Job j = I.jobs[R.job_off + tid + 512];
+    L.node1 = j.node;
+    L.slot1 = j.slot;
+  }
+  const int q = wave + 8 * (lane >> 2);
+  if (lane < 32 && q < R.fb_cnt) L.fbw = reinterpret_cast<const uint32_t*>(I.fbrec + R.fb_off + q)[lane & 3];
+  return L;
+}
+
+// gathered data of one tile held by one thread
+template <int D>
+struct PipeData {
+  double t0[3];          // closest point (grid units) of the first job (a second job, needed
+                         // only by tiles with more than 512 jobs, is fetched when evaluated)
+  double sval[8];        // footprint values this lane stages
+  int sidx[8];           // their LDS slots, -1 = none
+  double xi;             // x at the stencil row
+};
+
+template <int D>
+__device__ __forceinline__ void pipe_data(const DevInst* __restrict__ insts, const PipeRec& R, const PipeList& L,
+                                          const double* __restrict__ x, const int* l, int wave, int lane,
+                                          PipeData<D>& Dt) {
+  const DevInst& I = insts[R.inst];
+  const double* xb = x + I.vec_off;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Dt.t0[k] = 0.0;
+  if (L.slot0 >= 0) load_tcp<D>(I, L.node0, Dt.t0);
+  const int loff = lane_box_offset<D>(l, R.s0, R.s1);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    Dt.sidx[u] = -1;
+    Dt.sval[u] = 0.0;
+    if (wave + 8 * u < R.fb_cnt) {
+      const uint32_t mlo = __builtin_amdgcn_readlane(L.fbw, 4 * u);
+      const uint32_t mhi = __builtin_amdgcn_readlane(L.fbw, 4 * u + 1);
+      const int off = (int)__builtin_amdgcn_readlane(L.fbw, 4 * u + 2);
+      const int lds = (int)__builtin_amdgcn_readlane(L.fbw, 4 * u + 3);
+      const uint64_t m = ((uint64_t)mhi << 32) | mlo;
+      if ((m >> lane) & 1ull) {
+        Dt.sidx[u] = lds + loff;
+        Dt.sval[u] = xb[off + mbcnt64(m)];
+      }
+    }
+  }
+  Dt.xi = 0.0;
+  if ((R.mA >> lane) & 1ull) Dt.xi = xb[R.oA + mbcnt64(R.mA)];
+}
+
+template <int D, int P>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_apply_pipe(const DevInst* __restrict__ insts,
+                                                    const WorkItem* __restrict__ work, int nwork, int ucap,
+                                                    const double* __restrict__ x, double* __restrict__ y) {
+  extern __shared__ double smem[];
+  constexpr int E = kEdge<D>;
+  double* U = smem;
+  double* V = U + ucap;
+  const int tid = threadIdx.x, lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int l[3];
+  local_of<D>(lane, l);
+  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+  const int w_end = (int)(((int64_t)nwork * (xcd + 1)) >> 3);
+  int w = (int)(((int64_t)nwork * xcd) >> 3) + (blockIdx.x >> 3);
+  if (w >= w_end) return;  // uniform over the workgroup, before any barrier
+
+  // slot in V of this thread's stencil row (fixed: wavefront = tile brick, lane = node)
+  int vi = 0;
+  if (wave < (1 << D)) {
+    const int sub[3] = {D == 3 ? (wave >> 2) : (wave >> 1), D == 3 ? ((wave >> 1) & 1) : (wave & 1),
+                        D == 3 ? (wave & 1) : 0};
+    int ll[3] = {l[0] + sub[0] * E, l[1] + sub[1] * E, l[2] + sub[2] * E};
+    vi = vbox_index<D, 1>(ll);
+  }
+
+  // prologue: data of tile w, lists of w+per, record of w+2per
+  PipeRec R0 = pipe_rec<D>(insts, work, w, wave);
+  PipeList L0 = pipe_list<D>(insts, R0, tid, wave, lane);
+  PipeData<D> D0;
+  pipe_data<D>(insts, R0, L0, x, l, wave, lane, D0);
+  const bool v1 = w + per < w_end, v2 = w + 2 * per < w_end;
+  PipeRec R1 = v1 ? pipe_rec<D>(insts, work, w + per, wave) : R0;
+  PipeList L1 = v1 ? pipe_list<D>(insts, R1, tid, wave, lane) : L0;
+  PipeRec R2 = v2 ? pipe_rec<D>(insts, work, w + 2 * per, wave) : R1;
+
+#pragma unroll 1
+  for (; w < w_end; w += per) {
+    const DevInst& I = insts[R0.inst];
+    // ---- stage this tile's footprint of x
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (D0.sidx[u] >= 0) U[D0.sidx[u]] = D0.sval[u];
+    const bool has_row = (R0.mA >> lane) & 1ull;
+    const int row = R0.oA + mbcnt64(R0.mA);
+    const double xi = D0.xi;
+    const double diag = I.diag, inv_h2 = I.inv_h2;
+    double* yb = y + I.vec_off;
+    const int s0 = R0.s0, s1 = R0.s1, fbase = R0.fbase;
+    const int slot0 = L0.slot0, slot1 = L0.slot1, node1 = L0.node1;
+    double t0[3] = {D0.t0[0], D0.t0[1], D0.t0[2]};
+    __syncthreads();
+    // ---- next tiles' loads: data of w+per, lists of w+2per, record of w+3per
+    const bool n1 = w + per < w_end, n2 = w + 2 * per < w_end, n3 = w + 3 * per < w_end;
+    if (n1) pipe_data<D>(insts, R1, L1, x, l, wave, lane, D0);
+    PipeList L2 = L1;
+    if (n2) L2 = pipe_list<D>(insts, R2, tid, wave, lane);
+    PipeRec R3 = R2;
+    if (n3) R3 = pipe_rec<D>(insts, work, w + 3 * per, wave);
+    // ---- extension rows of this tile
+    if (slot0 >= 0) V[slot0] = erow_lds<D, P>(t0, U, s0, s1, fbase);
+    if (slot1 >= 0) {
+      double t1[3];
+      load_tcp<D>(I, node1, t1);
+      V[slot1] = erow_lds<D, P>(t1, U, s0, s1, fbase);
+    }
+    __syncthreads();
+    // ---- stencil
+    if (has_row) yb[row] = stencil_row<D>(V, vi, diag, inv_h2, xi);
+    R0 = R1; L0 = L1;
+    R1 = R2; L1 = L2;
+    R2 = R3;
   }
 }
 
@@ -509,21 +665,57 @@ __global__ void __launch_bounds__(256) k_ET(DevInst I, const double* __restrict_
 }
 
 // ------------------------------------------------------------- launchers
+// Persistent grid of the pipelined apply: resident workgroups per CU (from the
+// occupancy calculator, cached per kernel and LDS size) times the CU count,
+// no more than the tiles, rounded up to a multiple of 8 (one share per XCD).
+static int pipe_grid(int nwork, size_t shm, const void* kern) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, size_t>, int> cache;
+  static int ncu = 0;
+  int per_cu = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (ncu == 0) {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        ncu = 256;
+    }
+    auto it = cache.find({kern, shm});
+    if (it != cache.end()) {
+      per_cu = it->second;
+    } else {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 512, shm) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+      cache[{kern, shm}] = per_cu;
+    }
+  }
+  int g = std::min(ncu * per_cu, nwork);
+  return ((g + 7) / 8) * 8;
+}
+
 template <int D, int P, int NRHS>
-static hipError_t launch_apply_t(const DevInst* insts, const WorkItem* work, int nwork, int ucap, const WorkItem* fb,
-                                 int nfb, const double* x, double* y, hipStream_t s) {
+static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkItem* work, int nwork, int ucap,
+                                 const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s) {
   if (nwork > 0) {
-    size_t shm = (size_t)ucap * sizeof(double) + tile_lds_extra<D>();
-    hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(nwork), dim3(512), shm, s, insts, work, nwork, ucap, x, y);
+    const size_t shm = (size_t)ucap * sizeof(double) + tile_lds_extra<D>();
+    if (NRHS == 1 && variant == kApplyPipelined) {
+      const int grid = pipe_grid(nwork, shm, (const void*)k_apply_pipe<D, P>);
+      hipLaunchKernelGGL((k_apply_pipe<D, P>), dim3(grid), dim3(512), shm, s, insts, work, nwork, ucap, x, y);
+    } else {
+      hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(nwork), dim3(512), shm, s, insts, work, nwork, ucap, x,
+                         y);
+    }
   }
   if (nfb > 0) hipLaunchKernelGGL((k_apply_fallback<D, P, NRHS>), dim3(nfb), dim3(256), 0, s, insts, fb, nfb, x, y);
   return hipGetLastError();
 }
 
-hipError_t launch_apply(int d, int p, int nrhs, const DevInst* insts, const WorkItem* work, int nwork, int ucap,
-                        const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s) {
+hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work, int nwork,
+                        int ucap, const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s) {
 #define CPM_CASE(D, P, R) \
-  if (d == D && p == P && nrhs == R) return launch_apply_t<D, P, R>(insts, work, nwork, ucap, fb, nfb, x, y, s);
+  if (d == D && p == P && nrhs == R)                                                              \
+    return launch_apply_t<D, P, R>(variant, insts, work, nwork, ucap, fb, nfb, x, y, s);
   CPM_CASE(3, 3, 1) CPM_CASE(3, 3, 2) CPM_CASE(3, 3, 4)
   CPM_CASE(3, 2, 1) CPM_CASE(3, 2, 2) CPM_CASE(3, 2, 4)
   CPM_CASE(3, 1, 1) CPM_CASE(3, 1, 2) CPM_CASE(3, 1, 4)

@@ -53,13 +53,16 @@ struct DevBuf {
 };
 
 // kernel launchers (apply.hip)
-hipError_t launch_apply(int d, int p, int nrhs, const DevInst* insts, const WorkItem* work, int nwork, int ucap,
-                        const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s);
+hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work, int nwork,
+                        int ucap, const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s);
 hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream_t s);
 hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* zscratch, double* y,
                           hipStream_t s);
 
 inline int vbox_nodes(int d) { return d == 3 ? 10 * 10 * 10 : 18 * 18; }
+// footprint bricks a tile may stage in the pipelined apply (8 per wavefront)
+constexpr int kMaxFootBricks = 64;
+
 // LDS of the fused apply besides the footprint: the tile's box of extension values
 inline size_t tile_lds_extra_bytes(int d) { return (size_t)vbox_nodes(d) * 8; }
 constexpr size_t kApplyLdsBytes = 64 * 1024;
@@ -83,6 +86,7 @@ struct cpm_operator_s {
   cpm::DevBuf<cpm::WorkItem> d_work, d_fb;      // (instance 0, tile) lists: LDS path / fallback
   std::vector<cpm::WorkItem> h_work, h_fb;
   int nwork = 0, nfb = 0, ucap = 0;
+  int apply_variant = cpm::kApplyPipelined;   // one-RHS apply kernel (tunable)
   // workspace of single solves (one solve at a time per operator)
   mutable std::shared_ptr<cpm_batch_s> solve_cache;
   mutable int64_t solve_cache_key = -1;

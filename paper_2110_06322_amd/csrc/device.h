@@ -9,21 +9,24 @@ namespace cpm {
 // Sigma_A first (0..nA-1) then Sigma_G (nA..nA+nG-1).
 struct DevTile {
   int32_t origin[3];   // node coordinates of the tile's lower corner
-  int32_t flo[3];      // LDS footprint of the tile's interpolation cubes: lower corner
-  int32_t fdim[3];     //   and extent (node units)
+  int32_t fstr[2];     // LDS strides of the footprint box along x and y (z stride 1)
+  int32_t fbase;       // dot(flo, (fstr[0], fstr[1], 1)), flo the box's lower corner
   int32_t fb_off;      // footprint brick records fbrec[fb_off .. fb_off+fb_cnt)
   int32_t fb_cnt;
   int32_t job_off;     // extension-row jobs jobs[job_off .. job_off+job_cnt)
   int32_t job_cnt;
+  int32_t fvol;        // doubles of LDS the footprint box occupies (with padding)
+  int32_t pad;
   int32_t oA[8];       // the tile's bricks (3-D index bx*4+by*2+bz, 2-D bx*2+by):
   uint64_t mA[8];      //   first Sigma_A index and Sigma_A occupancy (0 when absent)
 };
 
-// a Sigma_A brick overlapping a tile's footprint
+// a Sigma_A brick overlapping a tile's footprint box (the box is brick aligned,
+// so all 64 nodes of the brick lie inside it)
 struct FootBrick {
   uint64_t mask;       // Sigma_A occupancy
   int32_t off;         // first Sigma_A index of the brick
-  int32_t rel;         // brick position relative to the footprint's first brick: x<<16 | y<<8 | z
+  int32_t lds;         // LDS index of the brick's lower corner node
 };
 
 // an extension row a tile evaluates: node index (Sigma_A then Sigma_G) and its slot in
@@ -55,6 +58,10 @@ struct DevInst {
   const int32_t* bucket_rows;  // [nA+nG], extension-row ids sorted by corner
   int64_t vec_off;          // offset of this instance's vectors inside a packed batch (doubles / nrhs)
 };
+
+// apply kernels for one right-hand side: persistent pipelined (default) or one workgroup per tile
+constexpr int kApplyPipelined = 0;
+constexpr int kApplyPerTile = 1;
 
 // (instance, item) pair of a work list: a tile, a subdomain or a vector chunk
 struct WorkItem {

@@ -32,6 +32,7 @@ struct cpm_batch_s {
   DevBuf<DevInst> d_insts;
   DevBuf<WorkItem> d_work, d_fb;
   int nwork = 0, nfb = 0, ucap = 0;
+  int apply_variant = kApplyPipelined;
   // preconditioners
   bool any_pc = false, all_pc = true;
   int pc_fp32 = 0, pc_transpose = -1, max_rows = 0, npcwork = 0;
@@ -186,7 +187,8 @@ GmresState state_of(cpm_batch_s& Bt, int m) {
 // y = A x (or A^T x) over all instances of the batch, packed layout
 void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hipStream_t s) {
   if (!transpose) {
-    hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap, Bt.d_fb.p, Bt.nfb, x, y, s),
+    hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
+                           Bt.nfb, x, y, s),
               "operator apply");
     return;
   }
