@@ -263,6 +263,33 @@ cpm_status cpm_batch_apply(cpm_batch* batch, const double* const* x, double* con
 void cpm_batch_destroy(cpm_batch* batch);
 
 /* ---------------------------------------------------------------------
+ * Autotuning. Times the candidate kernel configurations of the operator's
+ * apply (one right-hand side: persistent pipelined kernel or one workgroup
+ * per tile) and, when pc is given, of its subdomain solves (completion flags
+ * or values-as-flags; 256, 512 or 1024 threads per subdomain; with or
+ * without back-off while waiting) on library-allocated scratch vectors, and
+ * keeps the fastest. All candidates compute bit-identical results; only
+ * speed differs. Choices are cached per shape class (device, d, p, nrhs and
+ * power-of-two size classes) in the JSON file cache_path (NULL: no file; a
+ * missing or unreadable file counts as empty; it is rewritten when a class is
+ * added). force = 1 re-times classes found in the cache. Synchronizes the
+ * stream; allocates device memory, so it must not run under graph capture.
+ * Batches and solves created afterwards use the new choices.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int32_t apply_variant;     /* 0 pipelined, 1 per tile */
+  int32_t schwarz_variant;   /* 0 completion flags, 1 values as flags */
+  int32_t schwarz_threads;   /* threads per subdomain workgroup */
+  int32_t schwarz_sleep;     /* 1 = back off while waiting on a dependency */
+  double apply_ms;           /* mean time of one apply with the chosen kernel */
+  double precond_ms;         /* mean time of one preconditioner apply (0 without pc) */
+  int32_t from_cache;        /* 1 when every choice came from the cache file */
+} cpm_tune_result;
+
+cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const char* cache_path,
+                        int32_t force, void* stream, cpm_tune_result* out);
+
+/* ---------------------------------------------------------------------
  * Reaction-diffusion (Sec. 1, eq. rdsys; Sec. 4.1.5, eq. grayscott):
  * IMEX-Euler right-hand sides of the Gray-Scott system, the reaction taken
  * explicitly and the diffusion implicitly:

@@ -60,6 +60,12 @@ class SolveStats(C.Structure):
                 ("n_apply", C.c_int32)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("apply_variant", C.c_int32), ("schwarz_variant", C.c_int32), ("schwarz_threads", C.c_int32),
+                ("schwarz_sleep", C.c_int32), ("apply_ms", C.c_double), ("precond_ms", C.c_double),
+                ("from_cache", C.c_int32)]
+
+
 P = C.c_void_p
 I32 = C.c_int32
 I64 = C.c_int64
@@ -91,6 +97,7 @@ SIGNATURES = [
     ("cpm_batch_solve", I32, [P, C.POINTER(P), C.POINTER(P), C.POINTER(SolveOpts), C.POINTER(SolveStats), P]),
     ("cpm_batch_apply", I32, [P, C.POINTER(P), C.POINTER(P), P]),
     ("cpm_batch_destroy", None, [P]),
+    ("cpm_autotune", I32, [P, P, I32, C.c_char_p, I32, P, C.POINTER(TuneResult)]),
     ("cpm_gray_scott_rhs", I32, [I64, P, P, D, D, D, D, D, P, P, P]),
     ("cpm_last_error", C.c_char_p, []),
     ("cpm_version", I32, []),

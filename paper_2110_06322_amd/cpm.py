@@ -206,6 +206,17 @@ class Precond:
             pass
 
 
+def autotune(op: Operator, pc: Precond | None = None, nrhs: int = 1, cache: str | None = None,
+             force: bool = False, stream=None) -> dict:
+    """Pick the fastest apply / subdomain-solve kernels for this operator (and
+    preconditioner); choices are cached per shape class in the JSON file `cache`."""
+    r = _capi.TuneResult()
+    path = None if cache is None else str(cache).encode()
+    check(lib().cpm_autotune(op._h, None if pc is None else pc._h, int(nrhs), path, int(bool(force)),
+                             _stream(stream), C.byref(r)))
+    return {f: getattr(r, f) for f, _ in _capi.TuneResult._fields_}
+
+
 @dataclass
 class SolveOptions:
     restart: int = 30

@@ -62,8 +62,19 @@ struct DevPC {
 };
 
 int64_t next_serial();
-hipError_t launch_schwarz(const DevPC* pcs, const WorkItem* work, int nwork, int max_rows, int fp32, int nrhs,
-                          const double* r, double* z, hipStream_t s);
+
+// kernel configuration of the subdomain solves (chosen by the tuner)
+constexpr int kSchwarzFlags = 0;        // LDS value array plus per-row completion flags
+constexpr int kSchwarzValueFlags = 1;   // values double as flags (forward and backward arrays)
+constexpr size_t kSchwarzMaxLds = 160 * 1024;
+struct SchwarzCfg {
+  int variant = kSchwarzValueFlags;
+  int threads = 1024;   // threads per subdomain workgroup (a multiple of 64, at most 1024)
+  int sleep = 1;        // back off with s_sleep while waiting on a dependency
+};
+inline size_t schwarz_value_lds(int max_rows, int nrhs, size_t elem) { return 2 * (size_t)max_rows * nrhs * elem; }
+hipError_t launch_schwarz(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
+                          int fp32, int nrhs, const double* r, double* z, hipStream_t s);
 
 }  // namespace cpm
 
@@ -81,6 +92,7 @@ struct cpm_precond_s {
   cpm::DevBuf<cpm::WorkItem> d_work;
   std::vector<cpm::WorkItem> h_work;
   int64_t serial = 0;           // identifies this preconditioner in solver caches
+  cpm::SchwarzCfg cfg;          // kernel configuration (tunable)
   int max_rows = 0, max_levels = 0;
   int64_t total_rows = 0, total_nnz = 0;
 };

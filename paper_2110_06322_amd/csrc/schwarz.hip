@@ -189,34 +189,239 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz(const DevPC* __rest
   }
 }
 
-template <class T, int NRHS>
-static hipError_t launch_t(const DevPC* pcs, const WorkItem* work, int nwork, int max_rows, const double* r,
-                           double* z, hipStream_t s) {
-  const size_t shm = (size_t)max_rows * (NRHS * sizeof(T) + sizeof(int));
+// ---- value-as-flag variant
+//
+// The solution arrays start filled with a signalling-NaN bit pattern that no
+// arithmetic produces; a row's first right-hand-side component is published
+// with a release store after the others, so a waiting wavefront polls the
+// value it needs and gets it in the same load. Input values are read from HBM
+// by the wavefront that owns the row (no gather phase), forward results go to
+// one array and backward results to another, saving one LDS round trip per
+// dependency and per row against the flag-array variant.
+template <class T>
+struct Sentinel;
+template <>
+struct Sentinel<double> {
+  using Bits = unsigned long long;
+  static constexpr Bits kBits = 0x7ff40000deadbeefull;
+};
+template <>
+struct Sentinel<float> {
+  using Bits = unsigned int;
+  static constexpr Bits kBits = 0x7fa0beefu;
+};
+
+template <class T>
+__device__ __forceinline__ T bits_to(typename Sentinel<T>::Bits b) {
+  T v;
+  __builtin_memcpy(&v, &b, sizeof(T));
+  return v;
+}
+template <class T>
+__device__ __forceinline__ typename Sentinel<T>::Bits to_bits(T v) {
+  typename Sentinel<T>::Bits b;
+  __builtin_memcpy(&b, &v, sizeof(T));
+  return b;
+}
+
+// wait until slot p (component 0 of a row) holds a value, return it
+template <class T, bool SLEEP>
+__device__ __forceinline__ T wait_value(T* p, int32_t* err) {
+  using Bits = typename Sentinel<T>::Bits;
+  Bits* bp = reinterpret_cast<Bits*>(p);
+  int spins = 0;
+  for (;;) {
+    const Bits b = __hip_atomic_load(bp, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (b != Sentinel<T>::kBits) return bits_to<T>(b);
+    if (SLEEP) __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return (T)0;
+    }
+  }
+}
+
+template <class T, int NRHS, bool SLEEP>
+__device__ __forceinline__ void dep_accumulate(const T* src, int k, T v, T* acc, int32_t* err) {
+  const T x0 = wait_value<T, SLEEP>(const_cast<T*>(src) + (size_t)k * NRHS, err);
+  acc[0] += v * x0;
+#pragma unroll
+  for (int r = 1; r < NRHS; ++r) acc[r] += v * src[(size_t)k * NRHS + r];
+}
+
+// One sweep of the value-as-flag variant. Forward (BACKWARD = false): dst_q =
+// r_q - sum_k l_qk dst_k, r_q read from HBM through the input index. Backward:
+// dst_q = (y_q - sum_k u_qk dst_k) * dinv_q with y from the forward array.
+template <class T, int NRHS, bool BACKWARD, bool SLEEP>
+__device__ __forceinline__ void sweep_v(int n, int wave, int nw, int lane, const uint64_t* __restrict__ rec,
+                                        const uint16_t* __restrict__ col, const T* __restrict__ val,
+                                        const T* __restrict__ dinv, const int32_t* __restrict__ in_idx,
+                                        const double* __restrict__ rb, const T* yv, T* dst, int32_t* err) {
+  int pos = wave;
+  if (pos >= n) return;
+  uint64_t r0 = rec[pos];
+  uint64_t r1 = pos + nw < n ? rec[pos + nw] : 0ull;
+  int k = -1;
+  T v = (T)0, dq = (T)0;
+  T own[NRHS];
+  {
+    const int q = (int)(r0 >> 48);
+    const int len = (int)((r0 >> 32) & 0xffff);
+    const int64_t off = (int64_t)(r0 & 0xffffffffull);
+    if (lane < len) { k = col[off + lane]; v = val[off + lane]; }
+    if (lane == 63) {
+      if (BACKWARD) {
+        dq = dinv[q];
+      } else {
+        const int64_t g = in_idx[q];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) own[r] = (T)rb[g * NRHS + r];
+      }
+    }
+  }
+  for (;;) {
+    const int q = (int)(r0 >> 48);
+    const int len = (int)((r0 >> 32) & 0xffff);
+    const int64_t off = (int64_t)(r0 & 0xffffffffull);
+    const bool has1 = pos + nw < n;
+    const uint64_t r2 = pos + 2 * nw < n ? rec[pos + 2 * nw] : 0ull;
+    int kn = -1;
+    T vn = (T)0, dn = (T)0;
+    T ownn[NRHS];
+    if (has1) {
+      const int q1 = (int)(r1 >> 48);
+      const int len1 = (int)((r1 >> 32) & 0xffff);
+      const int64_t off1 = (int64_t)(r1 & 0xffffffffull);
+      if (lane < len1) { kn = col[off1 + lane]; vn = val[off1 + lane]; }
+      if (lane == 63) {
+        if (BACKWARD) {
+          dn = dinv[q1];
+        } else {
+          const int64_t g = in_idx[q1];
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r) ownn[r] = (T)rb[g * NRHS + r];
+        }
+      }
+    }
+    T acc[NRHS];
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) acc[r] = (T)0;
+    if (k >= 0) dep_accumulate<T, NRHS, SLEEP>(dst, k, v, acc, err);
+    for (int t = 64 + lane; t < len; t += 64) {   // rows longer than a wavefront
+      dep_accumulate<T, NRHS, SLEEP>(dst, col[off + t], val[off + t], acc, err);
+    }
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) acc[r] = wave_sum_to_63(acc[r]);
+    if (lane == 63) {
+      T out[NRHS];
+      if (BACKWARD) {
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) out[r] = (yv[(size_t)q * NRHS + r] - acc[r]) * dq;
+      } else {
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) out[r] = own[r] - acc[r];
+      }
+#pragma unroll
+      for (int r = 1; r < NRHS; ++r) dst[(size_t)q * NRHS + r] = out[r];
+      __hip_atomic_store(reinterpret_cast<typename Sentinel<T>::Bits*>(dst + (size_t)q * NRHS), to_bits<T>(out[0]),
+                         __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    if (!has1) break;
+    pos += nw;
+    r0 = r1;
+    r1 = r2;
+    k = kn;
+    v = vn;
+    dq = dn;
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) own[r] = ownn[r];
+  }
+}
+
+template <class T, int NRHS, bool SLEEP>
+__global__ void __launch_bounds__(kSchwarzThreads) k_schwarz_v(const DevPC* __restrict__ pcs,
+                                                              const WorkItem* __restrict__ work, int nwork,
+                                                              const double* __restrict__ rin,
+                                                              double* __restrict__ zout) {
+  extern __shared__ double smem_d[];
+  if ((int)blockIdx.x >= nwork) return;
+  const WorkItem wi = work[blockIdx.x];
+  const DevPC& P = pcs[wi.inst];
+  const DevSub sub = P.subs[wi.idx];
+  const int n = sub.n;
+  T* yv = reinterpret_cast<T*>(smem_d);
+  T* zv = yv + (size_t)n * NRHS;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id(), nw = blockDim.x >> 6;
+  const int32_t* in_idx = P.in_idx + sub.row_off;
+  const int32_t* out_idx = P.out_idx + sub.row_off;
+  const T* lv = reinterpret_cast<const T*>(P.lval) + sub.lbase;
+  const T* uv = reinterpret_cast<const T*>(P.uval) + sub.ubase;
+  const T* di = reinterpret_cast<const T*>(P.dinv) + sub.row_off;
+  const double* rb = rin + P.vec_off * NRHS;
+  double* zb = zout + P.vec_off * NRHS;
+  const T sent = bits_to<T>(Sentinel<T>::kBits);
+  for (int q = tid; q < 2 * n * NRHS; q += blockDim.x) yv[q] = sent;
+  __syncthreads();
+  sweep_v<T, NRHS, false, SLEEP>(n, wave, nw, lane, P.recL + sub.row_off, P.lcol + sub.lbase, lv, nullptr, in_idx,
+                                 rb, nullptr, yv, P.error_flag);
+  __syncthreads();
+  sweep_v<T, NRHS, true, SLEEP>(n, wave, nw, lane, P.recU + sub.row_off, P.ucol + sub.ubase, uv, di, nullptr,
+                                nullptr, yv, zv, P.error_flag);
+  __syncthreads();
+  for (int q = tid; q < n; q += blockDim.x) {
+    const int32_t o = out_idx[q];
+    if (o < 0) {
+      const int64_t g = o & 0x7fffffff;
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) zb[g * NRHS + r] = (double)zv[(size_t)q * NRHS + r];
+    }
+  }
+}
+
+static hipError_t lds_ok(const void* kern, size_t shm) {
   int dev = 0, lim = 0;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (shm > (size_t)lim) return hipErrorInvalidConfiguration;
-  if (shm > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_schwarz<T, NRHS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)shm);
-    if (e != hipSuccess) return e;
+  if (shm > 65536) return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  return hipSuccess;
+}
+
+template <class T, int NRHS>
+static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
+                           const double* r, double* z, hipStream_t s) {
+  const int threads = cfg.threads > 0 ? cfg.threads : kSchwarzThreads;
+  if (cfg.variant == kSchwarzValueFlags && schwarz_value_lds(max_rows, NRHS, sizeof(T)) <= kSchwarzMaxLds) {
+    const size_t shm = schwarz_value_lds(max_rows, NRHS, sizeof(T));
+    if (cfg.sleep) {
+      hipError_t e = lds_ok((const void*)k_schwarz_v<T, NRHS, true>, shm);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_schwarz_v<T, NRHS, true>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r, z);
+    } else {
+      hipError_t e = lds_ok((const void*)k_schwarz_v<T, NRHS, false>, shm);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_schwarz_v<T, NRHS, false>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r, z);
+    }
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_schwarz<T, NRHS>), dim3(nwork), dim3(kSchwarzThreads), shm, s, pcs, work, nwork, r, z);
+  const size_t shm = (size_t)max_rows * (NRHS * sizeof(T) + sizeof(int));
+  hipError_t e = lds_ok((const void*)k_schwarz<T, NRHS>, shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_schwarz<T, NRHS>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r, z);
   return hipGetLastError();
 }
 
-hipError_t launch_schwarz(const DevPC* pcs, const WorkItem* work, int nwork, int max_rows, int fp32, int nrhs,
-                          const double* r, double* z, hipStream_t s) {
+hipError_t launch_schwarz(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
+                          int fp32, int nrhs, const double* r, double* z, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   if (fp32) {
-    if (nrhs == 1) return launch_t<float, 1>(pcs, work, nwork, max_rows, r, z, s);
-    if (nrhs == 2) return launch_t<float, 2>(pcs, work, nwork, max_rows, r, z, s);
-    if (nrhs == 4) return launch_t<float, 4>(pcs, work, nwork, max_rows, r, z, s);
+    if (nrhs == 1) return launch_t<float, 1>(cfg, pcs, work, nwork, max_rows, r, z, s);
+    if (nrhs == 2) return launch_t<float, 2>(cfg, pcs, work, nwork, max_rows, r, z, s);
+    if (nrhs == 4) return launch_t<float, 4>(cfg, pcs, work, nwork, max_rows, r, z, s);
   } else {
-    if (nrhs == 1) return launch_t<double, 1>(pcs, work, nwork, max_rows, r, z, s);
-    if (nrhs == 2) return launch_t<double, 2>(pcs, work, nwork, max_rows, r, z, s);
-    if (nrhs == 4) return launch_t<double, 4>(pcs, work, nwork, max_rows, r, z, s);
+    if (nrhs == 1) return launch_t<double, 1>(cfg, pcs, work, nwork, max_rows, r, z, s);
+    if (nrhs == 2) return launch_t<double, 2>(cfg, pcs, work, nwork, max_rows, r, z, s);
+    if (nrhs == 4) return launch_t<double, 4>(cfg, pcs, work, nwork, max_rows, r, z, s);
   }
   return hipErrorInvalidValue;
 }

@@ -187,7 +187,7 @@ cpm_status cpm_precond_export_partition(const cpm_precond* pc, int32_t* owner, i
 namespace cpm {
 // z = M^-1 r for one preconditioner (also used by the solver)
 hipError_t precond_apply_raw(const cpm_precond_s* pc, const double* r, double* z, int nrhs, hipStream_t s) {
-  return launch_schwarz(pc->d_pc.p, pc->d_work.p, pc->host.nparts, pc->max_rows, pc->P.fp32, nrhs, r, z, s);
+  return launch_schwarz(pc->cfg, pc->d_pc.p, pc->d_work.p, pc->host.nparts, pc->max_rows, pc->P.fp32, nrhs, r, z, s);
 }
 // error flag of the bounded waits (0 = fine); resets it
 int precond_take_error(const cpm_precond_s* pc) {

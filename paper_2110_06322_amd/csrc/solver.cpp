@@ -33,6 +33,7 @@ struct cpm_batch_s {
   DevBuf<WorkItem> d_work, d_fb;
   int nwork = 0, nfb = 0, ucap = 0;
   int apply_variant = kApplyPipelined;
+  SchwarzCfg pc_cfg;
   // preconditioners
   bool any_pc = false, all_pc = true;
   int pc_fp32 = 0, pc_transpose = -1, max_rows = 0, npcwork = 0;
@@ -86,6 +87,7 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
     for (const WorkItem& wi : op->h_work) fast.push_back(WorkItem{i, wi.idx});
     for (const WorkItem& wi : op->h_fb) slow.push_back(WorkItem{i, wi.idx});
     Bt.ucap = std::max(Bt.ucap, op->ucap);
+    if (i == 0) Bt.apply_variant = op->apply_variant;
     const cpm_precond_s* pc = pcs ? pcs[i] : nullptr;
     Bt.pcs.push_back(pc);
     if (pc) {
@@ -93,6 +95,7 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
       if (Bt.any_pc && pc->P.fp32 != Bt.pc_fp32) fail(CPM_ERR_ARG, "mixed preconditioner precisions in one batch");
       if (Bt.pc_transpose >= 0 && pc->opts.transpose != Bt.pc_transpose)
         fail(CPM_ERR_ARG, "mixed transposed / plain preconditioners in one batch");
+      if (!Bt.any_pc) Bt.pc_cfg = pc->cfg;
       Bt.pc_fp32 = pc->P.fp32;
       Bt.pc_transpose = pc->opts.transpose;
       Bt.any_pc = true;
@@ -201,7 +204,8 @@ void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hi
 
 void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s) {
   if (Bt.any_pc) {
-    hipError_t e = launch_schwarz(Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.pc_fp32, Bt.R, v, z, s);
+    hipError_t e = launch_schwarz(Bt.pc_cfg, Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.pc_fp32, Bt.R, v, z,
+                                  s);
     if (e == hipErrorInvalidConfiguration)
       fail(CPM_ERR_ARG, "subdomains too large for the local-memory budget at this nrhs/precision");
     hip_check(e, "preconditioner apply");

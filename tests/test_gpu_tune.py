@@ -1,0 +1,91 @@
+"""Autotuner: every candidate kernel configuration computes bit-identical
+results (the tuner may only change speed), and choices round-trip through the
+JSON cache. Candidates are forced by writing their class entry into the cache
+file, the same path a cached choice takes in production.
+"""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2110_06322_amd import cpm, inputs
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    G.ensure_built()
+    b = cpm.Band("sphere", (1.0,), 3, 0.05, 3)
+    op = cpm.Operator(b, 1.0)
+    pcs = {prec: cpm.Precond(op, kind="oras", n_parts=16, overlap=2.0, precision=prec) for prec in ("fp64", "fp32")}
+    return b, op, pcs
+
+
+def _vec(b, nrhs, seed):
+    F = np.stack([inputs.normal(seed, r, b.active_keys) for r in range(nrhs)], axis=1)
+    return torch.tensor(np.ascontiguousarray(F).reshape(-1), dtype=torch.float64, device="cuda")
+
+
+def _force(path, prefix, values):
+    c = json.loads(path.read_text())
+    keys = [k for k in c if k.startswith(prefix)]
+    assert keys, (prefix, list(c))
+    for k in keys:
+        c[k] = values
+    path.write_text(json.dumps(c))
+
+
+def test_tuner_caches_and_reports(sphere, tmp_path):
+    b, op, pcs = sphere
+    cache = tmp_path / "tune.json"
+    r1 = cpm.autotune(op, pcs["fp32"], nrhs=1, cache=cache)
+    assert r1["from_cache"] == 0 and r1["apply_ms"] > 0 and r1["precond_ms"] > 0
+    c = json.loads(cache.read_text())
+    assert any(k.startswith("apply|") for k in c) and any(k.startswith("schwarz|") for k in c)
+    r2 = cpm.autotune(op, pcs["fp32"], nrhs=1, cache=cache)
+    assert r2["from_cache"] == 1
+    for k in ("apply_variant", "schwarz_variant", "schwarz_threads", "schwarz_sleep"):
+        assert r1[k] == r2[k]
+
+
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_apply_variants_bit_identical(sphere, tmp_path, nrhs):
+    b, op, _ = sphere
+    cache = tmp_path / "tune.json"
+    x = _vec(b, nrhs, 11)
+    cpm.autotune(op, None, nrhs=nrhs, cache=cache)
+    outs = []
+    for v in ([0, 1] if nrhs == 1 else [0]):
+        _force(cache, "apply|", [v])
+        r = cpm.autotune(op, None, nrhs=nrhs, cache=cache)
+        assert r["apply_variant"] == v and r["from_cache"] == 1
+        outs.append(op.apply(x, nrhs=nrhs))
+    for y in outs[1:]:
+        assert torch.equal(y, outs[0])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_schwarz_variants_bit_identical(sphere, tmp_path, prec, nrhs):
+    b, op, pcs = sphere
+    pc = pcs[prec]
+    cache = tmp_path / "tune.json"
+    r = _vec(b, nrhs, 12)
+    cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
+    ref = None
+    for cfg in ([0, 256, 1], [0, 1024, 1], [1, 256, 0], [1, 512, 1], [1, 1024, 0], [1, 1024, 1]):
+        _force(cache, "schwarz|", cfg)
+        res = cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
+        assert [res["schwarz_variant"], res["schwarz_threads"], res["schwarz_sleep"]] == cfg
+        z = pc.apply(r, nrhs=nrhs)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = z
+        else:
+            assert torch.equal(z, ref), cfg
+    # restore the default choice for later users of the fixture
+    _force(cache, "schwarz|", [1, 1024, 1])
+    cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
