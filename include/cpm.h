@@ -212,7 +212,12 @@ typedef struct {
   int32_t max_it;         /* cap on Arnoldi steps */
   int32_t mode;           /* cpm_solve_mode */
   int32_t transpose;      /* 1: solve A^T u = f (pc must be built with transpose=1) */
-  int32_t use_graph;      /* 1: replay each restart cycle as a captured hipGraph */
+  int32_t use_graph;      /* 1: run each restart cycle as one captured hipGraph, replayed on a
+                             library stream ordered after `stream`; all m steps are launched and
+                             the operator and preconditioner kernels turn into no-ops once every
+                             system has stopped (results equal those of the eager path); the
+                             graph is captured on first use per batch and restart length.
+                             Not combinable with profile. */
   double inner_rtol;      /* MIXED_IR: per-cycle reduction target (default 1e-4) */
   int32_t stagnation_cycles; /* cycles without 1% progress before giving up (default 50) */
   int32_t profile;        /* 1: time operator / preconditioner kernels with hipEvents (adds syncs) */
@@ -227,7 +232,8 @@ typedef struct {
   double ms_total;        /* wall time of the solve (hipEvent) */
   double ms_precond;      /* profiled: total time of the timed preconditioner launches, else 0 */
   double ms_apply;        /* profiled: total time of the timed operator launches, else 0 */
-  int32_t n_precond;      /* preconditioner applications (profiled: the timed ones) */
+  int32_t n_precond;      /* preconditioner applications (profiled: the timed ones; use_graph:
+                             launches, some of which may have been no-ops) */
   int32_t n_apply;        /* operator applications (profiled: the timed ones, one per Arnoldi step) */
 } cpm_solve_stats;
 

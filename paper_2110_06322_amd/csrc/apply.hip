@@ -273,8 +273,10 @@ constexpr size_t tile_lds_extra() {
 template <int D, int P, int NRHS>
 __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ insts,
                                                     const WorkItem* __restrict__ work, int nwork, int ucap,
-                                                    const double* __restrict__ x, double* __restrict__ y) {
+                                                    const double* __restrict__ x, double* __restrict__ y,
+                                                    const int32_t* __restrict__ gate) {
   extern __shared__ double smem[];
+  if (gate && *gate == 0) return;
   constexpr int NT = 512, NW = NT / 64;
   constexpr int E = kEdge<D>;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -466,8 +468,10 @@ __device__ __forceinline__ void pipe_data(const DevInst* __restrict__ insts, con
 template <int D, int P>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_apply_pipe(const DevInst* __restrict__ insts,
                                                     const WorkItem* __restrict__ work, int nwork, int ucap,
-                                                    const double* __restrict__ x, double* __restrict__ y) {
+                                                    const double* __restrict__ x, double* __restrict__ y,
+                                                    const int32_t* __restrict__ gate) {
   extern __shared__ double smem[];
+  if (gate && *gate == 0) return;
   constexpr int E = kEdge<D>;
   double* U = smem;
   double* V = U + ucap;
@@ -543,7 +547,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
 template <int D, int P, int NRHS>
 __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restrict__ insts,
                                                         const WorkItem* __restrict__ work, int nwork,
-                                                        const double* __restrict__ x, double* __restrict__ y) {
+                                                        const double* __restrict__ x, double* __restrict__ y,
+                                                        const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   constexpr int NB = D == 3 ? 8 : 4, E = kEdge<D>;
   const int w = blockIdx.x;
   if (w >= nwork) return;
@@ -586,7 +592,9 @@ __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restric
 
 // ---- transpose: z = O^T y over Sigma_A u Sigma_G
 template <int D, int NRHS>
-__global__ void __launch_bounds__(256) k_OT(DevInst I, const double* __restrict__ y, double* __restrict__ z) {
+__global__ void __launch_bounds__(256) k_OT(DevInst I, const double* __restrict__ y, double* __restrict__ z,
+                                            const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (id >= I.nbricks) return;
   const int lane = lane_id();
@@ -618,7 +626,8 @@ __global__ void __launch_bounds__(256) k_OT(DevInst I, const double* __restrict_
 // ---- transpose: y_out = diag y - h^-2 E^T z, each output gathers the rows whose cube holds it
 template <int D, int P, int NRHS>
 __global__ void __launch_bounds__(256) k_ET(DevInst I, const double* __restrict__ yin, const double* __restrict__ z,
-                                            double* __restrict__ yout) {
+                                            double* __restrict__ yout, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (id >= I.nbricks) return;
   const int lane = lane_id();
@@ -696,26 +705,29 @@ static int pipe_grid(int nwork, size_t shm, const void* kern) {
 
 template <int D, int P, int NRHS>
 static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkItem* work, int nwork, int ucap,
-                                 const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s) {
+                                 const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s,
+                                 const int32_t* gate) {
   if (nwork > 0) {
     const size_t shm = (size_t)ucap * sizeof(double) + tile_lds_extra<D>();
     if (NRHS == 1 && variant == kApplyPipelined) {
       const int grid = pipe_grid(nwork, shm, (const void*)k_apply_pipe<D, P>);
-      hipLaunchKernelGGL((k_apply_pipe<D, P>), dim3(grid), dim3(512), shm, s, insts, work, nwork, ucap, x, y);
+      hipLaunchKernelGGL((k_apply_pipe<D, P>), dim3(grid), dim3(512), shm, s, insts, work, nwork, ucap, x, y, gate);
     } else {
       hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(nwork), dim3(512), shm, s, insts, work, nwork, ucap, x,
-                         y);
+                         y, gate);
     }
   }
-  if (nfb > 0) hipLaunchKernelGGL((k_apply_fallback<D, P, NRHS>), dim3(nfb), dim3(256), 0, s, insts, fb, nfb, x, y);
+  if (nfb > 0)
+    hipLaunchKernelGGL((k_apply_fallback<D, P, NRHS>), dim3(nfb), dim3(256), 0, s, insts, fb, nfb, x, y, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work, int nwork,
-                        int ucap, const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s) {
+                        int ucap, const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s,
+                        const int32_t* gate) {
 #define CPM_CASE(D, P, R) \
   if (d == D && p == P && nrhs == R)                                                              \
-    return launch_apply_t<D, P, R>(variant, insts, work, nwork, ucap, fb, nfb, x, y, s);
+    return launch_apply_t<D, P, R>(variant, insts, work, nwork, ucap, fb, nfb, x, y, s, gate);
   CPM_CASE(3, 3, 1) CPM_CASE(3, 3, 2) CPM_CASE(3, 3, 4)
   CPM_CASE(3, 2, 1) CPM_CASE(3, 2, 2) CPM_CASE(3, 2, 4)
   CPM_CASE(3, 1, 1) CPM_CASE(3, 1, 2) CPM_CASE(3, 1, 4)
@@ -738,17 +750,19 @@ hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream
 }
 
 template <int D, int P, int NRHS>
-static hipError_t launch_apply_T_t(const DevInst& I, const double* x, double* z, double* y, hipStream_t s) {
+static hipError_t launch_apply_T_t(const DevInst& I, const double* x, double* z, double* y, hipStream_t s,
+                                   const int32_t* gate) {
   dim3 g((I.nbricks + 3) / 4), b(256);
-  hipLaunchKernelGGL((k_OT<D, NRHS>), g, b, 0, s, I, x, z);
-  hipLaunchKernelGGL((k_ET<D, P, NRHS>), g, b, 0, s, I, x, z, y);
+  hipLaunchKernelGGL((k_OT<D, NRHS>), g, b, 0, s, I, x, z, gate);
+  hipLaunchKernelGGL((k_ET<D, P, NRHS>), g, b, 0, s, I, x, z, y, gate);
   return hipGetLastError();
 }
 
-hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* zscratch, double* y, hipStream_t s) {
+hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* zscratch, double* y, hipStream_t s,
+                          const int32_t* gate) {
   if (I.nbricks == 0) return hipSuccess;
 #define CPM_CASE(D, P, R) \
-  if (I.d == D && I.p == P && nrhs == R) return launch_apply_T_t<D, P, R>(I, x, zscratch, y, s);
+  if (I.d == D && I.p == P && nrhs == R) return launch_apply_T_t<D, P, R>(I, x, zscratch, y, s, gate);
   CPM_CASE(3, 3, 1) CPM_CASE(3, 3, 2) CPM_CASE(3, 3, 4)
   CPM_CASE(3, 2, 1) CPM_CASE(3, 2, 2) CPM_CASE(3, 2, 4)
   CPM_CASE(3, 1, 1) CPM_CASE(3, 1, 2) CPM_CASE(3, 1, 4)

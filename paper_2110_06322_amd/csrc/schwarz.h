@@ -74,7 +74,8 @@ struct SchwarzCfg {
 };
 inline size_t schwarz_value_lds(int max_rows, int nrhs, size_t elem) { return 2 * (size_t)max_rows * nrhs * elem; }
 hipError_t launch_schwarz(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
-                          int fp32, int nrhs, const double* r, double* z, hipStream_t s);
+                          int fp32, int nrhs, const double* r, double* z, hipStream_t s,
+                          const int32_t* gate = nullptr);
 
 }  // namespace cpm
 

@@ -144,9 +144,11 @@ __device__ __forceinline__ void sweep(int n, int wave, int nw, int lane, const u
 template <class T, int NRHS>
 __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz(const DevPC* __restrict__ pcs,
                                                             const WorkItem* __restrict__ work, int nwork,
-                                                            const double* __restrict__ rin, double* __restrict__ zout) {
+                                                            const double* __restrict__ rin, double* __restrict__ zout,
+                                                            const int32_t* __restrict__ gate) {
   extern __shared__ double smem_d[];
   if ((int)blockIdx.x >= nwork) return;
+  if (gate && *gate == 0) return;
   const WorkItem wi = work[blockIdx.x];
   const DevPC& P = pcs[wi.inst];
   const DevSub sub = P.subs[wi.idx];
@@ -342,9 +344,11 @@ template <class T, int NRHS, bool SLEEP>
 __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz_v(const DevPC* __restrict__ pcs,
                                                               const WorkItem* __restrict__ work, int nwork,
                                                               const double* __restrict__ rin,
-                                                              double* __restrict__ zout) {
+                                                              double* __restrict__ zout,
+                                                              const int32_t* __restrict__ gate) {
   extern __shared__ double smem_d[];
   if ((int)blockIdx.x >= nwork) return;
+  if (gate && *gate == 0) return;
   const WorkItem wi = work[blockIdx.x];
   const DevPC& P = pcs[wi.inst];
   const DevSub sub = P.subs[wi.idx];
@@ -389,39 +393,39 @@ static hipError_t lds_ok(const void* kern, size_t shm) {
 
 template <class T, int NRHS>
 static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
-                           const double* r, double* z, hipStream_t s) {
+                           const double* r, double* z, hipStream_t s, const int32_t* gate) {
   const int threads = cfg.threads > 0 ? cfg.threads : kSchwarzThreads;
   if (cfg.variant == kSchwarzValueFlags && schwarz_value_lds(max_rows, NRHS, sizeof(T)) <= kSchwarzMaxLds) {
     const size_t shm = schwarz_value_lds(max_rows, NRHS, sizeof(T));
     if (cfg.sleep) {
       hipError_t e = lds_ok((const void*)k_schwarz_v<T, NRHS, true>, shm);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_schwarz_v<T, NRHS, true>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r, z);
+      hipLaunchKernelGGL((k_schwarz_v<T, NRHS, true>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r, z, gate);
     } else {
       hipError_t e = lds_ok((const void*)k_schwarz_v<T, NRHS, false>, shm);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_schwarz_v<T, NRHS, false>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r, z);
+      hipLaunchKernelGGL((k_schwarz_v<T, NRHS, false>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r, z, gate);
     }
     return hipGetLastError();
   }
   const size_t shm = (size_t)max_rows * (NRHS * sizeof(T) + sizeof(int));
   hipError_t e = lds_ok((const void*)k_schwarz<T, NRHS>, shm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_schwarz<T, NRHS>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r, z);
+  hipLaunchKernelGGL((k_schwarz<T, NRHS>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r, z, gate);
   return hipGetLastError();
 }
 
 hipError_t launch_schwarz(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
-                          int fp32, int nrhs, const double* r, double* z, hipStream_t s) {
+                          int fp32, int nrhs, const double* r, double* z, hipStream_t s, const int32_t* gate) {
   if (nwork == 0) return hipSuccess;
   if (fp32) {
-    if (nrhs == 1) return launch_t<float, 1>(cfg, pcs, work, nwork, max_rows, r, z, s);
-    if (nrhs == 2) return launch_t<float, 2>(cfg, pcs, work, nwork, max_rows, r, z, s);
-    if (nrhs == 4) return launch_t<float, 4>(cfg, pcs, work, nwork, max_rows, r, z, s);
+    if (nrhs == 1) return launch_t<float, 1>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
+    if (nrhs == 2) return launch_t<float, 2>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
+    if (nrhs == 4) return launch_t<float, 4>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
   } else {
-    if (nrhs == 1) return launch_t<double, 1>(cfg, pcs, work, nwork, max_rows, r, z, s);
-    if (nrhs == 2) return launch_t<double, 2>(cfg, pcs, work, nwork, max_rows, r, z, s);
-    if (nrhs == 4) return launch_t<double, 4>(cfg, pcs, work, nwork, max_rows, r, z, s);
+    if (nrhs == 1) return launch_t<double, 1>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
+    if (nrhs == 2) return launch_t<double, 2>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
+    if (nrhs == 4) return launch_t<double, 4>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
   }
   return hipErrorInvalidValue;
 }

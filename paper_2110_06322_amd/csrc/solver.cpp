@@ -53,10 +53,20 @@ struct cpm_batch_s {
   DevBuf<int32_t> act, steps, bad, budget, n_active;
   int32_t* h_nact = nullptr;   // pinned [2]
   hipEvent_t ev[2] = {nullptr, nullptr};
+  int ws_gen = 0;               // bumped when the Krylov bases are reallocated
+  // one restart cycle captured as a graph, replayed on a private stream
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  int g_m = -1, g_tr = -1, g_gen = -1;
   ~cpm_batch_s() {
     if (h_nact) (void)hipHostFree(h_nact);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (auto& e : gev)
+      if (e) (void)hipEventDestroy(e);
+    if (gstream) (void)hipStreamDestroy(gstream);
   }
 };
 
@@ -155,6 +165,7 @@ void ensure_workspace(cpm_batch_s& Bt, int m) {
     Bt.hcol.alloc(ns * (m + 1));
     Bt.hv.alloc(ns * (m + 1));
     Bt.m_alloc = m;
+    ++Bt.ws_gen;
   }
   Bt.w.alloc(Ns);
   Bt.r.alloc(Ns);
@@ -188,10 +199,11 @@ GmresState state_of(cpm_batch_s& Bt, int m) {
 }
 
 // y = A x (or A^T x) over all instances of the batch, packed layout
-void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hipStream_t s) {
+void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hipStream_t s,
+                 const int32_t* gate = nullptr) {
   if (!transpose) {
     hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
-                           Bt.nfb, x, y, s),
+                           Bt.nfb, x, y, s, gate),
               "operator apply");
     return;
   }
@@ -199,18 +211,98 @@ void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hi
   for (auto* op : Bt.ops) mx = std::max<int64_t>(mx, op->band->nodes());
   Bt.zT.alloc((size_t)mx * Bt.R);
   for (int i = 0; i < Bt.ni; ++i)
-    hip_check(launch_apply_T(Bt.hinst[i], Bt.R, x, Bt.zT.p, y, s), "transposed operator apply");
+    hip_check(launch_apply_T(Bt.hinst[i], Bt.R, x, Bt.zT.p, y, s, gate), "transposed operator apply");
 }
 
-void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s) {
+void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s, const int32_t* gate = nullptr) {
   if (Bt.any_pc) {
     hipError_t e = launch_schwarz(Bt.pc_cfg, Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.pc_fp32, Bt.R, v, z,
-                                  s);
+                                  s, gate);
     if (e == hipErrorInvalidConfiguration)
       fail(CPM_ERR_ARG, "subdomains too large for the local-memory budget at this nrhs/precision");
     hip_check(e, "preconditioner apply");
   }
   if (!Bt.all_pc) hip_check(vec_copy(Bt.R, v, z, Bt.d_chunks.p, Bt.nchunks, Bt.d_copy_inst.p, s), "copy");
+}
+
+// One Arnoldi step j of every active system (preconditioner, operator, CGS2,
+// Givens, next basis vector). gate: device count of active systems, used by
+// graph-captured cycles to turn the preconditioner and operator into no-ops
+// once every system has stopped.
+// pe / ae (optional): event pairs recorded around the preconditioner and the operator.
+void issue_step(cpm_batch_s& Bt, const GmresState& S, int m, int j, bool tr, hipStream_t st, const int32_t* gate,
+                hipEvent_t* pe = nullptr, hipEvent_t* ae = nullptr) {
+  const int R = Bt.R, ns = Bt.ns;
+  const size_t Ns = (size_t)Bt.Ntot * R;
+  double* Vj = Bt.V.p + (size_t)j * Ns;
+  double* Zj = Bt.any_pc ? Bt.Z.p + (size_t)j * Ns : Vj;
+  if (pe) hip_check(hipEventRecord(pe[0], st), "event");
+  if (Bt.any_pc) batch_precond(Bt, Vj, Zj, st, gate);
+  if (pe) hip_check(hipEventRecord(pe[1], st), "event");
+  if (ae) hip_check(hipEventRecord(ae[0], st), "event");
+  batch_apply(Bt, Zj, Bt.w.p, tr, st, gate);
+  if (ae) hip_check(hipEventRecord(ae[1], st), "event");
+  hip_check(gmres_zero_col(S, ns, st), "zero col");
+  for (int pass = 0; pass < 2; ++pass) {
+    hip_check(vec_dots(R, Bt.V.p, Ns, j + 1, Bt.w.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.part.p, st), "dots");
+    hip_check(vec_reduce(R, Bt.part.p, j + 1, Bt.nchunks, Bt.d_cbeg.p, ns, Bt.hv.p, m + 1, Bt.hcol.p, m + 1, st),
+              "reduce");
+    hip_check(vec_update(R, Bt.V.p, Ns, j + 1, Bt.w.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.hv.p, m + 1,
+                         pass == 1 ? Bt.partn.p : nullptr, st),
+              "update");
+  }
+  hip_check(vec_reduce(R, Bt.partn.p, 1, Bt.nchunks, Bt.d_cbeg.p, ns, Bt.nrm2.p, 1, nullptr, 0, st), "reduce");
+  hip_check(gmres_givens(S, j, ns, st), "givens");
+  hip_check(vec_scale(R, Bt.w.p, Bt.V.p + (size_t)(j + 1) * Ns, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.scale.p, st),
+            "scale");
+}
+
+// end of a cycle: x += Z y, t = A x, r = f - t and |r|^2 per system into nrm2
+void issue_cycle_end(cpm_batch_s& Bt, const GmresState& S, int m, bool tr, hipStream_t st) {
+  const int R = Bt.R, ns = Bt.ns;
+  const size_t Ns = (size_t)Bt.Ntot * R;
+  const double* Zb = Bt.any_pc ? Bt.Z.p : Bt.V.p;
+  hip_check(gmres_hsolve(S, ns, st), "hsolve");
+  hip_check(vec_xupdate(R, Bt.x.p, Zb, Ns, Bt.d_chunks.p, Bt.nchunks, Bt.steps.p, Bt.y.p, m, st), "xupdate");
+  batch_apply(Bt, Bt.x.p, Bt.t.p, tr, st);
+  hip_check(vec_residual(R, Bt.f.p, Bt.t.p, Bt.r.p, Bt.d_chunks.p, Bt.nchunks, Bt.partn.p, st), "norm");
+  hip_check(vec_reduce(R, Bt.partn.p, 1, Bt.nchunks, Bt.d_cbeg.p, ns, Bt.nrm2.p, 1, nullptr, 0, st), "reduce");
+}
+
+// the whole restart cycle as a graph (captured once per batch, restart length and direction)
+void ensure_cycle_graph(cpm_batch_s& Bt, const GmresState& S, int m, bool tr) {
+  if (Bt.gexec && Bt.g_m == m && Bt.g_tr == (int)tr && Bt.g_gen == Bt.ws_gen) return;
+  if (Bt.gexec) {
+    (void)hipGraphExecDestroy(Bt.gexec);
+    Bt.gexec = nullptr;
+  }
+  if (!Bt.gstream) hip_check(hipStreamCreateWithFlags(&Bt.gstream, hipStreamNonBlocking), "graph stream");
+  for (auto& e : Bt.gev)
+    if (!e) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "graph event");
+  const int R = Bt.R, ns = Bt.ns;
+  const size_t Ns = (size_t)Bt.Ntot * R;
+  hipStream_t gs = Bt.gstream;
+  hipGraph_t graph = nullptr;
+  hip_check(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal), "begin capture");
+  try {
+    hip_check(gmres_cycle_init(S, ns, gs), "cycle init");
+    hip_check(vec_scale(R, Bt.r.p, Bt.V.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.scale.p, gs), "v0");
+    for (int j = 0; j < m; ++j) issue_step(Bt, S, m, j, tr, gs, Bt.n_active.p);
+    issue_cycle_end(Bt, S, m, tr, gs);
+  } catch (...) {
+    hipGraph_t dead = nullptr;
+    (void)hipStreamEndCapture(gs, &dead);
+    if (dead) (void)hipGraphDestroy(dead);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(gs, &graph), "end capture");
+  hipError_t e = hipGraphInstantiate(&Bt.gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  hip_check(e, "graph instantiate");
+  Bt.g_m = m;
+  Bt.g_tr = (int)tr;
+  Bt.g_gen = Bt.ws_gen;
+  (void)Ns;
 }
 
 // |v|^2 per system (packed v) into host array
@@ -273,7 +365,13 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
     hip_check(vec_scale(R, Bt.x.p, Bt.x.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.scale.p, st), "zero");
   }
   GmresState S = state_of(Bt, m);
-  const double* Zb = Bt.any_pc ? Bt.Z.p : Bt.V.p;
+  const bool graph = o.use_graph != 0;
+  if (graph) {
+    if (o.profile) fail(CPM_ERR_ARG, "profile cannot be combined with use_graph");
+    if (Bt.any_pc) batch_precond(Bt, Bt.r.p, Bt.w.p, st);   // kernel attributes set outside the capture
+    hip_check(hipStreamSynchronize(st), "sync");
+    ensure_cycle_graph(Bt, S, m, tr);
+  }
   double ms_pc = 0, ms_ap = 0;
   int n_pc = 0, n_ap = 2, n_pc_t = 0, n_ap_t = 0;
   std::vector<hipEvent_t> pev, aev;
@@ -301,48 +399,42 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
     hip_check(hipMemcpyAsync(Bt.tol_in.p, tin.data(), ns * sizeof(double), hipMemcpyHostToDevice, st), "upload");
     hip_check(hipMemcpyAsync(Bt.beta.p, beta.data(), ns * sizeof(double), hipMemcpyHostToDevice, st), "upload");
     hip_check(hipMemsetAsync(Bt.bad.p, 0, ns * sizeof(int32_t), st), "memset");
-    hip_check(gmres_cycle_init(S, ns, st), "cycle init");
-    hip_check(vec_scale(R, Bt.r.p, Bt.V.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.scale.p, st), "v0");
     int jdone = 0;
-    for (int j = 0; j < m; ++j) {
-      double* Vj = Bt.V.p + (size_t)j * Ns;
-      double* Zj = Bt.any_pc ? Bt.Z.p + (size_t)j * Ns : Vj;
-      if (o.profile) hip_check(hipEventRecord(pev[2 * j], st), "event");
-      if (Bt.any_pc) batch_precond(Bt, Vj, Zj, st);
-      if (o.profile) hip_check(hipEventRecord(pev[2 * j + 1], st), "event");
-      if (Bt.any_pc) ++n_pc;
-      if (o.profile) hip_check(hipEventRecord(aev[2 * j], st), "event");
-      batch_apply(Bt, Zj, Bt.w.p, tr, st);
-      if (o.profile) hip_check(hipEventRecord(aev[2 * j + 1], st), "event");
+    if (graph) {
+      // the gate of the captured steps starts at the number of active systems
+      Bt.h_nact[0] = nact;
+      hip_check(hipMemcpyAsync(Bt.n_active.p, &Bt.h_nact[0], sizeof(int32_t), hipMemcpyHostToDevice, st), "upload");
+      hip_check(hipEventRecord(Bt.gev[0], st), "event");
+      hip_check(hipStreamWaitEvent(Bt.gstream, Bt.gev[0], 0), "wait");
+      hip_check(hipGraphLaunch(Bt.gexec, Bt.gstream), "graph launch");
+      hip_check(hipEventRecord(Bt.gev[1], Bt.gstream), "event");
+      hip_check(hipStreamWaitEvent(st, Bt.gev[1], 0), "wait");
+      jdone = m;
+      n_pc += Bt.any_pc ? m : 0;
+      n_ap += m + 1;
+    } else {
+      hip_check(gmres_cycle_init(S, ns, st), "cycle init");
+      hip_check(vec_scale(R, Bt.r.p, Bt.V.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.scale.p, st), "v0");
+      for (int j = 0; j < m; ++j) {
+        issue_step(Bt, S, m, j, tr, st, nullptr, o.profile ? &pev[2 * j] : nullptr,
+                   o.profile ? &aev[2 * j] : nullptr);
+        if (Bt.any_pc) ++n_pc;
+        ++n_ap;
+        hip_check(hipMemcpyAsync(&Bt.h_nact[j & 1], Bt.n_active.p, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "poll");
+        hip_check(hipEventRecord(Bt.ev[j & 1], st), "event");
+        jdone = j + 1;
+        if (j >= 1) {
+          hip_check(hipEventSynchronize(Bt.ev[(j - 1) & 1]), "poll");
+          if (Bt.h_nact[(j - 1) & 1] == 0) break;
+        }
+      }
+      issue_cycle_end(Bt, S, m, tr, st);
       ++n_ap;
-      hip_check(gmres_zero_col(S, ns, st), "zero col");
-      for (int pass = 0; pass < 2; ++pass) {
-        hip_check(vec_dots(R, Bt.V.p, Ns, j + 1, Bt.w.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.part.p, st), "dots");
-        hip_check(vec_reduce(R, Bt.part.p, j + 1, Bt.nchunks, Bt.d_cbeg.p, ns, Bt.hv.p, m + 1, Bt.hcol.p, m + 1, st),
-                  "reduce");
-        hip_check(vec_update(R, Bt.V.p, Ns, j + 1, Bt.w.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.hv.p, m + 1,
-                             pass == 1 ? Bt.partn.p : nullptr, st),
-                  "update");
-      }
-      hip_check(vec_reduce(R, Bt.partn.p, 1, Bt.nchunks, Bt.d_cbeg.p, ns, Bt.nrm2.p, 1, nullptr, 0, st), "reduce");
-      hip_check(gmres_givens(S, j, ns, st), "givens");
-      hip_check(vec_scale(R, Bt.w.p, Bt.V.p + (size_t)(j + 1) * Ns, Bt.d_chunks.p, Bt.nchunks, Bt.act.p,
-                          Bt.scale.p, st),
-                "scale");
-      hip_check(hipMemcpyAsync(&Bt.h_nact[j & 1], Bt.n_active.p, sizeof(int32_t), hipMemcpyDeviceToHost, st), "poll");
-      hip_check(hipEventRecord(Bt.ev[j & 1], st), "event");
-      jdone = j + 1;
-      if (j >= 1) {
-        hip_check(hipEventSynchronize(Bt.ev[(j - 1) & 1]), "poll");
-        if (Bt.h_nact[(j - 1) & 1] == 0) break;
-      }
     }
-    (void)jdone;
-    hip_check(gmres_hsolve(S, ns, st), "hsolve");
-    hip_check(vec_xupdate(R, Bt.x.p, Zb, Ns, Bt.d_chunks.p, Bt.nchunks, Bt.steps.p, Bt.y.p, m, st), "xupdate");
-    batch_apply(Bt, Bt.x.p, Bt.t.p, tr, st);
-    ++n_ap;
-    norms2(Bt, Bt.f.p, Bt.t.p, Bt.r.p, b2, st);  // synchronises
+    b2.resize(ns);
+    hip_check(hipMemcpyAsync(b2.data(), Bt.nrm2.p, ns * sizeof(double), hipMemcpyDeviceToHost, st), "copy");
+    hip_check(hipStreamSynchronize(st), "sync");
     hip_check(hipMemcpy(steps.data(), Bt.steps.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost), "steps");
     hip_check(hipMemcpy(bad.data(), Bt.bad.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost), "bad");
     if (o.profile) {
@@ -428,7 +520,6 @@ cpm_status cpm_solve(const cpm_operator* op, const cpm_precond* pc, const double
   try {
     if (!op || !f || !u || !opts) fail(CPM_ERR_ARG, "null argument");
     if (f == u) fail(CPM_ERR_ARG, "f and u must not alias");
-    if (opts->use_graph) fail(CPM_ERR_ARG, "use_graph is not available for single solves");
     auto& cache = op->solve_cache;
     const int64_t key = pc ? pc->serial : 0;
     if (!cache || cache->R != nrhs || op->solve_cache_key != key) {
@@ -487,7 +578,6 @@ cpm_status cpm_batch_solve(cpm_batch* b, const double* const* f, double* const* 
                            cpm_solve_stats* stats, void* stream) {
   try {
     if (!b || !f || !u || !opts) fail(CPM_ERR_ARG, "null argument");
-    if (opts->use_graph) fail(CPM_ERR_ARG, "use_graph is not available yet");
     return solve_impl(*b, f, u, *opts, stats, (hipStream_t)stream);
   } catch (const Error& e) {
     set_error(e.msg);
