@@ -6,15 +6,23 @@ f = 21 Y with Y a seeded combination of degree-4 spherical harmonics, (O)RAS
 with 64 box subdomains and overlap 2h. One step = one pass of the whole hot
 path over that input: a mixed-precision solve to 1e-8 (FP32 subdomain
 solves inside FP64 FGMRES with iterative refinement), which runs the
-extension + stabilized operator apply, the Schwarz apply and the Krylov core.
-The FP64 solve of the same system is timed beside it.
+extension + stabilized operator apply, the Schwarz apply and the Krylov core,
+followed by a burst of back-to-back operator applies (the metric kernel,
+bracketed by HIP events on its stream). The FP64 solve of the same system is
+timed beside it.
+
+Before timing, the autotuner picks the apply and subdomain-solve kernels
+(no cache file: every run tunes afresh, about a second).
 
 Reported: metric value = operator-apply throughput (active nodes per second)
 of the fused apply kernel, timed with HIP events on the stream the kernel runs
 on inside the timed region; `roofline` for that kernel (algorithmic bytes
 per active node = 8 (x) + 8 (y) + 8 d (1 + N_G/N_A) (closest points));
-`solve` = time to 1e-8, mixed vs FP64; `cpu_baseline` = the CPU oracle on a
-bounded sample (rank 0, N = 1 only).
+`solve` = time to 1e-8, mixed vs FP64; `apply_scaling` = the same apply on
+larger tori (h = 0.005 and 0.0025, the latter about 0.65 GB per apply) with
+four rotating vector copies so repetitions read HBM rather than the 256 MB
+last-level cache; `cpu_baseline` = the CPU oracle on a bounded sample (rank 0,
+N = 1 only).
 """
 from __future__ import annotations
 
@@ -35,11 +43,47 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--apply-reps", type=int, default=500)
+    ap.add_argument("--apply-burst", type=int, default=100, help="operator applies timed per step")
+    ap.add_argument("--tune-cache", default=None, help="JSON cache of the autotuner (default: tune afresh)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--subsolver", default=os.environ.get("CPM_BENCH_SUBSOLVER", "ilu0"))
     ap.add_argument("--pc", default=os.environ.get("CPM_BENCH_PC", "oras"))
+    ap.add_argument("--no-scaling", action="store_true", help="skip the larger-torus apply measurements")
     return ap.parse_args()
+
+
+def apply_scaling(cpm, inputs, torch, dev, hs=(0.005, 0.0025), reps=40, copies=4):
+    """Apply throughput on tori R = 1, r = 0.4 (p = 3), rotating through `copies`
+    input/output pairs (HIP events around `reps` launches per copy)."""
+    out = []
+    for h in hs:
+        band = cpm.Band("torus", (1.0, 0.4), 3, h, 3)
+        op = cpm.Operator(band, 1.0)
+        cpm.autotune(op, None)
+        nA, nG = band.n_active, band.n_ghost
+        xs = [torch.tensor(inputs.normal(10 + i, 0, band.active_keys), dtype=torch.float64, device=dev)
+              for i in range(copies)]
+        ys = [torch.empty_like(xs[0]) for _ in range(copies)]
+        for i in range(copies):
+            op.apply(xs[i], out=ys[i])
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for r in range(reps):
+            for i in range(copies):
+                op.apply(xs[i], out=ys[i])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / (reps * copies)
+        b_alg = 16.0 + 24.0 * (1.0 + nG / nA)
+        out.append({"workload": f"torus R=1 r=0.4 h={h} p=3", "n_active": nA, "ms": round(ms, 4),
+                    "gnodes_per_s": round(nA / (ms * 1e-3) / 1e9, 3),
+                    "hbm_frac": round(b_alg * nA / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "bytes_per_node": round(b_alg, 2)})
+        del xs, ys, op, band
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(seconds_budget=20.0):
@@ -74,7 +118,7 @@ def measured_traffic():
     """HBM bytes per apply launch from the committed counter summary, or None when the
     kernel source changed since the counters were taken."""
     import hashlib
-    f = os.path.join(ROOT, "profiles", "k_apply_tile_sphere_h0.02_counters.md")
+    f = os.path.join(ROOT, "profiles", "k_apply_pipe_sphere_h0.02_counters.md")
     src = os.path.join(ROOT, "paper_2110_06322_amd", "csrc", "apply.hip")
     if not os.path.exists(f):
         return None
@@ -118,41 +162,43 @@ def main():
     pc64 = cpm.Precond(op, kind=a.pc, n_parts=64, overlap=2.0, precision="fp64", subsolver=a.subsolver)
     t_pc64 = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
+    tune32 = cpm.autotune(op, pc32, cache=a.tune_cache)
+    tune64 = cpm.autotune(op, pc64, cache=a.tune_cache)
     u = torch.zeros_like(f)
-    x = torch.tensor(inputs.normal(1, 0, band.active_keys), dtype=torch.float64, device=dev)
-    y = torch.empty_like(x)
+    y = torch.empty_like(f)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
 
-    def step(mode, pc, profile=False):
+    def step(mode, pc, k=None):
         u.zero_()
-        _, st = cpm.solve(op, f, pc=pc, u=u, rtol=1e-8, mode=mode, max_it=20000, profile=profile)
+        _, st = cpm.solve(op, f, pc=pc, u=u, rtol=1e-8, mode=mode, max_it=20000)
+        # burst of operator applies on the solution (events on the apply's stream)
+        if k is not None:
+            ev[k][0].record(stream)
+        for _ in range(a.apply_burst):
+            op.apply(u, out=y, stream=stream)
+        if k is not None:
+            ev[k][1].record(stream)
         return st
 
     for _ in range(a.warmup):
-        step("mixed", pc32, True)
+        step("mixed", pc32)
     torch.cuda.synchronize()
-    # ---- timed region: K steps; the apply and Schwarz kernels are timed with HIP
-    # events on the solver's stream inside each step
+    # ---- timed region: K steps
     t_start = time.perf_counter()
-    stats = [step("mixed", pc32, True) for _ in range(a.steps)]
+    stats = [step("mixed", pc32, k) for k in range(a.steps)]
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_step = t_total * 1e3 / a.steps
     solve_ms = float(np.mean([s["ms_total"] for s in stats]))
-    ms_apply = float(sum(s["ms_apply"] for s in stats) / max(1, sum(s["n_apply"] for s in stats)))
-    ms_pc = float(sum(s["ms_precond"] for s in stats) / max(1, sum(s["n_precond"] for s in stats)))
+    ms_apply = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev])) / a.apply_burst
     # FP64 solve of the same system (comparison leg, after the timed steps)
     st64 = [step("fp64", pc64) for _ in range(max(1, min(3, a.steps)))]
     solve64_ms = float(np.mean([s["ms_total"] for s in st64]))
-    # standalone apply (outside the timed steps): many back-to-back launches
-    for _ in range(10):
-        op.apply(x, out=y)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(a.apply_reps):
-        op.apply(x, out=y)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_apply_alone = e0.elapsed_time(e1) / a.apply_reps
+    # per-launch kernel times inside a solve (profiled with events; outside the timed steps)
+    u.zero_()
+    _, stp = cpm.solve(op, f, pc=pc32, u=u, rtol=1e-8, mode="mixed", max_it=20000, profile=True)
+    ms_apply_in_solve = stp["ms_apply"] / max(1, stp["n_apply"])
+    ms_pc = stp["ms_precond"] / max(1, stp["n_precond"])
     gnodes = nA / (ms_apply * 1e-3) / 1e9
     b_alg = 16.0 + 8.0 * d * (1.0 + nG / nA)
     achieved = b_alg * nA / (ms_apply * 1e-3) / 1e9
@@ -161,6 +207,9 @@ def main():
     # row pointers (2 x 8 B), input index, output index and FP64 r/z per local row
     b_pc = pci.total_nnz * (4 + 2) + pci.total_rows * (8 + 8 + 4 + 4 + 8 + 8) + 4 * pci.total_rows
     traffic = measured_traffic()
+    apply_kernel = "k_apply_pipe<3,3>" if tune32["apply_variant"] == 0 else "k_apply_tile<3,3,1>"
+    pc_kernel = ("k_schwarz_v<float,1>" if tune32["schwarz_variant"] == 1 else "k_schwarz<float,1>")
+    scaling = None if a.no_scaling else apply_scaling(cpm, inputs, torch, dev)
     out = {
         "metric": "CPM apply Gnodes/s (%HBM peak); ORAS-GMRES time to 1e-8, mixed vs FP64",
         "value": round(gnodes, 3),
@@ -179,7 +228,7 @@ def main():
                    "n_active": nA, "n_ghost": nG, "n_band": band.n_band},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_apply_tile<3,3,1>", "bytes_per_node": round(b_alg, 2)},
+                     "kernel": apply_kernel, "bytes_per_node": round(b_alg, 2)},
         "solve": {"mixed_ms": round(solve_ms, 3), "fp64_ms": round(solve64_ms, 3),
                   "speedup_mixed": round(solve64_ms / solve_ms, 3) if solve_ms > 0 else None,
                   "iters_mixed": int(stats[-1]["iterations"]), "iters_fp64": int(st64[-1]["iterations"]),
@@ -188,10 +237,11 @@ def main():
         "setup_s": {"band_and_operator": round(t_band, 3), "precond_fp32": round(t_pc32, 3),
                     "precond_fp64": round(t_pc64, 3)},
         "apply_ms": round(ms_apply, 5),
-        "apply_standalone": {"ms": round(ms_apply_alone, 5),
-                             "gnodes_per_s": round(nA / (ms_apply_alone * 1e-3) / 1e9, 3),
-                             "frac": round(b_alg * nA / (ms_apply_alone * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-        "roofline_precond": {"bound": "hbm", "kernel": "k_schwarz<float,1>", "ms": round(ms_pc, 5),
+        "apply_in_solve": {"ms_per_launch": round(ms_apply_in_solve, 5),
+                           "note": "event pair around each launch inside a solve; includes dispatch latency"},
+        "tuning": {"fp32": tune32, "fp64": tune64},
+        "apply_scaling": scaling,
+        "roofline_precond": {"bound": "hbm", "kernel": pc_kernel, "ms": round(ms_pc, 5),
                              "achieved": round(b_pc / (ms_pc * 1e-3) / 1e9, 1) if ms_pc > 0 else None,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(b_pc / (ms_pc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms_pc > 0 else None,

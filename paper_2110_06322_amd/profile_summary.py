@@ -14,11 +14,12 @@ import sys
 
 
 def stats(db):
+    """Per-kernel totals (rocprofv3's top_kernels view reports microseconds)."""
     con = sqlite3.connect(db)
     rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
-    print(f"{'calls':>7} {'total_us':>12} {'avg_us':>10} {'pct':>6}  kernel")
+    print(f"{'calls':>7} {'total_ms':>12} {'avg_us':>10} {'pct':>6}  kernel")
     for name, calls, tot, avg, pct in rows:
-        print(f"{calls:7d} {tot / 1e3:12.1f} {avg / 1e3:10.3f} {pct:6.2f}  {name}")
+        print(f"{calls:7d} {tot / 1e3:12.3f} {avg:10.3f} {pct:6.2f}  {name}")
 
 
 def counter(db, pattern):
