@@ -50,6 +50,7 @@ struct DevPC {
   const DevSub* subs;
   const int32_t* in_idx;        // global node feeding input slot q
   const int32_t* out_idx;       // global node of solution slot q, bit 31 set when owned
+  const int32_t* gL;            // global node of the row at each forward-sweep position
   const uint64_t* recL;         // per subdomain (at row_off): forward sweep records
   const uint64_t* recU;         //   backward sweep records
   const uint16_t* lcol;
@@ -73,8 +74,9 @@ struct SchwarzCfg {
   int sleep = 1;        // back off with s_sleep while waiting on a dependency
 };
 inline size_t schwarz_value_lds(int max_rows, int nrhs, size_t elem) { return 2 * (size_t)max_rows * nrhs * elem; }
+constexpr int kSchwarzValueMaxLen = 128;   // longest factor row the values-as-flags kernel takes
 hipError_t launch_schwarz(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
-                          int fp32, int nrhs, const double* r, double* z, hipStream_t s,
+                          int max_len, int fp32, int nrhs, const double* r, double* z, hipStream_t s,
                           const int32_t* gate = nullptr);
 
 }  // namespace cpm
@@ -86,7 +88,7 @@ struct cpm_precond_s {
   cpm::DevPC P{};
   cpm::DevBuf<cpm::DevPC> d_pc;
   cpm::DevBuf<cpm::DevSub> d_subs;
-  cpm::DevBuf<int32_t> d_in, d_out, d_err;
+  cpm::DevBuf<int32_t> d_in, d_out, d_err, d_gL;
   cpm::DevBuf<uint64_t> d_recL, d_recU;
   cpm::DevBuf<uint16_t> d_lcol, d_ucol;
   cpm::DevBuf<char> d_lval, d_uval, d_dinv;
@@ -94,6 +96,6 @@ struct cpm_precond_s {
   std::vector<cpm::WorkItem> h_work;
   int64_t serial = 0;           // identifies this preconditioner in solver caches
   cpm::SchwarzCfg cfg;          // kernel configuration (tunable)
-  int max_rows = 0, max_levels = 0;
+  int max_rows = 0, max_levels = 0, max_len = 0;
   int64_t total_rows = 0, total_nnz = 0;
 };

@@ -233,8 +233,13 @@ __device__ __forceinline__ T wait_value(T* p, int32_t* err) {
   Bits* bp = reinterpret_cast<Bits*>(p);
   int spins = 0;
   for (;;) {
-    const Bits b = __hip_atomic_load(bp, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (b != Sentinel<T>::kBits) return bits_to<T>(b);
+    const Bits b = __hip_atomic_load(bp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (b != Sentinel<T>::kBits) {
+      // acquire limited to LDS: global loads in flight (the next rows' prefetch)
+      // need not complete first
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+      return bits_to<T>(b);
+    }
     if (SLEEP) __builtin_amdgcn_s_sleep(1);
     if (++spins > kSpinLimit) {
       __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -251,92 +256,108 @@ __device__ __forceinline__ void dep_accumulate(const T* src, int k, T v, T* acc,
   for (int r = 1; r < NRHS; ++r) acc[r] += v * src[(size_t)k * NRHS + r];
 }
 
+// global-memory view of a pointer: loads through it are global (vector memory
+// counter only), not flat loads that also hold the LDS counter the sweeps wait on
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
+// what one wavefront holds for one row: record, entries (two per lane) and its
+// own value (forward: r_q; backward: 1/u_qq)
+template <class T, int NRHS>
+struct SweepRow {
+  uint64_t rec;
+  int k0, k1;
+  T v0, v1;
+  T own[NRHS];
+  T dq;
+};
+
 // One sweep of the value-as-flag variant. Forward (BACKWARD = false): dst_q =
-// r_q - sum_k l_qk dst_k, r_q read from HBM through the input index. Backward:
-// dst_q = (y_q - sum_k u_qk dst_k) * dinv_q with y from the forward array.
+// r_q - sum_k l_qk dst_k, r_q read from HBM through the schedule-ordered input
+// index. Backward: dst_q = (y_q - sum_k u_qk dst_k) * dinv_q with y from the
+// forward array. Every load of the loop is unconditional (indices clamped into
+// the padded arrays) and two row buffers are used in turn, so the next row's
+// entries and right-hand side stay in flight while the current row waits for
+// its dependencies. Rows have at most 128 entries (two per lane).
 template <class T, int NRHS, bool BACKWARD, bool SLEEP>
-__device__ __forceinline__ void sweep_v(int n, int wave, int nw, int lane, const uint64_t* __restrict__ rec,
-                                        const uint16_t* __restrict__ col, const T* __restrict__ val,
-                                        const T* __restrict__ dinv, const int32_t* __restrict__ in_idx,
-                                        const double* __restrict__ rb, const T* yv, T* dst, int32_t* err) {
+__device__ __forceinline__ void sweep_v(int n, int wave, int nw, int lane, const uint64_t* __restrict__ rec_,
+                                        const uint16_t* __restrict__ col_, const T* __restrict__ val_,
+                                        const T* __restrict__ dinv_, const int32_t* __restrict__ gsched_,
+                                        const double* __restrict__ rb_, const T* yv, T* dst, int32_t* err) {
+  const auto rec = gmem(rec_);
+  const auto col = gmem(col_);
+  const auto val = gmem(val_);
+  const auto dinv = gmem(dinv_);
+  const auto gsched = gmem(gsched_);
+  const auto rb = gmem(rb_);
   int pos = wave;
   if (pos >= n) return;
-  uint64_t r0 = rec[pos];
-  uint64_t r1 = pos + nw < n ? rec[pos + nw] : 0ull;
-  int k = -1;
-  T v = (T)0, dq = (T)0;
-  T own[NRHS];
-  {
-    const int q = (int)(r0 >> 48);
-    const int len = (int)((r0 >> 32) & 0xffff);
-    const int64_t off = (int64_t)(r0 & 0xffffffffull);
-    if (lane < len) { k = col[off + lane]; v = val[off + lane]; }
-    if (lane == 63) {
-      if (BACKWARD) {
-        dq = dinv[q];
-      } else {
-        const int64_t g = in_idx[q];
+  const int last = n - 1;
+  auto slot = [&](uint64_t r, int l) {
+    const int len = (int)((r >> 32) & 0xffff);
+    return (int64_t)(r & 0xffffffffull) + min(l, max(len - 1, 0));
+  };
+  auto fetch = [&](SweepRow<T, NRHS>& D, uint64_t r, int g) {
+    D.rec = r;
+    D.k0 = col[slot(r, lane)];
+    D.k1 = col[slot(r, lane + 64)];
+    D.v0 = val[slot(r, lane)];
+    D.v1 = val[slot(r, lane + 64)];
+    if (BACKWARD) {
+      D.dq = dinv[(int)(r >> 48)];
+    } else {
+      D.dq = (T)0;
 #pragma unroll
-        for (int r = 0; r < NRHS; ++r) own[r] = (T)rb[g * NRHS + r];
-      }
+      for (int q = 0; q < NRHS; ++q) D.own[q] = (T)rb[(int64_t)g * NRHS + q];
     }
-  }
-  for (;;) {
-    const int q = (int)(r0 >> 48);
-    const int len = (int)((r0 >> 32) & 0xffff);
-    const int64_t off = (int64_t)(r0 & 0xffffffffull);
-    const bool has1 = pos + nw < n;
-    const uint64_t r2 = pos + 2 * nw < n ? rec[pos + 2 * nw] : 0ull;
-    int kn = -1;
-    T vn = (T)0, dn = (T)0;
-    T ownn[NRHS];
-    if (has1) {
-      const int q1 = (int)(r1 >> 48);
-      const int len1 = (int)((r1 >> 32) & 0xffff);
-      const int64_t off1 = (int64_t)(r1 & 0xffffffffull);
-      if (lane < len1) { kn = col[off1 + lane]; vn = val[off1 + lane]; }
-      if (lane == 63) {
-        if (BACKWARD) {
-          dn = dinv[q1];
-        } else {
-          const int64_t g = in_idx[q1];
+  };
+  auto solve_row = [&](SweepRow<T, NRHS>& D) {
+    const int q = (int)(D.rec >> 48);
+    const int len = (int)((D.rec >> 32) & 0xffff);
+    if (BACKWARD) {
 #pragma unroll
-          for (int r = 0; r < NRHS; ++r) ownn[r] = (T)rb[g * NRHS + r];
-        }
-      }
+      for (int r = 0; r < NRHS; ++r) D.own[r] = yv[(size_t)q * NRHS + r];   // y_q, complete before this sweep
     }
     T acc[NRHS];
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) acc[r] = (T)0;
-    if (k >= 0) dep_accumulate<T, NRHS, SLEEP>(dst, k, v, acc, err);
-    for (int t = 64 + lane; t < len; t += 64) {   // rows longer than a wavefront
-      dep_accumulate<T, NRHS, SLEEP>(dst, col[off + t], val[off + t], acc, err);
-    }
+    if (lane < len) dep_accumulate<T, NRHS, SLEEP>(dst, D.k0, D.v0, acc, err);
+    if (lane + 64 < len) dep_accumulate<T, NRHS, SLEEP>(dst, D.k1, D.v1, acc, err);
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) acc[r] = wave_sum_to_63(acc[r]);
     if (lane == 63) {
       T out[NRHS];
-      if (BACKWARD) {
 #pragma unroll
-        for (int r = 0; r < NRHS; ++r) out[r] = (yv[(size_t)q * NRHS + r] - acc[r]) * dq;
-      } else {
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r) out[r] = own[r] - acc[r];
-      }
+      for (int r = 0; r < NRHS; ++r) out[r] = BACKWARD ? (D.own[r] - acc[r]) * D.dq : D.own[r] - acc[r];
 #pragma unroll
       for (int r = 1; r < NRHS; ++r) dst[(size_t)q * NRHS + r] = out[r];
+      // release limited to LDS: global loads in flight need not complete first;
+      // readers pair it with an LDS-only acquire
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
       __hip_atomic_store(reinterpret_cast<typename Sentinel<T>::Bits*>(dst + (size_t)q * NRHS), to_bits<T>(out[0]),
-                         __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    if (!has1) break;
+  };
+  // records and input indices two rows ahead, entries and own values one row ahead
+  SweepRow<T, NRHS> A, B;
+  uint64_t rn = rec[min(pos + nw, last)];
+  int gn = BACKWARD ? 0 : gsched[min(pos + nw, last)];
+  fetch(A, rec[pos], BACKWARD ? 0 : gsched[pos]);
+  for (;;) {
+    const uint64_t rnn = rec[min(pos + 2 * nw, last)];
+    const int gnn = BACKWARD ? 0 : gsched[min(pos + 2 * nw, last)];
+    fetch(B, rn, gn);
+    solve_row(A);
+    if (pos + nw >= n) break;
     pos += nw;
-    r0 = r1;
-    r1 = r2;
-    k = kn;
-    v = vn;
-    dq = dn;
-#pragma unroll
-    for (int r = 0; r < NRHS; ++r) own[r] = ownn[r];
+    rn = rec[min(pos + 2 * nw, last)];
+    gn = BACKWARD ? 0 : gsched[min(pos + 2 * nw, last)];
+    fetch(A, rnn, gnn);
+    solve_row(B);
+    if (pos + nw >= n) break;
+    pos += nw;
   }
 }
 
@@ -366,8 +387,8 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz_v(const DevPC* __re
   const T sent = bits_to<T>(Sentinel<T>::kBits);
   for (int q = tid; q < 2 * n * NRHS; q += blockDim.x) yv[q] = sent;
   __syncthreads();
-  sweep_v<T, NRHS, false, SLEEP>(n, wave, nw, lane, P.recL + sub.row_off, P.lcol + sub.lbase, lv, nullptr, in_idx,
-                                 rb, nullptr, yv, P.error_flag);
+  sweep_v<T, NRHS, false, SLEEP>(n, wave, nw, lane, P.recL + sub.row_off, P.lcol + sub.lbase, lv, nullptr,
+                                 P.gL + sub.row_off, rb, nullptr, yv, P.error_flag);
   __syncthreads();
   sweep_v<T, NRHS, true, SLEEP>(n, wave, nw, lane, P.recU + sub.row_off, P.ucol + sub.ubase, uv, di, nullptr,
                                 nullptr, yv, zv, P.error_flag);
@@ -384,8 +405,9 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz_v(const DevPC* __re
 
 static hipError_t lds_ok(const void* kern, size_t shm) {
   int dev = 0, lim = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return hipErrorInvalidDevice;
   if (shm > (size_t)lim) return hipErrorInvalidConfiguration;
   if (shm > 65536) return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   return hipSuccess;
@@ -393,9 +415,10 @@ static hipError_t lds_ok(const void* kern, size_t shm) {
 
 template <class T, int NRHS>
 static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
-                           const double* r, double* z, hipStream_t s, const int32_t* gate) {
+                           int max_len, const double* r, double* z, hipStream_t s, const int32_t* gate) {
   const int threads = cfg.threads > 0 ? cfg.threads : kSchwarzThreads;
-  if (cfg.variant == kSchwarzValueFlags && schwarz_value_lds(max_rows, NRHS, sizeof(T)) <= kSchwarzMaxLds) {
+  if (cfg.variant == kSchwarzValueFlags && max_len <= kSchwarzValueMaxLen &&
+      schwarz_value_lds(max_rows, NRHS, sizeof(T)) <= kSchwarzMaxLds) {
     const size_t shm = schwarz_value_lds(max_rows, NRHS, sizeof(T));
     if (cfg.sleep) {
       hipError_t e = lds_ok((const void*)k_schwarz_v<T, NRHS, true>, shm);
@@ -416,16 +439,17 @@ static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkIt
 }
 
 hipError_t launch_schwarz(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
-                          int fp32, int nrhs, const double* r, double* z, hipStream_t s, const int32_t* gate) {
+                          int max_len, int fp32, int nrhs, const double* r, double* z, hipStream_t s,
+                          const int32_t* gate) {
   if (nwork == 0) return hipSuccess;
   if (fp32) {
-    if (nrhs == 1) return launch_t<float, 1>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
-    if (nrhs == 2) return launch_t<float, 2>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
-    if (nrhs == 4) return launch_t<float, 4>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
+    if (nrhs == 1) return launch_t<float, 1>(cfg, pcs, work, nwork, max_rows, max_len, r, z, s, gate);
+    if (nrhs == 2) return launch_t<float, 2>(cfg, pcs, work, nwork, max_rows, max_len, r, z, s, gate);
+    if (nrhs == 4) return launch_t<float, 4>(cfg, pcs, work, nwork, max_rows, max_len, r, z, s, gate);
   } else {
-    if (nrhs == 1) return launch_t<double, 1>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
-    if (nrhs == 2) return launch_t<double, 2>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
-    if (nrhs == 4) return launch_t<double, 4>(cfg, pcs, work, nwork, max_rows, r, z, s, gate);
+    if (nrhs == 1) return launch_t<double, 1>(cfg, pcs, work, nwork, max_rows, max_len, r, z, s, gate);
+    if (nrhs == 2) return launch_t<double, 2>(cfg, pcs, work, nwork, max_rows, max_len, r, z, s, gate);
+    if (nrhs == 4) return launch_t<double, 4>(cfg, pcs, work, nwork, max_rows, max_len, r, z, s, gate);
   }
   return hipErrorInvalidValue;
 }

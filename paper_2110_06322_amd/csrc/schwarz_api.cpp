@@ -50,7 +50,7 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     SchwarzHost& H = pc->host;
     const int np = H.nparts;
     std::vector<DevSub> subs(np);
-    std::vector<int32_t> in_idx, out_idx;
+    std::vector<int32_t> in_idx, out_idx, gL;
     std::vector<uint64_t> recL, recU;
     std::vector<uint16_t> lcol, ucol;
     std::vector<double> lval, uval;
@@ -81,6 +81,8 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
           const int row = sched[t];
           const int64_t b = ptr[row], e = ptr[row + 1];
           if (e - b > 65535) fail(CPM_ERR_ARG, "row too long for the sweep record");
+          pc->max_len = std::max<int>(pc->max_len, (int)(e - b));
+          if (lower) gL.push_back(s.rows[s.perm[row]]);
           const uint64_t off = (uint64_t)((int64_t)oc.size() - base);
           if (off > 0xffffffffull) fail(CPM_ERR_ARG, "subdomain factors too large");
           rec.push_back(((uint64_t)row << 48) | ((uint64_t)(e - b) << 32) | off);
@@ -94,8 +96,14 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
       pc->total_nnz += s.nnz;
     }
     pc->total_rows = row_off;
+    // one zero entry past the end: the sweeps clamp their loads into the arrays
+    lcol.push_back(0);
+    ucol.push_back(0);
+    lval.push_back(0.0);
+    uval.push_back(0.0);
     pc->d_subs.upload(subs);
     pc->d_in.upload(in_idx);
+    pc->d_gL.upload(gL);
     pc->d_out.upload(out_idx);
     pc->d_recL.upload(recL);
     pc->d_recU.upload(recU);
@@ -127,6 +135,7 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     P.subs = pc->d_subs.p;
     P.in_idx = pc->d_in.p;
     P.out_idx = pc->d_out.p;
+    P.gL = pc->d_gL.p;
     P.recL = pc->d_recL.p;
     P.recU = pc->d_recU.p;
     P.lcol = pc->d_lcol.p;
@@ -187,7 +196,8 @@ cpm_status cpm_precond_export_partition(const cpm_precond* pc, int32_t* owner, i
 namespace cpm {
 // z = M^-1 r for one preconditioner (also used by the solver)
 hipError_t precond_apply_raw(const cpm_precond_s* pc, const double* r, double* z, int nrhs, hipStream_t s) {
-  return launch_schwarz(pc->cfg, pc->d_pc.p, pc->d_work.p, pc->host.nparts, pc->max_rows, pc->P.fp32, nrhs, r, z, s);
+  return launch_schwarz(pc->cfg, pc->d_pc.p, pc->d_work.p, pc->host.nparts, pc->max_rows, pc->max_len, pc->P.fp32,
+                        nrhs, r, z, s);
 }
 // error flag of the bounded waits (0 = fine); resets it
 int precond_take_error(const cpm_precond_s* pc) {

@@ -36,7 +36,7 @@ struct cpm_batch_s {
   SchwarzCfg pc_cfg;
   // preconditioners
   bool any_pc = false, all_pc = true;
-  int pc_fp32 = 0, pc_transpose = -1, max_rows = 0, npcwork = 0;
+  int pc_fp32 = 0, pc_transpose = -1, max_rows = 0, max_len = 0, npcwork = 0;
   DevBuf<DevPC> d_pcs;
   DevBuf<WorkItem> d_pcwork;
   DevBuf<int32_t> d_copy_inst;
@@ -114,6 +114,7 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
       hpcs[i] = P;
       for (const WorkItem& wi : pc->h_work) pcw.push_back(WorkItem{i, wi.idx});
       Bt.max_rows = std::max(Bt.max_rows, pc->max_rows);
+      Bt.max_len = std::max(Bt.max_len, pc->max_len);
     } else {
       Bt.all_pc = false;
       copy_inst[i] = 1;
@@ -216,8 +217,8 @@ void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hi
 
 void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s, const int32_t* gate = nullptr) {
   if (Bt.any_pc) {
-    hipError_t e = launch_schwarz(Bt.pc_cfg, Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.pc_fp32, Bt.R, v, z,
-                                  s, gate);
+    hipError_t e = launch_schwarz(Bt.pc_cfg, Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.max_len,
+                                  Bt.pc_fp32, Bt.R, v, z, s, gate);
     if (e == hipErrorInvalidConfiguration)
       fail(CPM_ERR_ARG, "subdomains too large for the local-memory budget at this nrhs/precision");
     hip_check(e, "preconditioner apply");
