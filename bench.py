@@ -49,7 +49,64 @@ def _args():
     ap.add_argument("--subsolver", default=os.environ.get("CPM_BENCH_SUBSOLVER", "ilu0"))
     ap.add_argument("--pc", default=os.environ.get("CPM_BENCH_PC", "oras"))
     ap.add_argument("--no-scaling", action="store_true", help="skip the larger-torus apply measurements")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time one batched solve of the 48-surface workload (4 RHS each; adds minutes of setup)")
+    ap.add_argument("--gray-scott", type=int, default=0, metavar="STEPS",
+                    help="also run STEPS semi-implicit Gray-Scott steps on the torus h=0.005 (1024 subdomains)")
     return ap.parse_args()
+
+
+def batched_leg(cpm, workloads, torch):
+    """One mixed-precision batched solve to 1e-8 of the 48-surface workload (192 systems)."""
+    t0 = time.perf_counter()
+    print("batched: building 48 instances", file=sys.stderr, flush=True)
+    insts = workloads.batched()
+    t_setup = time.perf_counter() - t0
+    print(f"batched: setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+    bt = cpm.Batch([i.op for i in insts], [i.pc for i in insts], [4] * len(insts))
+    tune = bt.autotune()
+    fs = [i.f for i in insts]
+    bt.solve(fs, rtol=1e-8, mode="mixed", max_it=20000)   # warm-up (workspace, caches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    us, stats = bt.solve(fs, rtol=1e-8, mode="mixed", max_it=20000)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    its = [s["iterations"] for s in stats]
+    return {"workload": "48 surfaces (16 spheres, 16 ellipsoids, 16 tori), h cyclic 0.04/0.02/0.01, p=3, "
+                        "4 N(0,1) RHS each, FP32 ORAS 32-512 boxes, FP64 FGMRES-IR to 1e-8",
+            "systems": len(stats), "n_active_total": int(sum(i.band.n_active for i in insts)),
+            "solve_ms": round(ms, 2), "iterations_max": int(max(its)), "iterations_mean": round(float(sum(its)) / len(its), 1),
+            "converged": bool(all(s["converged"] for s in stats)), "setup_s": round(t_setup, 2),
+            "tuning": tune}
+
+
+def gray_scott_leg(cpm, torch, steps):
+    """Semi-implicit Gray-Scott on the torus R=1 r=0.4 h=0.005: steps of two batched shifted solves."""
+    from paper_2110_06322_amd import gray_scott
+    t0 = time.perf_counter()
+    band = cpm.Band("torus", (1.0, 0.4), 3, 0.005, 3)
+    gs = gray_scott.GrayScott(band, n_parts=1024, mode="mixed", precision="fp32", rtol=1e-8, tune=True)
+    t_setup = time.perf_counter() - t0
+    print(f"gray-scott: setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+    gs.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for k in range(steps - 1):
+        st = gs.step()
+        its.append(max(s["iterations"] for s in st))
+        if k % 50 == 0:
+            print(f"gray-scott: step {k + 1}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    u = gs.u
+    return {"workload": "Gray-Scott torus R=1 r=0.4 h=0.005 p=3, mu=(2e-5,1e-5) F=0.04 k=0.06 dt=1, "
+                        "FP32 ORAS 1024 boxes, FP64 FGMRES-IR to 1e-8, warm starts",
+            "n_active": band.n_active, "steps": steps, "ms_per_step": round(el * 1e3 / max(1, steps - 1), 3),
+            "iterations_max": int(max(its) if its else 0), "setup_s": round(t_setup, 2),
+            "u_min": float(u.min()), "u_max": float(u.max()), "finite": bool(torch.isfinite(u).all()),
+            "tuning": gs.tuning}
 
 
 def apply_scaling(cpm, inputs, torch, dev, hs=(0.005, 0.0025), reps=40, copies=4):
@@ -247,6 +304,11 @@ def main():
                              "frac": round(b_pc / (ms_pc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms_pc > 0 else None,
                              "bytes_per_launch": int(b_pc), "max_levels": int(pci.max_levels)},
     }
+    if a.batched:
+        from paper_2110_06322_amd import workloads
+        out["batched"] = batched_leg(cpm, workloads, torch)
+    if a.gray_scott > 0:
+        out["gray_scott"] = gray_scott_leg(cpm, torch, a.gray_scott)
     if not a.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

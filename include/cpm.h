@@ -295,6 +295,14 @@ typedef struct {
 cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const char* cache_path,
                         int32_t force, void* stream, cpm_tune_result* out);
 
+/* The same for a batch: times the batch's shared apply and subdomain-solve
+ * launches over all its instances (so concurrency between subdomains of
+ * different instances counts) and sets the batch's own choices; classes are
+ * keyed by instance count and total size as well. Allocates the batch's
+ * workspace if needed; synchronizes the stream. */
+cpm_status cpm_batch_autotune(cpm_batch* batch, const char* cache_path, int32_t force, void* stream,
+                              cpm_tune_result* out);
+
 /* ---------------------------------------------------------------------
  * Reaction-diffusion (Sec. 1, eq. rdsys; Sec. 4.1.5, eq. grayscott):
  * IMEX-Euler right-hand sides of the Gray-Scott system, the reaction taken

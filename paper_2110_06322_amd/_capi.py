@@ -98,6 +98,7 @@ SIGNATURES = [
     ("cpm_batch_apply", I32, [P, C.POINTER(P), C.POINTER(P), P]),
     ("cpm_batch_destroy", None, [P]),
     ("cpm_autotune", I32, [P, P, I32, C.c_char_p, I32, P, C.POINTER(TuneResult)]),
+    ("cpm_batch_autotune", I32, [P, C.c_char_p, I32, P, C.POINTER(TuneResult)]),
     ("cpm_gray_scott_rhs", I32, [I64, P, P, D, D, D, D, D, P, P, P]),
     ("cpm_last_error", C.c_char_p, []),
     ("cpm_version", I32, []),

@@ -295,6 +295,13 @@ class Batch:
             check(code)
         return us, [_stats_dict(s) for s in st]
 
+    def autotune(self, cache: str | None = None, force: bool = False, stream=None) -> dict:
+        """Pick the batch's apply and subdomain-solve kernels by timing them on the whole batch."""
+        r = _capi.TuneResult()
+        path = None if cache is None else str(cache).encode()
+        check(lib().cpm_batch_autotune(self._h, path, int(bool(force)), _stream(stream), C.byref(r)))
+        return {f: getattr(r, f) for f, _ in _capi.TuneResult._fields_}
+
     def apply(self, xs, ys=None, stream=None):
         torch = _torch()
         ys = ys or [torch.empty_like(x) for x in xs]

@@ -29,6 +29,18 @@ namespace cpm {
 // ------------------------------------------------------------- helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// true when the gate says instance `inst` has nothing to do
+__device__ __forceinline__ bool gate_skip(const Gate& g, int inst) {
+  if (g.count && *g.count == 0) return true;
+  if (g.act) {
+    int any = 0;
+    for (int r = 0; r < g.nrhs; ++r) any |= g.act[inst * g.nrhs + r];
+    return any == 0;
+  }
+  return false;
+}
+
+
 // number of set bits of m strictly below this lane
 __device__ __forceinline__ int mbcnt64(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
@@ -274,14 +286,14 @@ template <int D, int P, int NRHS>
 __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ insts,
                                                     const WorkItem* __restrict__ work, int nwork, int ucap,
                                                     const double* __restrict__ x, double* __restrict__ y,
-                                                    const int32_t* __restrict__ gate) {
+                                                    Gate gate) {
   extern __shared__ double smem[];
-  if (gate && *gate == 0) return;
   constexpr int NT = 512, NW = NT / 64;
   constexpr int E = kEdge<D>;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   if (w >= nwork) return;
   const WorkItem wi = work[w];
+  if (gate_skip(gate, wi.inst)) return;
   const DevInst& I = insts[wi.inst];
   const DevTile& tile = I.tiles[wi.idx];
   const int s0 = tile.fstr[0], s1 = tile.fstr[1], fbase = tile.fbase;
@@ -380,11 +392,16 @@ struct PipeRec {
 
 template <int D>
 __device__ __forceinline__ PipeRec pipe_rec(const DevInst* __restrict__ insts, const WorkItem* __restrict__ work,
-                                            int w, int wave) {
+                                            int w, int wave, const Gate& gate) {
   const WorkItem wi = work[w];
   const DevTile& T = insts[wi.inst].tiles[wi.idx];
   PipeRec R;
   R.inst = wi.inst;
+  if (gate.act && gate_skip(gate, wi.inst)) {   // an instance whose systems have stopped: an empty tile
+    R.s0 = R.s1 = R.fbase = R.fb_off = R.fb_cnt = R.job_off = R.job_cnt = R.oA = 0;
+    R.mA = 0ull;
+    return R;
+  }
   R.s0 = T.fstr[0];
   R.s1 = T.fstr[1];
   R.fbase = T.fbase;
@@ -469,9 +486,9 @@ template <int D, int P>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_apply_pipe(const DevInst* __restrict__ insts,
                                                     const WorkItem* __restrict__ work, int nwork, int ucap,
                                                     const double* __restrict__ x, double* __restrict__ y,
-                                                    const int32_t* __restrict__ gate) {
+                                                    Gate gate) {
   extern __shared__ double smem[];
-  if (gate && *gate == 0) return;
+  if (gate.count && *gate.count == 0) return;
   constexpr int E = kEdge<D>;
   double* U = smem;
   double* V = U + ucap;
@@ -494,14 +511,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
   }
 
   // prologue: data of tile w, lists of w+per, record of w+2per
-  PipeRec R0 = pipe_rec<D>(insts, work, w, wave);
+  PipeRec R0 = pipe_rec<D>(insts, work, w, wave, gate);
   PipeList L0 = pipe_list<D>(insts, R0, tid, wave, lane);
   PipeData<D> D0;
   pipe_data<D>(insts, R0, L0, x, l, wave, lane, D0);
   const bool v1 = w + per < w_end, v2 = w + 2 * per < w_end;
-  PipeRec R1 = v1 ? pipe_rec<D>(insts, work, w + per, wave) : R0;
+  PipeRec R1 = v1 ? pipe_rec<D>(insts, work, w + per, wave, gate) : R0;
   PipeList L1 = v1 ? pipe_list<D>(insts, R1, tid, wave, lane) : L0;
-  PipeRec R2 = v2 ? pipe_rec<D>(insts, work, w + 2 * per, wave) : R1;
+  PipeRec R2 = v2 ? pipe_rec<D>(insts, work, w + 2 * per, wave, gate) : R1;
 
 #pragma unroll 1
   for (; w < w_end; w += per) {
@@ -525,7 +542,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     PipeList L2 = L1;
     if (n2) L2 = pipe_list<D>(insts, R2, tid, wave, lane);
     PipeRec R3 = R2;
-    if (n3) R3 = pipe_rec<D>(insts, work, w + 3 * per, wave);
+    if (n3) R3 = pipe_rec<D>(insts, work, w + 3 * per, wave, gate);
     // ---- extension rows of this tile
     if (slot0 >= 0) V[slot0] = erow_lds<D, P>(t0, U, s0, s1, fbase);
     if (slot1 >= 0) {
@@ -548,12 +565,12 @@ template <int D, int P, int NRHS>
 __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restrict__ insts,
                                                         const WorkItem* __restrict__ work, int nwork,
                                                         const double* __restrict__ x, double* __restrict__ y,
-                                                        const int32_t* __restrict__ gate) {
-  if (gate && *gate == 0) return;
+                                                        Gate gate) {
   constexpr int NB = D == 3 ? 8 : 4, E = kEdge<D>;
   const int w = blockIdx.x;
   if (w >= nwork) return;
   const WorkItem wi = work[w];
+  if (gate_skip(gate, wi.inst)) return;
   const DevInst& I = insts[wi.inst];
   const DevTile& tile = I.tiles[wi.idx];
   const int wave = threadIdx.x >> 6, lane = lane_id();
@@ -593,8 +610,8 @@ __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restric
 // ---- transpose: z = O^T y over Sigma_A u Sigma_G
 template <int D, int NRHS>
 __global__ void __launch_bounds__(256) k_OT(DevInst I, const double* __restrict__ y, double* __restrict__ z,
-                                            const int32_t* __restrict__ gate) {
-  if (gate && *gate == 0) return;
+                                            Gate gate, int inst) {
+  if (gate_skip(gate, inst)) return;
   const int id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (id >= I.nbricks) return;
   const int lane = lane_id();
@@ -626,8 +643,8 @@ __global__ void __launch_bounds__(256) k_OT(DevInst I, const double* __restrict_
 // ---- transpose: y_out = diag y - h^-2 E^T z, each output gathers the rows whose cube holds it
 template <int D, int P, int NRHS>
 __global__ void __launch_bounds__(256) k_ET(DevInst I, const double* __restrict__ yin, const double* __restrict__ z,
-                                            double* __restrict__ yout, const int32_t* __restrict__ gate) {
-  if (gate && *gate == 0) return;
+                                            double* __restrict__ yout, Gate gate, int inst) {
+  if (gate_skip(gate, inst)) return;
   const int id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (id >= I.nbricks) return;
   const int lane = lane_id();
@@ -706,7 +723,7 @@ static int pipe_grid(int nwork, size_t shm, const void* kern) {
 template <int D, int P, int NRHS>
 static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkItem* work, int nwork, int ucap,
                                  const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s,
-                                 const int32_t* gate) {
+                                 const Gate& gate) {
   if (nwork > 0) {
     const size_t shm = (size_t)ucap * sizeof(double) + tile_lds_extra<D>();
     if (NRHS == 1 && variant == kApplyPipelined) {
@@ -724,7 +741,7 @@ static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkIt
 
 hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work, int nwork,
                         int ucap, const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s,
-                        const int32_t* gate) {
+                        const Gate& gate) {
 #define CPM_CASE(D, P, R) \
   if (d == D && p == P && nrhs == R)                                                              \
     return launch_apply_t<D, P, R>(variant, insts, work, nwork, ucap, fb, nfb, x, y, s, gate);
@@ -751,18 +768,18 @@ hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream
 
 template <int D, int P, int NRHS>
 static hipError_t launch_apply_T_t(const DevInst& I, const double* x, double* z, double* y, hipStream_t s,
-                                   const int32_t* gate) {
+                                   const Gate& gate, int inst) {
   dim3 g((I.nbricks + 3) / 4), b(256);
-  hipLaunchKernelGGL((k_OT<D, NRHS>), g, b, 0, s, I, x, z, gate);
-  hipLaunchKernelGGL((k_ET<D, P, NRHS>), g, b, 0, s, I, x, z, y, gate);
+  hipLaunchKernelGGL((k_OT<D, NRHS>), g, b, 0, s, I, x, z, gate, inst);
+  hipLaunchKernelGGL((k_ET<D, P, NRHS>), g, b, 0, s, I, x, z, y, gate, inst);
   return hipGetLastError();
 }
 
 hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* zscratch, double* y, hipStream_t s,
-                          const int32_t* gate) {
+                          const Gate& gate, int inst) {
   if (I.nbricks == 0) return hipSuccess;
 #define CPM_CASE(D, P, R) \
-  if (I.d == D && I.p == P && nrhs == R) return launch_apply_T_t<D, P, R>(I, x, zscratch, y, s, gate);
+  if (I.d == D && I.p == P && nrhs == R) return launch_apply_T_t<D, P, R>(I, x, zscratch, y, s, gate, inst);
   CPM_CASE(3, 3, 1) CPM_CASE(3, 3, 2) CPM_CASE(3, 3, 4)
   CPM_CASE(3, 2, 1) CPM_CASE(3, 2, 2) CPM_CASE(3, 2, 4)
   CPM_CASE(3, 1, 1) CPM_CASE(3, 1, 2) CPM_CASE(3, 1, 4)

@@ -53,14 +53,13 @@ struct DevBuf {
 };
 
 // kernel launchers (apply.hip)
-// gate (device int, may be null): when it reads 0 the kernels return at once (graph-captured
-// Krylov cycles whose systems have all converged)
+// gate: lets Krylov cycles skip instances whose systems have stopped (see Gate)
 hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work, int nwork,
                         int ucap, const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s,
-                        const int32_t* gate = nullptr);
+                        const Gate& gate = Gate{});
 hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream_t s);
 hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* zscratch, double* y,
-                          hipStream_t s, const int32_t* gate = nullptr);
+                          hipStream_t s, const Gate& gate = Gate{}, int inst = 0);
 
 inline int vbox_nodes(int d) { return d == 3 ? 10 * 10 * 10 : 18 * 18; }
 // footprint bricks a tile may stage in the pipelined apply (8 per wavefront)

@@ -63,6 +63,16 @@ struct DevInst {
 constexpr int kApplyPipelined = 0;
 constexpr int kApplyPerTile = 1;
 
+// Work gate of the operator and preconditioner kernels inside Krylov cycles.
+// count (device int, may be null): every system has stopped when it reads 0;
+// act (device [instances * nrhs], may be null): instance i is skipped when none
+// of act[i*nrhs .. i*nrhs + nrhs) is set.
+struct Gate {
+  const int32_t* count = nullptr;
+  const int32_t* act = nullptr;
+  int32_t nrhs = 1;
+};
+
 // (instance, item) pair of a work list: a tile, a subdomain or a vector chunk
 struct WorkItem {
   int32_t inst, idx;

@@ -77,7 +77,7 @@ inline size_t schwarz_value_lds(int max_rows, int nrhs, size_t elem) { return 2 
 constexpr int kSchwarzValueMaxLen = 128;   // longest factor row the values-as-flags kernel takes
 hipError_t launch_schwarz(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
                           int max_len, int fp32, int nrhs, const double* r, double* z, hipStream_t s,
-                          const int32_t* gate = nullptr);
+                          const Gate& gate = Gate{});
 
 }  // namespace cpm
 

@@ -15,6 +15,18 @@
 namespace cpm {
 
 constexpr int kSchwarzThreads = 1024;
+
+// true when the gate says instance `inst` has nothing to do
+__device__ __forceinline__ bool gate_skip(const Gate& g, int inst) {
+  if (g.count && *g.count == 0) return true;
+  if (g.act) {
+    int any = 0;
+    for (int r = 0; r < g.nrhs; ++r) any |= g.act[inst * g.nrhs + r];
+    return any == 0;
+  }
+  return false;
+}
+
 constexpr int kSpinLimit = 1 << 22;
 
 template <class T>
@@ -145,11 +157,11 @@ template <class T, int NRHS>
 __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz(const DevPC* __restrict__ pcs,
                                                             const WorkItem* __restrict__ work, int nwork,
                                                             const double* __restrict__ rin, double* __restrict__ zout,
-                                                            const int32_t* __restrict__ gate) {
+                                                            Gate gate) {
   extern __shared__ double smem_d[];
   if ((int)blockIdx.x >= nwork) return;
-  if (gate && *gate == 0) return;
   const WorkItem wi = work[blockIdx.x];
+  if (gate_skip(gate, wi.inst)) return;
   const DevPC& P = pcs[wi.inst];
   const DevSub sub = P.subs[wi.idx];
   const int n = sub.n;
@@ -366,11 +378,11 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz_v(const DevPC* __re
                                                               const WorkItem* __restrict__ work, int nwork,
                                                               const double* __restrict__ rin,
                                                               double* __restrict__ zout,
-                                                              const int32_t* __restrict__ gate) {
+                                                              Gate gate) {
   extern __shared__ double smem_d[];
   if ((int)blockIdx.x >= nwork) return;
-  if (gate && *gate == 0) return;
   const WorkItem wi = work[blockIdx.x];
+  if (gate_skip(gate, wi.inst)) return;
   const DevPC& P = pcs[wi.inst];
   const DevSub sub = P.subs[wi.idx];
   const int n = sub.n;
@@ -415,7 +427,7 @@ static hipError_t lds_ok(const void* kern, size_t shm) {
 
 template <class T, int NRHS>
 static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
-                           int max_len, const double* r, double* z, hipStream_t s, const int32_t* gate) {
+                           int max_len, const double* r, double* z, hipStream_t s, const Gate& gate) {
   const int threads = cfg.threads > 0 ? cfg.threads : kSchwarzThreads;
   if (cfg.variant == kSchwarzValueFlags && max_len <= kSchwarzValueMaxLen &&
       schwarz_value_lds(max_rows, NRHS, sizeof(T)) <= kSchwarzMaxLds) {
@@ -440,7 +452,7 @@ static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkIt
 
 hipError_t launch_schwarz(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
                           int max_len, int fp32, int nrhs, const double* r, double* z, hipStream_t s,
-                          const int32_t* gate) {
+                          const Gate& gate) {
   if (nwork == 0) return hipSuccess;
   if (fp32) {
     if (nrhs == 1) return launch_t<float, 1>(cfg, pcs, work, nwork, max_rows, max_len, r, z, s, gate);

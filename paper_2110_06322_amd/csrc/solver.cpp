@@ -8,11 +8,13 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 
 #include "krylov.h"
 #include "schwarz.h"
+#include "tune.h"
 
 using namespace cpm;
 
@@ -201,7 +203,7 @@ GmresState state_of(cpm_batch_s& Bt, int m) {
 
 // y = A x (or A^T x) over all instances of the batch, packed layout
 void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hipStream_t s,
-                 const int32_t* gate = nullptr) {
+                 const Gate& gate = Gate{}) {
   if (!transpose) {
     hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
                            Bt.nfb, x, y, s, gate),
@@ -212,10 +214,10 @@ void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hi
   for (auto* op : Bt.ops) mx = std::max<int64_t>(mx, op->band->nodes());
   Bt.zT.alloc((size_t)mx * Bt.R);
   for (int i = 0; i < Bt.ni; ++i)
-    hip_check(launch_apply_T(Bt.hinst[i], Bt.R, x, Bt.zT.p, y, s, gate), "transposed operator apply");
+    hip_check(launch_apply_T(Bt.hinst[i], Bt.R, x, Bt.zT.p, y, s, gate, i), "transposed operator apply");
 }
 
-void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s, const int32_t* gate = nullptr) {
+void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s, const Gate& gate = Gate{}) {
   if (Bt.any_pc) {
     hipError_t e = launch_schwarz(Bt.pc_cfg, Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.max_len,
                                   Bt.pc_fp32, Bt.R, v, z, s, gate);
@@ -227,11 +229,12 @@ void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s, c
 }
 
 // One Arnoldi step j of every active system (preconditioner, operator, CGS2,
-// Givens, next basis vector). gate: device count of active systems, used by
-// graph-captured cycles to turn the preconditioner and operator into no-ops
-// once every system has stopped.
+// Givens, next basis vector). The preconditioner and operator skip instances
+// whose systems have all stopped (device activity flags); graph-captured
+// cycles also pass the active-system count, so that steps after convergence
+// are no-ops.
 // pe / ae (optional): event pairs recorded around the preconditioner and the operator.
-void issue_step(cpm_batch_s& Bt, const GmresState& S, int m, int j, bool tr, hipStream_t st, const int32_t* gate,
+void issue_step(cpm_batch_s& Bt, const GmresState& S, int m, int j, bool tr, hipStream_t st, const Gate& gate,
                 hipEvent_t* pe = nullptr, hipEvent_t* ae = nullptr) {
   const int R = Bt.R, ns = Bt.ns;
   const size_t Ns = (size_t)Bt.Ntot * R;
@@ -288,7 +291,7 @@ void ensure_cycle_graph(cpm_batch_s& Bt, const GmresState& S, int m, bool tr) {
   try {
     hip_check(gmres_cycle_init(S, ns, gs), "cycle init");
     hip_check(vec_scale(R, Bt.r.p, Bt.V.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.scale.p, gs), "v0");
-    for (int j = 0; j < m; ++j) issue_step(Bt, S, m, j, tr, gs, Bt.n_active.p);
+    for (int j = 0; j < m; ++j) issue_step(Bt, S, m, j, tr, gs, Gate{Bt.n_active.p, Bt.act.p, Bt.R});
     issue_cycle_end(Bt, S, m, tr, gs);
   } catch (...) {
     hipGraph_t dead = nullptr;
@@ -417,7 +420,7 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
       hip_check(gmres_cycle_init(S, ns, st), "cycle init");
       hip_check(vec_scale(R, Bt.r.p, Bt.V.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.scale.p, st), "v0");
       for (int j = 0; j < m; ++j) {
-        issue_step(Bt, S, m, j, tr, st, nullptr, o.profile ? &pev[2 * j] : nullptr,
+        issue_step(Bt, S, m, j, tr, st, Gate{nullptr, Bt.act.p, Bt.R}, o.profile ? &pev[2 * j] : nullptr,
                    o.profile ? &aev[2 * j] : nullptr);
         if (Bt.any_pc) ++n_pc;
         ++n_ap;
@@ -571,6 +574,108 @@ cpm_status cpm_batch_create(int32_t n, const cpm_operator* const* ops, const cpm
     return e.code;
   } catch (const std::bad_alloc&) {
     set_error("host allocation failed in cpm_batch_create");
+    return CPM_ERR_OOM;
+  }
+}
+
+cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t force, void* stream,
+                              cpm_tune_result* out) {
+  try {
+    if (!b || !out) fail(CPM_ERR_ARG, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    cpm_batch_s& Bt = *b;
+    hipStream_t s = (hipStream_t)stream;
+    const int reps = 5;
+    ensure_workspace(Bt, 1);
+    const size_t Ns = (size_t)Bt.Ntot * Bt.R;
+    hip_check(hipMemsetD32Async((hipDeviceptr_t)Bt.r.p, 0x3ff00000, Ns * 2, s), "tune fill");
+    tune::Cache cache = tune::read_cache(cache_path);
+    bool dirty = false, all_cached = true;
+    const std::string dev = tune::device_tag();
+    {
+      char key[200];
+      std::snprintf(key, sizeof key, "batch-apply|%s|d%dp%dr%d|inst2^%d|nodes2^%d", dev.c_str(), Bt.d, Bt.p, Bt.R,
+                    tune::log2i(Bt.ni), tune::log2i((double)Bt.Ntot));
+      auto it = cache.find(key);
+      if (!force && it != cache.end() && it->second.size() == 1 &&
+          (it->second[0] == kApplyPipelined || it->second[0] == kApplyPerTile)) {
+        Bt.apply_variant = it->second[0];
+      } else {
+        all_cached = false;
+        double best = 1e30;
+        int bestv = kApplyPipelined;
+        for (int v : {kApplyPipelined, kApplyPerTile}) {
+          if (v == kApplyPipelined && Bt.R != 1) continue;
+          Bt.apply_variant = v;
+          const double ms = tune::time_ms(
+              [&] {
+                return launch_apply(Bt.d, Bt.p, Bt.R, v, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
+                                    Bt.nfb, Bt.r.p, Bt.w.p, s);
+              },
+              reps, s);
+          if (ms < best) { best = ms; bestv = v; }
+        }
+        Bt.apply_variant = bestv;
+        cache[key] = {bestv};
+        dirty = true;
+      }
+      out->apply_variant = Bt.apply_variant;
+      out->apply_ms = tune::time_ms(
+          [&] {
+            return launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap,
+                                Bt.d_fb.p, Bt.nfb, Bt.r.p, Bt.w.p, s);
+          },
+          reps, s);
+    }
+    if (Bt.any_pc) {
+      int max_levels = 0;
+      for (auto* pc : Bt.pcs)
+        if (pc) max_levels = std::max(max_levels, pc->max_levels);
+      char key[220];
+      std::snprintf(key, sizeof key, "batch-schwarz|%s|%s|r%d|rows2^%d|levels2^%d|parts2^%d", dev.c_str(),
+                    Bt.pc_fp32 ? "fp32" : "fp64", Bt.R, tune::log2i(Bt.max_rows), tune::log2i(max_levels),
+                    tune::log2i(Bt.npcwork));
+      auto it = cache.find(key);
+      auto run = [&] {
+        return launch_schwarz(Bt.pc_cfg, Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.max_len, Bt.pc_fp32,
+                              Bt.R, Bt.r.p, Bt.w.p, s);
+      };
+      if (!force && it != cache.end() && tune::valid_schwarz(it->second)) {
+        Bt.pc_cfg.variant = it->second[0];
+        Bt.pc_cfg.threads = it->second[1];
+        Bt.pc_cfg.sleep = it->second[2];
+      } else {
+        all_cached = false;
+        double best = 1e30;
+        SchwarzCfg bestc = Bt.pc_cfg;
+        for (const SchwarzCfg& c : tune::schwarz_candidates()) {
+          Bt.pc_cfg = c;
+          const double ms = tune::time_ms(run, reps, s);
+          if (ms < best) { best = ms; bestc = c; }
+        }
+        Bt.pc_cfg = bestc;
+        cache[key] = {bestc.variant, bestc.threads, bestc.sleep};
+        dirty = true;
+      }
+      out->schwarz_variant = Bt.pc_cfg.variant;
+      out->schwarz_threads = Bt.pc_cfg.threads;
+      out->schwarz_sleep = Bt.pc_cfg.sleep;
+      out->precond_ms = tune::time_ms(run, reps, s);
+      bool pc_err = false;
+      for (auto* pc : Bt.pcs)
+        if (pc && precond_take_error(pc)) pc_err = true;
+      if (pc_err) fail(CPM_ERR_DEVICE, "a subdomain solve timed out while tuning");
+    }
+    hip_check(hipStreamSynchronize(s), "tune");
+    Bt.g_gen = -1;   // a captured cycle holds the old kernel choices
+    out->from_cache = all_cached ? 1 : 0;
+    if (dirty) tune::write_cache(cache_path, cache);
+    return CPM_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed in cpm_batch_autotune");
     return CPM_ERR_OOM;
   }
 }

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <sstream>
 #include <string>
@@ -16,17 +17,15 @@
 
 #include "common.h"
 #include "schwarz.h"
+#include "tune.h"
 
 using namespace cpm;
 
 namespace cpm {
 hipError_t precond_apply_raw(const cpm_precond_s* pc, const double* r, double* z, int nrhs, hipStream_t s);
 int precond_take_error(const cpm_precond_s* pc);
-}
 
-namespace {
-
-using Cache = std::map<std::string, std::vector<int>>;
+namespace tune {
 
 // parse {"key": [i, j, ...], ...}; anything else yields an empty cache
 Cache read_cache(const char* path) {
@@ -98,6 +97,26 @@ void write_cache(const char* path, const Cache& c) {
 
 int log2i(double v) { return v <= 1 ? 0 : (int)std::lround(std::log2(v)); }
 
+bool valid_schwarz(const std::vector<int>& v) {
+  return v.size() == 3 && (v[0] == kSchwarzFlags || v[0] == kSchwarzValueFlags) && v[1] >= 64 && v[1] <= 1024 &&
+         v[1] % 64 == 0 && (v[2] == 0 || v[2] == 1);
+}
+
+std::vector<SchwarzCfg> schwarz_candidates() {
+  std::vector<SchwarzCfg> out;
+  for (int variant : {kSchwarzFlags, kSchwarzValueFlags})
+    for (int threads : {256, 512, 1024})
+      for (int sleep : {0, 1}) {
+        if (variant == kSchwarzFlags && sleep == 0) continue;   // the flag kernel always backs off
+        SchwarzCfg c;
+        c.variant = variant;
+        c.threads = threads;
+        c.sleep = sleep;
+        out.push_back(c);
+      }
+  return out;
+}
+
 std::string device_tag() {
   int dev = 0;
   hipDeviceProp_t prop{};
@@ -108,9 +127,7 @@ std::string device_tag() {
   return name + "-cu" + std::to_string(prop.multiProcessorCount);
 }
 
-// mean milliseconds of `reps` launches of f after two warm-up launches
-template <class F>
-double time_ms(F&& f, int reps, hipStream_t s) {
+double time_ms(const std::function<hipError_t()>& f, int reps, hipStream_t s) {
   hipEvent_t a, b;
   hip_check(hipEventCreate(&a), "tune");
   hip_check(hipEventCreate(&b), "tune");
@@ -122,12 +139,15 @@ double time_ms(F&& f, int reps, hipStream_t s) {
   hip_check(hipEventSynchronize(b), "tune");
   float ms = 0;
   hip_check(hipEventElapsedTime(&ms, a, b), "tune");
-  hipEventDestroy(a);
-  hipEventDestroy(b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   return ms / reps;
 }
 
-}  // namespace
+}  // namespace tune
+}  // namespace cpm
+
+using namespace cpm::tune;
 
 cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const char* cache_path, int32_t force,
                         void* stream, cpm_tune_result* out) {
@@ -165,11 +185,12 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
         int bestv = kApplyPipelined;
         for (int c = 0; c < ncand; ++c) {
           const int v = cand[c];
-          auto f = [&] {
-            return launch_apply(op->I.d, op->I.p, nrhs, v, op->d_inst.p, op->d_work.p, op->nwork, op->ucap,
-                                op->d_fb.p, op->nfb, x.p, y.p, s);
-          };
-          const double ms = time_ms(f, reps, s);
+          const double ms = time_ms(
+              [&] {
+                return launch_apply(op->I.d, op->I.p, nrhs, v, op->d_inst.p, op->d_work.p, op->nwork, op->ucap,
+                                    op->d_fb.p, op->nfb, x.p, y.p, s);
+              },
+              reps, s);
           if (ms < best) { best = ms; bestv = v; }
         }
         op->apply_variant = bestv;
@@ -191,11 +212,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
                     pc->P.fp32 ? "fp32" : "fp64", nrhs, log2i((double)pc->max_rows), log2i((double)pc->max_levels),
                     log2i((double)pc->host.nparts));
       auto it = cache.find(key);
-      const bool valid = it != cache.end() && it->second.size() == 3 &&
-                         (it->second[0] == kSchwarzFlags || it->second[0] == kSchwarzValueFlags) &&
-                         it->second[1] >= 64 && it->second[1] <= 1024 && it->second[1] % 64 == 0 &&
-                         (it->second[2] == 0 || it->second[2] == 1);
-      if (!force && valid) {
+      if (!force && it != cache.end() && valid_schwarz(it->second)) {
         pc->cfg.variant = it->second[0];
         pc->cfg.threads = it->second[1];
         pc->cfg.sleep = it->second[2];
@@ -203,19 +220,11 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
         all_cached = false;
         double best = 1e30;
         SchwarzCfg bestc = pc->cfg;
-        for (int variant : {kSchwarzFlags, kSchwarzValueFlags})
-          for (int threads : {256, 512, 1024})
-            for (int sleep : {0, 1}) {
-              SchwarzCfg c;
-              c.variant = variant;
-              c.threads = threads;
-              c.sleep = sleep;
-              if (variant == kSchwarzFlags && sleep == 0) continue;   // the flag kernel always backs off
-              pc->cfg = c;
-              auto f = [&] { return precond_apply_raw(pc, x.p, y.p, nrhs, s); };
-              const double ms = time_ms(f, reps, s);
-              if (ms < best) { best = ms; bestc = c; }
-            }
+        for (const SchwarzCfg& c : schwarz_candidates()) {
+          pc->cfg = c;
+          const double ms = time_ms([&] { return precond_apply_raw(pc, x.p, y.p, nrhs, s); }, reps, s);
+          if (ms < best) { best = ms; bestc = c; }
+        }
         pc->cfg = bestc;
         cache[key] = {bestc.variant, bestc.threads, bestc.sleep};
         dirty = true;
@@ -224,8 +233,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
       out->schwarz_variant = pc->cfg.variant;
       out->schwarz_threads = pc->cfg.threads;
       out->schwarz_sleep = pc->cfg.sleep;
-      auto f = [&] { return precond_apply_raw(pc, x.p, y.p, nrhs, s); };
-      out->precond_ms = time_ms(f, reps, s);
+      out->precond_ms = time_ms([&] { return precond_apply_raw(pc, x.p, y.p, nrhs, s); }, reps, s);
     }
     hip_check(hipStreamSynchronize(s), "tune");
     // cached single-solve workspaces were built with the old choices

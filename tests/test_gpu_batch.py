@@ -53,6 +53,18 @@ def test_batch_mixed_solve_equals_solo_and_meets_tolerance(small_batch):
             assert res <= 1e-8 * 1.01, (k, r, res)
 
 
+def test_batch_autotune_keeps_results(small_batch, tmp_path):
+    insts = small_batch
+    b = cpm.Batch([i.op for i in insts], [i.pc for i in insts], [4] * len(insts))
+    us0, st0 = b.solve([i.f for i in insts], rtol=1e-8, mode="mixed", max_it=5000)
+    r = b.autotune(cache=tmp_path / "t.json")
+    assert r["precond_ms"] > 0 and r["from_cache"] == 0
+    assert b.autotune(cache=tmp_path / "t.json")["from_cache"] == 1
+    us1, st1 = b.solve([i.f for i in insts], rtol=1e-8, mode="mixed", max_it=5000)
+    for a, c in zip(us0, us1):
+        assert torch.equal(a, c)
+
+
 def test_batch_rejects_mixed_dimensions():
     G.ensure_built()
     b2 = cpm.Band("circle", (1.0,), 2, 0.1, 3)
