@@ -22,7 +22,12 @@ Readings (the paper fixes none of these discretely):
     at the unvisited node of least degree, visit each node's unvisited
     neighbours by (degree, key position), reverse the whole sequence. The
     ordering decides whether ILU(0) is usable on these non-diagonally
-    dominant matrices (lexicographic order stagnates; RCM does not);
+    dominant matrices (lexicographic order stagnates; RCM does not). A second
+    order sorts rows by decreasing distance |x - cp(x)| of their grid node
+    from the surface (ties by key position): dependency chains of the
+    triangular solves about as long as the band is thick (~200 levels instead
+    of ~2000 on 4000-row subdomains) at the price of 50-85 % more GMRES
+    iterations;
   * Robin (ORAS): on row i of Omega_j with dropped couplings
     s_i = sum_{k not in Omega_j} a_ik, the diagonal becomes a_ii + s_i/(1 + alpha_i h),
     alpha_i = alpha_cross if the dropped k are owned by >= 2 other
@@ -120,6 +125,17 @@ def rcm_order(Aloc: sp.csr_matrix) -> np.ndarray:
     return np.array(order[::-1], dtype=np.int64)
 
 
+def distance_order(dist: np.ndarray) -> np.ndarray:
+    """Local rows by decreasing distance of their grid node from the surface,
+    ties by local index (ascending grid key). perm[q] = row placed at q.
+
+    Outer rows come first, so every row's lower-triangle couplings point away
+    from the surface and the dependency chains of the triangular solves are
+    about as long as the band is thick rather than as long as the subdomain.
+    """
+    return np.argsort(-np.asarray(dist, dtype=np.float64), kind="stable").astype(np.int64)
+
+
 def ilu0(Aloc: sp.csr_matrix):
     """ILU(0), IKJ form (Saad, Alg. 10.4) on the stored pattern of Aloc.
 
@@ -198,13 +214,19 @@ class Schwarz:
 def build_schwarz(A: sp.csr_matrix, pattern: sp.csr_matrix, cp: np.ndarray, keys: np.ndarray,
                   h: float, n_parts: int, overlap: float, kind: str = "ras",
                   alpha: float = 4.0, alpha_cross: float = 20.0, subsolver: str = "ilu0",
-                  partition=None, only=None) -> Schwarz:
+                  partition=None, only=None, ordering: str = "rcm", dist=None) -> Schwarz:
     """Partition, overlap, local matrices, optional Robin change, local factorizations.
 
     `A` must carry values on `pattern` (see operator.values_on_pattern). `overlap`
     is N_O, the growth in units of h. `only` restricts the local solves to the
     listed subdomains (the others contribute zero), to sample large cases.
+    `ordering` is the local row order before ILU(0): "rcm" (rcm_order) or
+    "distance" (distance_order; `dist` = |x - cp(x)| per active node).
     """
+    if ordering not in ("rcm", "distance"):
+        raise ValueError("ordering must be 'rcm' or 'distance'")
+    if ordering == "distance" and dist is None:
+        raise ValueError("the distance ordering needs dist")
     if partition is None:
         owner, blo, bhi = rcb_partition(cp, n_parts)
     else:
@@ -240,7 +262,7 @@ def build_schwarz(A: sp.csr_matrix, pattern: sp.csr_matrix, cp: np.ndarray, keys
                 Aj.data[dpos] = Aj.data[dpos] + s_i / (1.0 + a * h)
         S.local.append(Aj)
         if subsolver == "ilu0":
-            perm = rcm_order(Aj)
+            perm = rcm_order(Aj) if ordering == "rcm" else distance_order(np.asarray(dist)[idx])
             Ap = sp.csr_matrix(Aj[perm][:, perm])
             Ap.sort_indices()
             S.perms.append(perm)

@@ -37,7 +37,7 @@ class BandInfo(C.Structure):
 class PrecondOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_parts", C.c_int32), ("overlap", C.c_double),
                 ("alpha", C.c_double), ("alpha_cross", C.c_double), ("subsolver", C.c_int32),
-                ("precision", C.c_int32), ("transpose", C.c_int32)]
+                ("precision", C.c_int32), ("transpose", C.c_int32), ("ordering", C.c_int32)]
 
 
 class PrecondInfo(C.Structure):

@@ -18,6 +18,7 @@ PC_KIND = {"none": 0, "ras": 1, "oras": 2}
 SUBSOLVER = {"ilu0": 0, "lu": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 MODE = {"fp64": 0, "mixed": 1}
+ORDERING = {"rcm": 0, "distance": 1}
 
 
 def _torch():
@@ -154,6 +155,7 @@ class PrecondOptions:
     subsolver: str = "ilu0"
     precision: str = "fp64"
     transpose: bool = False
+    ordering: str = "rcm"
 
     def to_c(self):
         o = _capi.PrecondOpts()
@@ -165,6 +167,7 @@ class PrecondOptions:
         o.subsolver = SUBSOLVER[self.subsolver]
         o.precision = PRECISION[self.precision]
         o.transpose = int(bool(self.transpose))
+        o.ordering = ORDERING[self.ordering]
         return o
 
 

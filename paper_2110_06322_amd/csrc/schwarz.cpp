@@ -251,6 +251,27 @@ bool dense_lu(int n, std::vector<double>& a, std::vector<int32_t>& perm) {
 // Reverse Cuthill-McKee order of the symmetrized pattern (George & Liu 1981):
 // each component starts at its unvisited node of least (degree, index);
 // unvisited neighbours are queued by (degree, index); the sequence is reversed.
+// Local rows by decreasing distance |x - cp(x)| of their grid node from the
+// surface, ties by local index (ascending grid key); perm[q] = row at q.
+std::vector<int32_t> distance_order(const cpm_band_s& B, const std::vector<int32_t>& rows) {
+  const int n = (int)rows.size(), d = B.d;
+  std::vector<double> dist(n);
+  for (int q = 0; q < n; ++q) {
+    const int64_t i = rows[q];
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double x = B.lo[k] + B.gidx[i * d + k] * B.h;
+      const double e = x - B.cp[i * d + k];
+      s += e * e;
+    }
+    dist[q] = std::sqrt(s);
+  }
+  std::vector<int32_t> perm(n);
+  for (int q = 0; q < n; ++q) perm[q] = q;
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return dist[a] > dist[b]; });
+  return perm;
+}
+
 std::vector<int32_t> rcm_order(int n, const std::vector<int64_t>& ptr, const std::vector<int32_t>& col) {
   std::vector<int64_t> cnt(n + 1, 0);
   for (int i = 0; i < n; ++i)
@@ -455,8 +476,9 @@ void build_schwarz_host(const cpm_band_s& B, double c, const cpm_precond_opts& o
         }
         sub.nnz = (int64_t)col.size();
         if (o.subsolver == CPM_SUB_ILU0) {
-          // reverse Cuthill-McKee order, then ILU(0) of the permuted matrix
-          std::vector<int32_t> perm = rcm_order(n, ptr, col);
+          // reverse Cuthill-McKee or distance order, then ILU(0) of the permuted matrix
+          std::vector<int32_t> perm =
+              o.ordering == CPM_ORDER_DISTANCE ? distance_order(B, sub.rows) : rcm_order(n, ptr, col);
           std::vector<int32_t> inv(n);
           for (int q = 0; q < n; ++q) inv[perm[q]] = q;
           std::vector<int64_t> pptr(n + 1, 0);

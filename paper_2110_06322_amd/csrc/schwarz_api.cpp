@@ -18,6 +18,7 @@ cpm_status cpm_precond_opts_default(cpm_precond_opts* o) {
   o->subsolver = CPM_SUB_ILU0;
   o->precision = CPM_PREC_FP64;
   o->transpose = 0;
+  o->ordering = CPM_ORDER_RCM;
   return CPM_OK;
 }
 
@@ -43,6 +44,7 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     if (opts->kind != CPM_PC_RAS && opts->kind != CPM_PC_ORAS) fail(CPM_ERR_ARG, "kind must be RAS or ORAS");
     if (opts->subsolver != CPM_SUB_ILU0 && opts->subsolver != CPM_SUB_DENSE_LU) fail(CPM_ERR_ARG, "bad subsolver");
     if (opts->precision != CPM_PREC_FP64 && opts->precision != CPM_PREC_FP32) fail(CPM_ERR_ARG, "bad precision");
+    if (opts->ordering != CPM_ORDER_RCM && opts->ordering != CPM_ORDER_DISTANCE) fail(CPM_ERR_ARG, "bad ordering");
     auto pc = std::make_unique<cpm_precond_s>();
     pc->op = op;
     pc->opts = *opts;

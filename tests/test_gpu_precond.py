@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import schwarz
+from oracle import band as OB
+from oracle import schwarz, surfaces
 from paper_2110_06322_amd import _capi, cpm
 from tests import gpu_cases as G
 
@@ -19,32 +20,42 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
-def _setup(kind, params, h, n_parts, pc_kind, precision="fp64", subsolver="ilu0", transpose=False, c=1.0):
+def _setup(kind, params, h, n_parts, pc_kind, precision="fp64", subsolver="ilu0", transpose=False, c=1.0,
+           ordering="rcm"):
     lb = G.lib_band(kind, params, 3, h, 3)
     ob, E, O, A, P = G.oracle(kind, params, 3, h, 3, c)
     keys, pos = G.mapping(lb, ob)
     op = cpm.Operator(lb, c)
     pc = cpm.Precond(op, kind=pc_kind, n_parts=n_parts, overlap=2.0, precision=precision,
-                     subsolver=subsolver, transpose=transpose)
+                     subsolver=subsolver, transpose=transpose, ordering=ordering)
     return lb, ob, A, P, keys, pos, op, pc
 
 
-@pytest.mark.parametrize("pc_kind,precision,subsolver,transpose", [
-    ("ras", "fp64", "ilu0", False),
-    ("oras", "fp64", "ilu0", False),
-    ("oras", "fp32", "ilu0", False),
-    ("ras", "fp64", "lu", False),
-    ("ras", "fp64", "ilu0", True),
-    ("oras", "fp64", "ilu0", True),
+def _dist(ob):
+    return surfaces.distance(OB.coords(ob.active_ijk, ob.lo, ob.h), ob.cp_active)
+
+
+@pytest.mark.parametrize("pc_kind,precision,subsolver,transpose,ordering", [
+    ("ras", "fp64", "ilu0", False, "rcm"),
+    ("oras", "fp64", "ilu0", False, "rcm"),
+    ("oras", "fp32", "ilu0", False, "rcm"),
+    ("ras", "fp64", "lu", False, "rcm"),
+    ("ras", "fp64", "ilu0", True, "rcm"),
+    ("oras", "fp64", "ilu0", True, "rcm"),
+    ("ras", "fp64", "ilu0", False, "distance"),
+    ("oras", "fp64", "ilu0", False, "distance"),
+    ("oras", "fp32", "ilu0", False, "distance"),
+    ("ras", "fp64", "ilu0", True, "distance"),
 ])
-def test_precond_parity_small(pc_kind, precision, subsolver, transpose):
-    print("case", pc_kind, precision, subsolver, transpose, flush=True)
-    lb, ob, A, P, keys, pos, op, pc = _setup("sphere", (1.0,), 0.1, 8, pc_kind, precision, subsolver, transpose)
+def test_precond_parity_small(pc_kind, precision, subsolver, transpose, ordering):
+    print("case", pc_kind, precision, subsolver, transpose, ordering, flush=True)
+    lb, ob, A, P, keys, pos, op, pc = _setup("sphere", (1.0,), 0.1, 8, pc_kind, precision, subsolver, transpose,
+                                             ordering=ordering)
     owner, ptr, idx = pc.export_partition()
     Aop = A.T.tocsr() if transpose else A
     Pp = P.T.tocsr() if transpose else P
     S = schwarz.build_schwarz(Aop, Pp, ob.cp_active, ob.active_keys, ob.h, 8, 2.0, kind=pc_kind,
-                              subsolver=subsolver)
+                              subsolver=subsolver, ordering=ordering, dist=_dist(ob))
     assert np.array_equal(S.owner[pos], owner)
     for j in range(8):
         assert np.array_equal(pos[idx[ptr[j]:ptr[j + 1]]], S.omegas[j])
@@ -74,12 +85,14 @@ def test_precond_multi_rhs_matches_single(nrhs):
         assert np.array_equal(z1, z[:, r])
 
 
-def test_precond_config2_sampled_subdomains():
+@pytest.mark.parametrize("ordering", ["rcm", "distance"])
+def test_precond_config2_sampled_subdomains(ordering):
     """Sphere h = 0.02, p = 3, ORAS with 64 boxes, overlap 2h: partition exact, three subdomains' solves."""
-    lb, ob, A, P, keys, pos, op, pc = _setup("sphere", (1.0,), 0.02, 64, "oras")
+    lb, ob, A, P, keys, pos, op, pc = _setup("sphere", (1.0,), 0.02, 64, "oras", ordering=ordering)
     owner, ptr, idx = pc.export_partition()
     sample = [0, 31, 63]
-    S = schwarz.build_schwarz(A, P, ob.cp_active, ob.active_keys, ob.h, 64, 2.0, kind="oras", only=sample)
+    S = schwarz.build_schwarz(A, P, ob.cp_active, ob.active_keys, ob.h, 64, 2.0, kind="oras", only=sample,
+                              ordering=ordering, dist=_dist(ob))
     assert np.array_equal(S.owner[pos], owner)
     for j in range(64):
         assert np.array_equal(pos[idx[ptr[j]:ptr[j + 1]]], S.omegas[j])

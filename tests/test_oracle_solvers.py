@@ -14,7 +14,8 @@ import pytest
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from oracle import adjoint, krylov, reaction, schwarz
+from oracle import adjoint, krylov, reaction, schwarz, surfaces
+from oracle import band as OB
 from paper_2110_06322_amd import inputs
 from tests import oracle_cases as C
 
@@ -200,3 +201,28 @@ def test_rcm_textbook_cases():
     assert np.abs(r1 - c1).max() <= 12 < np.abs(r0 - c0).max()
     # the empty graph: least (degree, index) order reversed
     assert np.array_equal(schwarz.rcm_order(sp.identity(5, format="csr")), np.arange(5)[::-1])
+
+
+def test_distance_order_cases_and_short_chains():
+    """Distance order: decreasing distance, equal distances keep their index order; on
+    a real subdomain the ILU(0) forward sweep's longest dependency chain is short (rows
+    couple only to rows at larger or equal distance before them) while RCM's is long."""
+    assert np.array_equal(schwarz.distance_order(np.array([0.3, 0.1, 0.3, 0.2])), [0, 2, 3, 1])
+    assert np.array_equal(schwarz.distance_order(np.zeros(4)), np.arange(4))
+    bd, E, O, A, P = C.matrices("sphere", (1.0,), 3, 0.1, 3, 1.0)
+    dist = surfaces.distance(OB.coords(bd.active_ijk, bd.lo, bd.h), bd.cp_active)
+    owner, blo, bhi = schwarz.rcb_partition(bd.cp_active, 2)
+    idx = schwarz.overlap_sets(bd.cp_active, blo, bhi, 0.2, bd.active_keys)[0]
+    Aj = sp.csr_matrix(sp.csr_matrix(A)[idx][:, idx])
+
+    def chain(perm):
+        L = sp.csr_matrix(sp.tril(sp.csr_matrix(Aj[perm][:, perm]), k=-1))
+        lev = np.zeros(L.shape[0], dtype=np.int64)
+        for i in range(L.shape[0]):
+            js = L.indices[L.indptr[i]:L.indptr[i + 1]]
+            lev[i] = lev[js].max() + 1 if js.size else 0
+        return lev.max() + 1
+
+    pd = schwarz.distance_order(dist[idx])
+    assert np.all(np.diff(dist[idx][pd]) <= 0)
+    assert 3 * chain(pd) < chain(schwarz.rcm_order(Aj))
