@@ -48,6 +48,12 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--subsolver", default=os.environ.get("CPM_BENCH_SUBSOLVER", "ilu0"))
     ap.add_argument("--pc", default=os.environ.get("CPM_BENCH_PC", "oras"))
+    ap.add_argument("--ordering", default=os.environ.get("CPM_BENCH_ORDERING", "distance"),
+                    help="local row order before ILU(0): distance (packet kernel) or rcm")
+    ap.add_argument("--no-compare", action="store_true", help="skip the solve with the other row ordering")
+    ap.add_argument("--batched-ordering", default="rcm",
+                    help="row order of the batched leg (rcm: fewer iterations win on mixed surfaces)")
+    ap.add_argument("--gs-ordering", default="distance", help="row order of the Gray-Scott leg")
     ap.add_argument("--no-scaling", action="store_true", help="skip the larger-torus apply measurements")
     ap.add_argument("--batched", action="store_true",
                     help="also time one batched solve of the 48-surface workload (4 RHS each; adds minutes of setup)")
@@ -56,11 +62,11 @@ def _args():
     return ap.parse_args()
 
 
-def batched_leg(cpm, workloads, torch):
+def batched_leg(cpm, workloads, torch, ordering):
     """One mixed-precision batched solve to 1e-8 of the 48-surface workload (192 systems)."""
     t0 = time.perf_counter()
     print("batched: building 48 instances", file=sys.stderr, flush=True)
-    insts = workloads.batched()
+    insts = workloads.batched(ordering=ordering)
     t_setup = time.perf_counter() - t0
     print(f"batched: setup {t_setup:.1f} s", file=sys.stderr, flush=True)
     bt = cpm.Batch([i.op for i in insts], [i.pc for i in insts], [4] * len(insts))
@@ -74,19 +80,20 @@ def batched_leg(cpm, workloads, torch):
     ms = (time.perf_counter() - t0) * 1e3
     its = [s["iterations"] for s in stats]
     return {"workload": "48 surfaces (16 spheres, 16 ellipsoids, 16 tori), h cyclic 0.04/0.02/0.01, p=3, "
-                        "4 N(0,1) RHS each, FP32 ORAS 32-512 boxes, FP64 FGMRES-IR to 1e-8",
+                        f"4 N(0,1) RHS each, FP32 ORAS 32-512 boxes ({ordering} order), FP64 FGMRES-IR to 1e-8",
             "systems": len(stats), "n_active_total": int(sum(i.band.n_active for i in insts)),
             "solve_ms": round(ms, 2), "iterations_max": int(max(its)), "iterations_mean": round(float(sum(its)) / len(its), 1),
             "converged": bool(all(s["converged"] for s in stats)), "setup_s": round(t_setup, 2),
             "tuning": tune}
 
 
-def gray_scott_leg(cpm, torch, steps):
+def gray_scott_leg(cpm, torch, steps, ordering):
     """Semi-implicit Gray-Scott on the torus R=1 r=0.4 h=0.005: steps of two batched shifted solves."""
     from paper_2110_06322_amd import gray_scott
     t0 = time.perf_counter()
     band = cpm.Band("torus", (1.0, 0.4), 3, 0.005, 3)
-    gs = gray_scott.GrayScott(band, n_parts=1024, mode="mixed", precision="fp32", rtol=1e-8, tune=True)
+    gs = gray_scott.GrayScott(band, n_parts=1024, mode="mixed", precision="fp32", rtol=1e-8, tune=True,
+                              ordering=ordering)
     t_setup = time.perf_counter() - t0
     print(f"gray-scott: setup {t_setup:.1f} s", file=sys.stderr, flush=True)
     gs.step()
@@ -102,7 +109,7 @@ def gray_scott_leg(cpm, torch, steps):
     el = time.perf_counter() - t0
     u = gs.u
     return {"workload": "Gray-Scott torus R=1 r=0.4 h=0.005 p=3, mu=(2e-5,1e-5) F=0.04 k=0.06 dt=1, "
-                        "FP32 ORAS 1024 boxes, FP64 FGMRES-IR to 1e-8, warm starts",
+                        f"FP32 ORAS 1024 boxes ({ordering} order), FP64 FGMRES-IR to 1e-8, warm starts",
             "n_active": band.n_active, "steps": steps, "ms_per_step": round(el * 1e3 / max(1, steps - 1), 3),
             "iterations_max": int(max(its) if its else 0), "setup_s": round(t_setup, 2),
             "u_min": float(u.min()), "u_max": float(u.max()), "finite": bool(torch.isfinite(u).all()),
@@ -213,10 +220,12 @@ def main():
     nA, nG = band.n_active, band.n_ghost
     f = torch.tensor(21.0 * inputs.sphere_y4(cp[:nA], 2), dtype=torch.float64, device=dev)
     t0 = time.perf_counter()
-    pc32 = cpm.Precond(op, kind=a.pc, n_parts=64, overlap=2.0, precision="fp32", subsolver=a.subsolver)
+    pc32 = cpm.Precond(op, kind=a.pc, n_parts=64, overlap=2.0, precision="fp32", subsolver=a.subsolver,
+                       ordering=a.ordering)
     t_pc32 = time.perf_counter() - t0
     t0 = time.perf_counter()
-    pc64 = cpm.Precond(op, kind=a.pc, n_parts=64, overlap=2.0, precision="fp64", subsolver=a.subsolver)
+    pc64 = cpm.Precond(op, kind=a.pc, n_parts=64, overlap=2.0, precision="fp64", subsolver=a.subsolver,
+                       ordering=a.ordering)
     t_pc64 = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
     tune32 = cpm.autotune(op, pc32, cache=a.tune_cache)
@@ -265,7 +274,23 @@ def main():
     b_pc = pci.total_nnz * (4 + 2) + pci.total_rows * (8 + 8 + 4 + 4 + 8 + 8) + 4 * pci.total_rows
     traffic = measured_traffic()
     apply_kernel = "k_apply_pipe<3,3>" if tune32["apply_variant"] == 0 else "k_apply_tile<3,3,1>"
-    pc_kernel = ("k_schwarz_v<float,1>" if tune32["schwarz_variant"] == 1 else "k_schwarz<float,1>")
+    pc_kernel = {0: "k_schwarz<float,1>", 1: "k_schwarz_v<float,1>", 2: "k_schwarz_p<float,1> (values as flags)",
+                 3: "k_schwarz_p<float,1> (completion flags)"}[tune32["schwarz_variant"]]
+    other = None
+    if not a.no_compare:
+        # the same solves with the other local row order (context for the ordering choice)
+        o2 = "rcm" if a.ordering == "distance" else "distance"
+        other = {"ordering": o2}
+        for prec, mode in (("fp32", "mixed"), ("fp64", "fp64")):
+            pco = cpm.Precond(op, kind=a.pc, n_parts=64, overlap=2.0, precision=prec, subsolver=a.subsolver,
+                              ordering=o2)
+            tn = cpm.autotune(op, pco, cache=a.tune_cache)
+            u.zero_()
+            cpm.solve(op, f, pc=pco, u=u, rtol=1e-8, mode=mode, max_it=20000)
+            u.zero_()
+            _, sto = cpm.solve(op, f, pc=pco, u=u, rtol=1e-8, mode=mode, max_it=20000)
+            other[mode] = {"ms": round(sto["ms_total"], 3), "iterations": int(sto["iterations"]),
+                           "precond_ms": round(tn["precond_ms"], 4), "schwarz_variant": tn["schwarz_variant"]}
     scaling = None if a.no_scaling else apply_scaling(cpm, inputs, torch, dev)
     out = {
         "metric": "CPM apply Gnodes/s (%HBM peak); ORAS-GMRES time to 1e-8, mixed vs FP64",
@@ -281,7 +306,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "unit sphere h=0.02 on [-2,2]^3, p=3, c=1, f=21*Y4 (seed 2), "
-                               f"{a.pc.upper()} 64 boxes overlap 2h, local {a.subsolver}",
+                               f"{a.pc.upper()} 64 boxes overlap 2h, local {a.subsolver} ({a.ordering} order)",
                    "n_active": nA, "n_ghost": nG, "n_band": band.n_band},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -290,7 +315,8 @@ def main():
                   "speedup_mixed": round(solve64_ms / solve_ms, 3) if solve_ms > 0 else None,
                   "iters_mixed": int(stats[-1]["iterations"]), "iters_fp64": int(st64[-1]["iterations"]),
                   "relres_mixed": stats[-1]["relres"], "relres_fp64": st64[-1]["relres"],
-                  "converged": bool(stats[-1]["converged"] and st64[-1]["converged"])},
+                  "converged": bool(stats[-1]["converged"] and st64[-1]["converged"]),
+                  "ordering": a.ordering, "other_ordering": other},
         "setup_s": {"band_and_operator": round(t_band, 3), "precond_fp32": round(t_pc32, 3),
                     "precond_fp64": round(t_pc64, 3)},
         "apply_ms": round(ms_apply, 5),
@@ -306,9 +332,9 @@ def main():
     }
     if a.batched:
         from paper_2110_06322_amd import workloads
-        out["batched"] = batched_leg(cpm, workloads, torch)
+        out["batched"] = batched_leg(cpm, workloads, torch, a.batched_ordering)
     if a.gray_scott > 0:
-        out["gray_scott"] = gray_scott_leg(cpm, torch, a.gray_scott)
+        out["gray_scott"] = gray_scott_leg(cpm, torch, a.gray_scott, a.gs_ordering)
     if not a.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

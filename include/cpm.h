@@ -114,6 +114,9 @@ typedef struct cpm_operator_s cpm_operator;
 /* Uploads the band (closest points, brick map, tiles) to device memory
  * owned by the operator. The band may be destroyed afterwards. c > 0. */
 cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out);
+/* Changes the shift c (> 0) of A = (c + 2d/h^2) I - h^-2 O E. Synchronizes
+ * the device. Later cpm_solve calls use the new shift; a batch takes its
+ * operators' shifts when it is created, so create batches after this call. */
 cpm_status cpm_operator_set_shift(cpm_operator* op, double c);
 double cpm_operator_get_shift(const cpm_operator* op);
 int64_t cpm_operator_n_active(const cpm_operator* op);
@@ -152,9 +155,12 @@ typedef enum { CPM_PREC_FP64 = 0, CPM_PREC_FP32 = 1 } cpm_precision;
  * local graph (default), or decreasing distance |x - cp(x)| of the row's grid
  * node from the surface (ties by grid key). The distance order cuts the
  * dependency chains of the triangular solves about tenfold (as long as the
- * band is thick rather than the subdomain) and each apply about twofold, but
- * the Krylov iteration count grows by 50-85 % on the sphere and torus
- * workloads, so RCM gives the faster solves. */
+ * band is thick rather than the subdomain), but the Krylov iteration count
+ * grows by 50-85 % with ORAS on the sphere and torus workloads. Its wide
+ * levels are stored as packets of up to four same-level rows, solved together
+ * by one wavefront (16 lanes per row); this needs factor rows of at most 192
+ * entries (3-D p = 3 rows have at most 176), else the rows are solved one per
+ * wavefront. */
 typedef enum { CPM_ORDER_RCM = 0, CPM_ORDER_DISTANCE = 1 } cpm_ordering;
 
 typedef struct {
@@ -263,7 +269,8 @@ cpm_status cpm_solve(const cpm_operator* op, const cpm_precond* pc, const double
 typedef struct cpm_batch_s cpm_batch;
 
 /* ops[i], pcs[i] (pcs may be NULL or hold NULLs): borrowed, must outlive
- * the batch; nrhs[i] in {1,2,4}. */
+ * the batch; nrhs[i] in {1,2,4}. Each operator's shift is copied at
+ * creation (see cpm_operator_set_shift). */
 cpm_status cpm_batch_create(int32_t n, const cpm_operator* const* ops,
                             const cpm_precond* const* pcs, const int32_t* nrhs,
                             cpm_batch** out);
@@ -293,7 +300,8 @@ void cpm_batch_destroy(cpm_batch* batch);
  * ------------------------------------------------------------------- */
 typedef struct {
   int32_t apply_variant;     /* 0 pipelined, 1 per tile */
-  int32_t schwarz_variant;   /* 0 completion flags, 1 values as flags */
+  int32_t schwarz_variant;   /* rows one per wavefront: 0 completion flags, 1 values as flags;
+                                packets (distance order): 2 values as flags, 3 completion flags */
   int32_t schwarz_threads;   /* threads per subdomain workgroup */
   int32_t schwarz_sleep;     /* 1 = back off while waiting on a dependency */
   double apply_ms;           /* mean time of one apply with the chosen kernel */

@@ -391,13 +391,11 @@ struct PipeRec {
 };
 
 template <int D>
-__device__ __forceinline__ PipeRec pipe_rec(const DevInst* __restrict__ insts, const WorkItem* __restrict__ work,
-                                            int w, int wave, const Gate& gate) {
-  const WorkItem wi = work[w];
-  const DevTile& T = insts[wi.inst].tiles[wi.idx];
+__device__ __forceinline__ PipeRec pipe_rec(const DevTile* __restrict__ wtiles, int w, int wave, const Gate& gate) {
+  const DevTile& T = wtiles[w];
   PipeRec R;
-  R.inst = wi.inst;
-  if (gate.act && gate_skip(gate, wi.inst)) {   // an instance whose systems have stopped: an empty tile
+  R.inst = T.inst;
+  if (gate.act && gate_skip(gate, R.inst)) {   // an instance whose systems have stopped: an empty tile
     R.s0 = R.s1 = R.fbase = R.fb_off = R.fb_cnt = R.job_off = R.job_cnt = R.oA = 0;
     R.mA = 0ull;
     return R;
@@ -484,7 +482,7 @@ __device__ __forceinline__ void pipe_data(const DevInst* __restrict__ insts, con
 
 template <int D, int P>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_apply_pipe(const DevInst* __restrict__ insts,
-                                                    const WorkItem* __restrict__ work, int nwork, int ucap,
+                                                    const DevTile* __restrict__ wtiles, int nwork, int ucap,
                                                     const double* __restrict__ x, double* __restrict__ y,
                                                     Gate gate) {
   extern __shared__ double smem[];
@@ -511,14 +509,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
   }
 
   // prologue: data of tile w, lists of w+per, record of w+2per
-  PipeRec R0 = pipe_rec<D>(insts, work, w, wave, gate);
+  PipeRec R0 = pipe_rec<D>(wtiles, w, wave, gate);
   PipeList L0 = pipe_list<D>(insts, R0, tid, wave, lane);
   PipeData<D> D0;
   pipe_data<D>(insts, R0, L0, x, l, wave, lane, D0);
   const bool v1 = w + per < w_end, v2 = w + 2 * per < w_end;
-  PipeRec R1 = v1 ? pipe_rec<D>(insts, work, w + per, wave, gate) : R0;
+  PipeRec R1 = v1 ? pipe_rec<D>(wtiles, w + per, wave, gate) : R0;
   PipeList L1 = v1 ? pipe_list<D>(insts, R1, tid, wave, lane) : L0;
-  PipeRec R2 = v2 ? pipe_rec<D>(insts, work, w + 2 * per, wave, gate) : R1;
+  PipeRec R2 = v2 ? pipe_rec<D>(wtiles, w + 2 * per, wave, gate) : R1;
 
 #pragma unroll 1
   for (; w < w_end; w += per) {
@@ -542,7 +540,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     PipeList L2 = L1;
     if (n2) L2 = pipe_list<D>(insts, R2, tid, wave, lane);
     PipeRec R3 = R2;
-    if (n3) R3 = pipe_rec<D>(insts, work, w + 3 * per, wave, gate);
+    if (n3) R3 = pipe_rec<D>(wtiles, w + 3 * per, wave, gate);
     // ---- extension rows of this tile
     if (slot0 >= 0) V[slot0] = erow_lds<D, P>(t0, U, s0, s1, fbase);
     if (slot1 >= 0) {
@@ -721,14 +719,15 @@ static int pipe_grid(int nwork, size_t shm, const void* kern) {
 }
 
 template <int D, int P, int NRHS>
-static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkItem* work, int nwork, int ucap,
-                                 const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s,
-                                 const Gate& gate) {
+static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkItem* work, const DevTile* wtiles,
+                                 int nwork, int ucap, const WorkItem* fb, int nfb, const double* x, double* y,
+                                 hipStream_t s, const Gate& gate) {
   if (nwork > 0) {
     const size_t shm = (size_t)ucap * sizeof(double) + tile_lds_extra<D>();
     if (NRHS == 1 && variant == kApplyPipelined) {
+      if (!wtiles) return hipErrorInvalidValue;
       const int grid = pipe_grid(nwork, shm, (const void*)k_apply_pipe<D, P>);
-      hipLaunchKernelGGL((k_apply_pipe<D, P>), dim3(grid), dim3(512), shm, s, insts, work, nwork, ucap, x, y, gate);
+      hipLaunchKernelGGL((k_apply_pipe<D, P>), dim3(grid), dim3(512), shm, s, insts, wtiles, nwork, ucap, x, y, gate);
     } else {
       hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(nwork), dim3(512), shm, s, insts, work, nwork, ucap, x,
                          y, gate);
@@ -739,12 +738,12 @@ static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkIt
   return hipGetLastError();
 }
 
-hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work, int nwork,
-                        int ucap, const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s,
-                        const Gate& gate) {
+hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work,
+                        const DevTile* wtiles, int nwork, int ucap, const WorkItem* fb, int nfb, const double* x,
+                        double* y, hipStream_t s, const Gate& gate) {
 #define CPM_CASE(D, P, R) \
   if (d == D && p == P && nrhs == R)                                                              \
-    return launch_apply_t<D, P, R>(variant, insts, work, nwork, ucap, fb, nfb, x, y, s, gate);
+    return launch_apply_t<D, P, R>(variant, insts, work, wtiles, nwork, ucap, fb, nfb, x, y, s, gate);
   CPM_CASE(3, 3, 1) CPM_CASE(3, 3, 2) CPM_CASE(3, 3, 4)
   CPM_CASE(3, 2, 1) CPM_CASE(3, 2, 2) CPM_CASE(3, 2, 4)
   CPM_CASE(3, 1, 1) CPM_CASE(3, 1, 2) CPM_CASE(3, 1, 4)

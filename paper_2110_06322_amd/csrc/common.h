@@ -54,9 +54,11 @@ struct DevBuf {
 
 // kernel launchers (apply.hip)
 // gate: lets Krylov cycles skip instances whose systems have stopped (see Gate)
-hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work, int nwork,
-                        int ucap, const WorkItem* fb, int nfb, const double* x, double* y, hipStream_t s,
-                        const Gate& gate = Gate{});
+// wtiles[w]: copy of the tile of work item w (with its instance), read by the
+// pipelined kernel in one load instead of a work item -> instance -> tile chain
+hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work,
+                        const DevTile* wtiles, int nwork, int ucap, const WorkItem* fb, int nfb, const double* x,
+                        double* y, hipStream_t s, const Gate& gate = Gate{});
 hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream_t s);
 hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* zscratch, double* y,
                           hipStream_t s, const Gate& gate = Gate{}, int inst = 0);
@@ -86,6 +88,7 @@ struct cpm_operator_s {
   std::vector<cpm::DevTile> tiles;          // host copy
   std::vector<int32_t> tile_fvol;           // footprint nodes per tile
   cpm::DevBuf<cpm::WorkItem> d_work, d_fb;      // (instance 0, tile) lists: LDS path / fallback
+  cpm::DevBuf<cpm::DevTile> d_wtiles;           // tiles of d_work in work order
   std::vector<cpm::WorkItem> h_work, h_fb;
   int nwork = 0, nfb = 0, ucap = 0;
   int apply_variant = cpm::kApplyPipelined;   // one-RHS apply kernel (tunable)

@@ -16,7 +16,7 @@ struct DevTile {
   int32_t job_off;     // extension-row jobs jobs[job_off .. job_off+job_cnt)
   int32_t job_cnt;
   int32_t fvol;        // doubles of LDS the footprint box occupies (with padding)
-  int32_t pad;
+  int32_t inst;        // instance of the tile in work-ordered copies (0 in an operator's own list)
   int32_t oA[8];       // the tile's bricks (3-D index bx*4+by*2+bz, 2-D bx*2+by):
   uint64_t mA[8];      //   first Sigma_A index and Sigma_A occupancy (0 when absent)
 };

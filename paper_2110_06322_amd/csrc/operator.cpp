@@ -283,6 +283,15 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
       }
     }
     op->d_work.upload(fast);
+    {
+      std::vector<DevTile> wt;
+      wt.reserve(fast.size());
+      for (const WorkItem& wi : fast) {
+        wt.push_back(op->tiles[wi.idx]);
+        wt.back().inst = 0;
+      }
+      op->d_wtiles.upload(wt);
+    }
     op->d_fb.upload(slow);
     op->h_work = fast;
     op->h_fb = slow;
@@ -308,6 +317,9 @@ cpm_status cpm_operator_set_shift(cpm_operator* op, double c) {
     op->c = c;
     op->I.diag = c + 2.0 * op->I.d / (op->I.h * op->I.h);
     op->d_inst.upload(&op->I, 1);
+    // the cached single-solve batch holds a copy of the old shift
+    op->solve_cache.reset();
+    op->solve_cache_key = -1;
     return CPM_OK;
   } catch (const Error& e) {
     set_error(e.msg);
@@ -336,7 +348,7 @@ cpm_status cpm_apply(const cpm_operator* op, const double* x, double* y, int32_t
     if (!op || !x || !y) fail(CPM_ERR_ARG, "null argument");
     if (nrhs != 1 && nrhs != 2 && nrhs != 4) fail(CPM_ERR_ARG, "nrhs must be 1, 2 or 4");
     if (x == y) fail(CPM_ERR_ARG, "x and y must not alias");
-    hip_check(launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->nwork, op->ucap,
+    hip_check(launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->d_wtiles.p, op->nwork, op->ucap,
                            op->d_fb.p, op->nfb, x, y, (hipStream_t)stream),
               "cpm_apply");
     return CPM_OK;

@@ -322,8 +322,9 @@ std::vector<int32_t> rcm_order(int n, const std::vector<int64_t>& ptr, const std
 }
 
 // rows in increasing dependency level (a topological order of the sweep)
+// (levpos, when given, receives the level of the row at each schedule position)
 std::vector<uint16_t> schedule(int n, const std::vector<int64_t>& ptr, const std::vector<uint16_t>& col, bool lower,
-                               int& nlev) {
+                               int& nlev, std::vector<int32_t>* levpos = nullptr) {
   std::vector<int> lev(n, 0);
   nlev = 0;
   for (int t = 0; t < n; ++t) {
@@ -339,6 +340,10 @@ std::vector<uint16_t> schedule(int n, const std::vector<int64_t>& ptr, const std
     if (lev[a] != lev[b]) return lev[a] < lev[b];
     return lower ? a < b : a > b;
   });
+  if (levpos) {
+    levpos->resize(n);
+    for (int t = 0; t < n; ++t) (*levpos)[t] = lev[s[t]];
+  }
   return s;
 }
 
@@ -537,8 +542,8 @@ void build_schwarz_host(const cpm_band_s& B, double c, const cpm_precond_opts& o
           }
         }
         int ll = 0, lu = 0;
-        sub.schedL = schedule(n, sub.lptr, sub.lcol, true, ll);
-        sub.schedU = schedule(n, sub.uptr, sub.ucol, false, lu);
+        sub.schedL = schedule(n, sub.lptr, sub.lcol, true, ll, &sub.levL);
+        sub.schedU = schedule(n, sub.uptr, sub.ucol, false, lu, &sub.levU);
         sub.levels = std::max(ll, lu);
         for (int q = 0; q < n; ++q) local[om[q]] = -1;
       } catch (const Error& e) {

@@ -17,6 +17,7 @@ struct SchwarzHost {
     std::vector<int32_t> perm;     // input slot q takes local row perm[q] (key order)
     std::vector<int32_t> operm;    // solution slot q is local row operm[q]
     std::vector<uint16_t> schedL, schedU;  // level-ordered rows of the forward / backward sweeps
+    std::vector<int32_t> levL, levU;       // level of the row at each schedule position
     std::vector<int64_t> lptr, uptr;
     std::vector<uint16_t> lcol, ucol;
     std::vector<double> lval, uval, dinv;
@@ -37,7 +38,10 @@ struct DevSub {
   int64_t row_off;   // into in_idx / out_idx / dinv / recL / recU (n entries)
   int64_t lbase;     // first stored entry of the subdomain in lcol / lval
   int64_t ubase;     // first stored entry in ucol / uval
+  int64_t pk_off;    // first packet of the forward sweep in pk (backward packets follow)
   int32_t n;
+  int32_t npkL;      // packets of the forward / backward sweeps (packet layout only)
+  int32_t npkU;
   int32_t pad;
 };
 
@@ -53,6 +57,7 @@ struct DevPC {
   const int32_t* gL;            // global node of the row at each forward-sweep position
   const uint64_t* recL;         // per subdomain (at row_off): forward sweep records
   const uint64_t* recU;         //   backward sweep records
+  const uint32_t* pk;           // packets of same-level schedule positions (packet layout), else null
   const uint16_t* lcol;
   const uint16_t* ucol;
   const void* lval;
@@ -67,6 +72,16 @@ int64_t next_serial();
 // kernel configuration of the subdomain solves (chosen by the tuner)
 constexpr int kSchwarzFlags = 0;        // LDS value array plus per-row completion flags
 constexpr int kSchwarzValueFlags = 1;   // values double as flags (forward and backward arrays)
+constexpr int kSchwarzPacket = 2;       // values as flags, up to four same-level rows per wavefront
+constexpr int kSchwarzPacketFlags = 3;  // packets with per-row completion flags (less local memory)
+// Packet layout: consecutive schedule positions of one level are grouped into
+// packets of at most kPacketRows rows; a packet word holds its first position
+// (bits 2..31) and its row count minus one (bits 0..1). Each row is solved by
+// kPacketLanes lanes, each taking at most kPacketEntries of its entries.
+constexpr int kPacketRows = 4;
+constexpr int kPacketLanes = 16;
+constexpr int kPacketEntries = 12;
+constexpr int kPacketMaxThreads = 512;   // 32 rows in flight; leaves the kernel 256 registers per lane
 constexpr size_t kSchwarzMaxLds = 160 * 1024;
 struct SchwarzCfg {
   int variant = kSchwarzValueFlags;
@@ -90,6 +105,8 @@ struct cpm_precond_s {
   cpm::DevBuf<cpm::DevSub> d_subs;
   cpm::DevBuf<int32_t> d_in, d_out, d_err, d_gL;
   cpm::DevBuf<uint64_t> d_recL, d_recU;
+  cpm::DevBuf<uint32_t> d_pk;
+  bool packets = false;         // factor rows grouped into packets (the packet kernel runs)
   cpm::DevBuf<uint16_t> d_lcol, d_ucol;
   cpm::DevBuf<char> d_lval, d_uval, d_dinv;
   cpm::DevBuf<cpm::WorkItem> d_work;

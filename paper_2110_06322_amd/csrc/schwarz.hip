@@ -415,6 +415,251 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz_v(const DevPC* __re
   }
 }
 
+// ---- packet variant
+//
+// For orderings whose levels hold many rows (the distance order), a wavefront
+// takes a packet of up to four rows of one level at once: lane group g (16
+// lanes) solves the packet's row g, lane t of the group taking entries t,
+// t+16, ..., t+176 (rows of up to 192 entries). The dependencies of a row are all issued before the first
+// wait, re-polled together until none reads the sentinel, and the group's sum is
+// formed in a fixed order (entries of a lane in increasing order, then a DPP
+// prefix sum over the 16 lanes). Rows of one packet never depend on each other,
+// and packets follow the level order, so the earliest unfinished packet always
+// has its inputs: the sweep always advances.
+template <class T, int NRHS>
+struct PacketRow {
+  uint64_t rec;
+  int len;                     // stored entries of the group's row (0 for an empty slot)
+  bool live;                   // the group has a row in this packet
+  int k[kPacketEntries];
+  T v[kPacketEntries];
+  T own[NRHS];
+  T dq;
+};
+
+template <class T>
+__device__ __forceinline__ T row16_sum_to_15(T v) {
+  v += dpp_any<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_any<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_any<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_any<0x118, 0xf>(v);   // row_shr:8
+  return v;                      // lane 15 of each 16-lane row holds the row total
+}
+
+// FLAGS = false: values double as flags (dst starts filled with the sentinel,
+// yv holds the forward result in the backward sweep). FLAGS = true: one value
+// array (dst = yv, solved in place) and per-row completion flags `done`
+// (forward publishes level 1, backward level 2); less local memory, one more
+// LDS round trip per dependency, the same arithmetic in the same order.
+template <class T, int NRHS, bool BACKWARD, bool SLEEP, bool FLAGS>
+__device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, const uint32_t* __restrict__ pk_,
+                                        const uint64_t* __restrict__ rec_, const uint16_t* __restrict__ col_,
+                                        const T* __restrict__ val_, const T* __restrict__ dinv_,
+                                        const int32_t* __restrict__ gsched_, const double* __restrict__ rb_,
+                                        const T* yv, T* dst, int* done, int32_t* err) {
+  constexpr int LEVEL = BACKWARD ? 2 : 1;
+  using Bits = typename Sentinel<T>::Bits;
+  const auto pk = gmem(pk_);
+  const auto rec = gmem(rec_);
+  const auto col = gmem(col_);
+  const auto val = gmem(val_);
+  const auto dinv = gmem(dinv_);
+  const auto gsched = gmem(gsched_);
+  const auto rb = gmem(rb_);
+  int p = wave;
+  if (p >= npk) return;
+  const int last = npk - 1;
+  const int g = lane >> 4, t = lane & 15;
+  // schedule position of this lane group's row in a packet (clamped into the packet)
+  auto posof = [&](uint32_t w) { return (int)(w >> 2) + min(g, (int)(w & 3u)); };
+  auto fetch = [&](PacketRow<T, NRHS>& D, uint32_t w, uint64_t r, int gi) {
+    D.rec = r;
+    const int len = (int)((r >> 32) & 0xffff);
+    D.live = g <= (int)(w & 3u);
+    D.len = D.live ? len : 0;
+    const int64_t off = (int64_t)(r & 0xffffffffull);
+    const int hi = max(len - 1, 0);
+#pragma unroll
+    for (int j = 0; j < kPacketEntries; ++j) {
+      const int64_t e = off + min(t + kPacketLanes * j, hi);
+      D.k[j] = col[e];
+      D.v[j] = val[e];
+    }
+    if (BACKWARD) {
+      D.dq = dinv[(int)(r >> 48)];
+    } else {
+      D.dq = (T)0;
+#pragma unroll
+      for (int q = 0; q < NRHS; ++q) D.own[q] = (T)rb[(int64_t)gi * NRHS + q];
+    }
+  };
+  auto solve_row = [&](PacketRow<T, NRHS>& D) {
+    const int q = (int)(D.rec >> 48);
+    if (BACKWARD) {
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) D.own[r] = yv[(size_t)q * NRHS + r];   // y_q, complete before this sweep
+    }
+    // wait for every dependency: all polls issued together, pending ones re-polled
+    Bits b[kPacketEntries];
+    int spins = 0;
+    if constexpr (FLAGS) {
+      int f[kPacketEntries];
+#pragma unroll
+      for (int j = 0; j < kPacketEntries; ++j)
+        f[j] = t + kPacketLanes * j < D.len
+                   ? __hip_atomic_load(done + D.k[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                   : LEVEL;
+      for (;;) {
+        bool pending = false;
+#pragma unroll
+        for (int j = 0; j < kPacketEntries; ++j) pending |= f[j] < LEVEL;
+        if (!pending) break;
+        if (SLEEP) __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+#pragma unroll
+        for (int j = 0; j < kPacketEntries; ++j)
+          if (f[j] < LEVEL) f[j] = __hip_atomic_load(done + D.k[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+#pragma unroll
+      for (int j = 0; j < kPacketEntries; ++j)
+        b[j] = t + kPacketLanes * j < D.len ? to_bits<T>(dst[(size_t)D.k[j] * NRHS]) : (Bits)0;
+    } else {
+      const Bits sent = Sentinel<T>::kBits;
+#pragma unroll
+      for (int j = 0; j < kPacketEntries; ++j)
+        b[j] = t + kPacketLanes * j < D.len
+                   ? __hip_atomic_load(reinterpret_cast<Bits*>(dst + (size_t)D.k[j] * NRHS), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP)
+                   : (Bits)0;
+      for (;;) {
+        bool pending = false;
+#pragma unroll
+        for (int j = 0; j < kPacketEntries; ++j) pending |= b[j] == sent;
+        if (!pending) break;
+        if (SLEEP) __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+          for (int j = 0; j < kPacketEntries; ++j) b[j] = 0;
+          break;
+        }
+#pragma unroll
+        for (int j = 0; j < kPacketEntries; ++j)
+          if (b[j] == sent)
+            b[j] = __hip_atomic_load(reinterpret_cast<Bits*>(dst + (size_t)D.k[j] * NRHS), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    }
+    T acc[NRHS];
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) acc[r] = (T)0;
+#pragma unroll
+    for (int j = 0; j < kPacketEntries; ++j) {
+      if (t + kPacketLanes * j < D.len) {
+        acc[0] += D.v[j] * bits_to<T>(b[j]);
+#pragma unroll
+        for (int r = 1; r < NRHS; ++r) acc[r] += D.v[j] * dst[(size_t)D.k[j] * NRHS + r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) acc[r] = row16_sum_to_15(acc[r]);
+    if (t == kPacketLanes - 1 && D.live) {
+      T out[NRHS];
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) out[r] = BACKWARD ? (D.own[r] - acc[r]) * D.dq : D.own[r] - acc[r];
+      if constexpr (FLAGS) {
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) dst[(size_t)q * NRHS + r] = out[r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __hip_atomic_store(done + q, LEVEL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      } else {
+#pragma unroll
+        for (int r = 1; r < NRHS; ++r) dst[(size_t)q * NRHS + r] = out[r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __hip_atomic_store(reinterpret_cast<Bits*>(dst + (size_t)q * NRHS), to_bits<T>(out[0]), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  };
+  // packet words three packets ahead, records two ahead, entries one ahead
+  PacketRow<T, NRHS> A, B;
+  uint32_t w1 = pk[min(p + nw, last)], w2 = pk[min(p + 2 * nw, last)];
+  uint64_t r1 = rec[posof(w1)];
+  int g1 = BACKWARD ? 0 : gsched[posof(w1)];
+  {
+    const uint32_t w0 = pk[p];
+    fetch(A, w0, rec[posof(w0)], BACKWARD ? 0 : gsched[posof(w0)]);
+  }
+  auto step = [&](PacketRow<T, NRHS>& cur, PacketRow<T, NRHS>& nxt) {
+    const uint64_t r2 = rec[posof(w2)];
+    const int g2 = BACKWARD ? 0 : gsched[posof(w2)];
+    const uint32_t w3 = pk[min(p + 3 * nw, last)];
+    fetch(nxt, w1, r1, g1);
+    solve_row(cur);
+    if (p + nw > last) return false;
+    p += nw;
+    w1 = w2;
+    r1 = r2;
+    g1 = g2;
+    w2 = w3;
+    return true;
+  };
+  while (step(A, B) && step(B, A)) {
+  }
+}
+
+template <class T, int NRHS, bool SLEEP, bool FLAGS>
+__global__ void __launch_bounds__(kPacketMaxThreads) k_schwarz_p(const DevPC* __restrict__ pcs,
+                                                              const WorkItem* __restrict__ work, int nwork,
+                                                              const double* __restrict__ rin,
+                                                              double* __restrict__ zout, Gate gate) {
+  extern __shared__ double smem_d[];
+  if ((int)blockIdx.x >= nwork) return;
+  const WorkItem wi = work[blockIdx.x];
+  if (gate_skip(gate, wi.inst)) return;
+  const DevPC& P = pcs[wi.inst];
+  const DevSub sub = P.subs[wi.idx];
+  const int n = sub.n;
+  T* yv = reinterpret_cast<T*>(smem_d);
+  T* zv = FLAGS ? yv : yv + (size_t)n * NRHS;                // FLAGS: solved in place
+  int* done = reinterpret_cast<int*>(yv + (size_t)n * NRHS); // FLAGS only
+  const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id(), nw = blockDim.x >> 6;
+  const int32_t* out_idx = P.out_idx + sub.row_off;
+  const T* lv = reinterpret_cast<const T*>(P.lval) + sub.lbase;
+  const T* uv = reinterpret_cast<const T*>(P.uval) + sub.ubase;
+  const T* di = reinterpret_cast<const T*>(P.dinv) + sub.row_off;
+  const double* rb = rin + P.vec_off * NRHS;
+  double* zb = zout + P.vec_off * NRHS;
+  if (FLAGS) {
+    for (int q = tid; q < n; q += blockDim.x) done[q] = 0;
+  } else {
+    const T sent = bits_to<T>(Sentinel<T>::kBits);
+    for (int q = tid; q < 2 * n * NRHS; q += blockDim.x) yv[q] = sent;
+  }
+  __syncthreads();
+  sweep_p<T, NRHS, false, SLEEP, FLAGS>(sub.npkL, wave, nw, lane, P.pk + sub.pk_off, P.recL + sub.row_off,
+                                        P.lcol + sub.lbase, lv, nullptr, P.gL + sub.row_off, rb, nullptr, yv, done,
+                                        P.error_flag);
+  __syncthreads();
+  sweep_p<T, NRHS, true, SLEEP, FLAGS>(sub.npkU, wave, nw, lane, P.pk + sub.pk_off + sub.npkL,
+                                       P.recU + sub.row_off, P.ucol + sub.ubase, uv, di, nullptr, nullptr, yv, zv,
+                                       done, P.error_flag);
+  __syncthreads();
+  for (int q = tid; q < n; q += blockDim.x) {
+    const int32_t o = out_idx[q];
+    if (o < 0) {
+      const int64_t g = o & 0x7fffffff;
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) zb[g * NRHS + r] = (double)zv[(size_t)q * NRHS + r];
+    }
+  }
+}
+
 static hipError_t lds_ok(const void* kern, size_t shm) {
   int dev = 0, lim = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -429,6 +674,34 @@ template <class T, int NRHS>
 static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
                            int max_len, const double* r, double* z, hipStream_t s, const Gate& gate) {
   const int threads = cfg.threads > 0 ? cfg.threads : kSchwarzThreads;
+  if (cfg.variant == kSchwarzPacket || cfg.variant == kSchwarzPacketFlags) {
+    // packet factors: the value form when its two arrays fit, else the flag form
+    // (the same arithmetic); rows longer than a packet's lanes take are not packed
+    if (max_len > kPacketLanes * kPacketEntries || threads > kPacketMaxThreads) return hipErrorInvalidValue;
+    const bool flags = cfg.variant == kSchwarzPacketFlags ||
+                       schwarz_value_lds(max_rows, NRHS, sizeof(T)) > kSchwarzMaxLds;
+    const size_t shm = flags ? (size_t)max_rows * (NRHS * sizeof(T) + sizeof(int))
+                             : schwarz_value_lds(max_rows, NRHS, sizeof(T));
+    const void* kern = flags ? (cfg.sleep ? (const void*)k_schwarz_p<T, NRHS, true, true>
+                                          : (const void*)k_schwarz_p<T, NRHS, false, true>)
+                             : (cfg.sleep ? (const void*)k_schwarz_p<T, NRHS, true, false>
+                                          : (const void*)k_schwarz_p<T, NRHS, false, false>);
+    hipError_t e = lds_ok(kern, shm);
+    if (e != hipSuccess) return e;
+    if (flags && cfg.sleep)
+      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, true, true>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r,
+                         z, gate);
+    else if (flags)
+      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, false, true>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r,
+                         z, gate);
+    else if (cfg.sleep)
+      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, true, false>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r,
+                         z, gate);
+    else
+      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, false, false>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork,
+                         r, z, gate);
+    return hipGetLastError();
+  }
   if (cfg.variant == kSchwarzValueFlags && max_len <= kSchwarzValueMaxLen &&
       schwarz_value_lds(max_rows, NRHS, sizeof(T)) <= kSchwarzMaxLds) {
     const size_t shm = schwarz_value_lds(max_rows, NRHS, sizeof(T));

@@ -54,6 +54,9 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     std::vector<DevSub> subs(np);
     std::vector<int32_t> in_idx, out_idx, gL;
     std::vector<uint64_t> recL, recU;
+    std::vector<uint32_t> pk;
+    // the distance order's levels are wide: pack same-level rows for the packet kernel
+    const bool want_packets = opts->ordering == CPM_ORDER_DISTANCE && opts->subsolver == CPM_SUB_ILU0;
     std::vector<uint16_t> lcol, ucol;
     std::vector<double> lval, uval;
     int64_t row_off = 0;
@@ -63,6 +66,8 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
       subs[j].lbase = (int64_t)lcol.size();
       subs[j].ubase = (int64_t)ucol.size();
       subs[j].n = s.n;
+      subs[j].pk_off = (int64_t)pk.size();
+      subs[j].npkL = subs[j].npkU = 0;
       subs[j].pad = 0;
       for (int q = 0; q < s.n; ++q) {
         in_idx.push_back(s.rows[s.perm[q]]);
@@ -92,6 +97,19 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
           ov.insert(ov.end(), vs.begin() + b, vs.begin() + e);
         }
       }
+      if (want_packets) {
+        for (int lower = 1; lower >= 0; --lower) {
+          const auto& lev = lower ? s.levL : s.levU;
+          int32_t& count = lower ? subs[j].npkL : subs[j].npkU;
+          for (int t = 0; t < s.n;) {
+            int c = 1;
+            while (c < kPacketRows && t + c < s.n && lev[t + c] == lev[t]) ++c;
+            pk.push_back(((uint32_t)t << 2) | (uint32_t)(c - 1));
+            ++count;
+            t += c;
+          }
+        }
+      }
       row_off += s.n;
       pc->max_rows = std::max(pc->max_rows, s.n);
       pc->max_levels = std::max(pc->max_levels, s.levels);
@@ -109,6 +127,12 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     pc->d_out.upload(out_idx);
     pc->d_recL.upload(recL);
     pc->d_recU.upload(recU);
+    pc->packets = want_packets && pc->max_len <= kPacketLanes * kPacketEntries;
+    if (pc->packets) {
+      pc->d_pk.upload(pk);
+      pc->cfg.variant = kSchwarzPacket;
+      pc->cfg.threads = kPacketMaxThreads;
+    }
     pc->d_lcol.upload(lcol);
     pc->d_ucol.upload(ucol);
     const bool fp32 = opts->precision == CPM_PREC_FP32;
@@ -129,6 +153,8 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
       std::vector<int32_t>().swap(s.operm);
       std::vector<uint16_t>().swap(s.schedL);
       std::vector<uint16_t>().swap(s.schedU);
+      std::vector<int32_t>().swap(s.levL);
+      std::vector<int32_t>().swap(s.levU);
     }
     DevPC& P = pc->P;
     std::memset(&P, 0, sizeof(P));
@@ -140,6 +166,7 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     P.gL = pc->d_gL.p;
     P.recL = pc->d_recL.p;
     P.recU = pc->d_recU.p;
+    P.pk = pc->packets ? pc->d_pk.p : nullptr;
     P.lcol = pc->d_lcol.p;
     P.ucol = pc->d_ucol.p;
     P.lval = pc->d_lval.p;

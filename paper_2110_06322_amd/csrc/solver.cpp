@@ -33,11 +33,12 @@ struct cpm_batch_s {
   std::vector<DevInst> hinst;
   DevBuf<DevInst> d_insts;
   DevBuf<WorkItem> d_work, d_fb;
+  DevBuf<DevTile> d_wtiles;   // tiles of d_work in work order, with their instance
   int nwork = 0, nfb = 0, ucap = 0;
   int apply_variant = kApplyPipelined;
   SchwarzCfg pc_cfg;
   // preconditioners
-  bool any_pc = false, all_pc = true;
+  bool any_pc = false, all_pc = true, pc_packets = false;
   int pc_fp32 = 0, pc_transpose = -1, max_rows = 0, max_len = 0, npcwork = 0;
   DevBuf<DevPC> d_pcs;
   DevBuf<WorkItem> d_pcwork;
@@ -107,7 +108,10 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
       if (Bt.any_pc && pc->P.fp32 != Bt.pc_fp32) fail(CPM_ERR_ARG, "mixed preconditioner precisions in one batch");
       if (Bt.pc_transpose >= 0 && pc->opts.transpose != Bt.pc_transpose)
         fail(CPM_ERR_ARG, "mixed transposed / plain preconditioners in one batch");
+      if (Bt.any_pc && pc->packets != Bt.pc_packets)
+        fail(CPM_ERR_ARG, "mixed row orderings (packet and row layouts) in one batch");
       if (!Bt.any_pc) Bt.pc_cfg = pc->cfg;
+      Bt.pc_packets = pc->packets;
       Bt.pc_fp32 = pc->P.fp32;
       Bt.pc_transpose = pc->opts.transpose;
       Bt.any_pc = true;
@@ -126,6 +130,15 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
   Bt.Ntot = Bt.off[n];
   Bt.d_insts.upload(Bt.hinst);
   Bt.d_work.upload(fast);
+  {
+    std::vector<DevTile> wt;
+    wt.reserve(fast.size());
+    for (const WorkItem& wi : fast) {
+      wt.push_back(ops[wi.inst]->tiles[wi.idx]);
+      wt.back().inst = wi.inst;
+    }
+    Bt.d_wtiles.upload(wt);
+  }
   Bt.d_fb.upload(slow);
   Bt.nwork = (int)fast.size();
   Bt.nfb = (int)slow.size();
@@ -205,7 +218,7 @@ GmresState state_of(cpm_batch_s& Bt, int m) {
 void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hipStream_t s,
                  const Gate& gate = Gate{}) {
   if (!transpose) {
-    hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
+    hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.d_wtiles.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
                            Bt.nfb, x, y, s, gate),
               "operator apply");
     return;
@@ -609,7 +622,7 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
           Bt.apply_variant = v;
           const double ms = tune::time_ms(
               [&] {
-                return launch_apply(Bt.d, Bt.p, Bt.R, v, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
+                return launch_apply(Bt.d, Bt.p, Bt.R, v, Bt.d_insts.p, Bt.d_work.p, Bt.d_wtiles.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
                                     Bt.nfb, Bt.r.p, Bt.w.p, s);
               },
               reps, s);
@@ -622,7 +635,7 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
       out->apply_variant = Bt.apply_variant;
       out->apply_ms = tune::time_ms(
           [&] {
-            return launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.nwork, Bt.ucap,
+            return launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.d_wtiles.p, Bt.nwork, Bt.ucap,
                                 Bt.d_fb.p, Bt.nfb, Bt.r.p, Bt.w.p, s);
           },
           reps, s);
@@ -632,15 +645,15 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
       for (auto* pc : Bt.pcs)
         if (pc) max_levels = std::max(max_levels, pc->max_levels);
       char key[220];
-      std::snprintf(key, sizeof key, "batch-schwarz|%s|%s|r%d|rows2^%d|levels2^%d|parts2^%d", dev.c_str(),
-                    Bt.pc_fp32 ? "fp32" : "fp64", Bt.R, tune::log2i(Bt.max_rows), tune::log2i(max_levels),
+      std::snprintf(key, sizeof key, "batch-schwarz|%s|%s%s|r%d|rows2^%d|levels2^%d|parts2^%d", dev.c_str(),
+                    Bt.pc_fp32 ? "fp32" : "fp64", Bt.pc_packets ? "|packets" : "", Bt.R, tune::log2i(Bt.max_rows), tune::log2i(max_levels),
                     tune::log2i(Bt.npcwork));
       auto it = cache.find(key);
       auto run = [&] {
         return launch_schwarz(Bt.pc_cfg, Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.max_len, Bt.pc_fp32,
                               Bt.R, Bt.r.p, Bt.w.p, s);
       };
-      if (!force && it != cache.end() && tune::valid_schwarz(it->second)) {
+      if (!force && it != cache.end() && tune::valid_schwarz(it->second, Bt.pc_packets)) {
         Bt.pc_cfg.variant = it->second[0];
         Bt.pc_cfg.threads = it->second[1];
         Bt.pc_cfg.sleep = it->second[2];
@@ -648,7 +661,7 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
         all_cached = false;
         double best = 1e30;
         SchwarzCfg bestc = Bt.pc_cfg;
-        for (const SchwarzCfg& c : tune::schwarz_candidates()) {
+        for (const SchwarzCfg& c : tune::schwarz_candidates(Bt.pc_packets)) {
           Bt.pc_cfg = c;
           const double ms = tune::time_ms(run, reps, s);
           if (ms < best) { best = ms; bestc = c; }

@@ -97,17 +97,25 @@ void write_cache(const char* path, const Cache& c) {
 
 int log2i(double v) { return v <= 1 ? 0 : (int)std::lround(std::log2(v)); }
 
-bool valid_schwarz(const std::vector<int>& v) {
-  return v.size() == 3 && (v[0] == kSchwarzFlags || v[0] == kSchwarzValueFlags) && v[1] >= 64 && v[1] <= 1024 &&
-         v[1] % 64 == 0 && (v[2] == 0 || v[2] == 1);
+bool valid_schwarz(const std::vector<int>& v, bool packets) {
+  if (v.size() != 3) return false;
+  const bool variant_ok = packets ? (v[0] == kSchwarzPacket || v[0] == kSchwarzPacketFlags)
+                                  : (v[0] == kSchwarzFlags || v[0] == kSchwarzValueFlags);
+  return variant_ok && v[1] >= 64 && v[1] <= (packets ? kPacketMaxThreads : 1024) && v[1] % 64 == 0 &&
+         (v[2] == 0 || v[2] == 1);
 }
 
-std::vector<SchwarzCfg> schwarz_candidates() {
+// The packet kernels sum a row in another order than the two one-row-per-
+// wavefront kernels, so only they are candidates for a packet layout.
+std::vector<SchwarzCfg> schwarz_candidates(bool packets) {
   std::vector<SchwarzCfg> out;
-  for (int variant : {kSchwarzFlags, kSchwarzValueFlags})
+  const std::vector<int> variants = packets ? std::vector<int>{kSchwarzPacket, kSchwarzPacketFlags}
+                                            : std::vector<int>{kSchwarzFlags, kSchwarzValueFlags};
+  for (int variant : variants)
     for (int threads : {256, 512, 1024})
       for (int sleep : {0, 1}) {
         if (variant == kSchwarzFlags && sleep == 0) continue;   // the flag kernel always backs off
+        if (packets && threads > kPacketMaxThreads) continue;
         SchwarzCfg c;
         c.variant = variant;
         c.threads = threads;
@@ -187,7 +195,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
           const int v = cand[c];
           const double ms = time_ms(
               [&] {
-                return launch_apply(op->I.d, op->I.p, nrhs, v, op->d_inst.p, op->d_work.p, op->nwork, op->ucap,
+                return launch_apply(op->I.d, op->I.p, nrhs, v, op->d_inst.p, op->d_work.p, op->d_wtiles.p, op->nwork, op->ucap,
                                     op->d_fb.p, op->nfb, x.p, y.p, s);
               },
               reps, s);
@@ -199,7 +207,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
       }
       out->apply_variant = op->apply_variant;
       auto f = [&] {
-        return launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->nwork,
+        return launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->d_wtiles.p, op->nwork,
                             op->ucap, op->d_fb.p, op->nfb, x.p, y.p, s);
       };
       out->apply_ms = time_ms(f, reps, s);
@@ -208,11 +216,11 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
     // ---- subdomain solves
     if (pc) {
       char key[200];
-      std::snprintf(key, sizeof key, "schwarz|%s|%s|r%d|rows2^%d|levels2^%d|parts2^%d", dev.c_str(),
-                    pc->P.fp32 ? "fp32" : "fp64", nrhs, log2i((double)pc->max_rows), log2i((double)pc->max_levels),
+      std::snprintf(key, sizeof key, "schwarz|%s|%s%s|r%d|rows2^%d|levels2^%d|parts2^%d", dev.c_str(),
+                    pc->P.fp32 ? "fp32" : "fp64", pc->packets ? "|packets" : "", nrhs, log2i((double)pc->max_rows), log2i((double)pc->max_levels),
                     log2i((double)pc->host.nparts));
       auto it = cache.find(key);
-      if (!force && it != cache.end() && valid_schwarz(it->second)) {
+      if (!force && it != cache.end() && valid_schwarz(it->second, pc->packets)) {
         pc->cfg.variant = it->second[0];
         pc->cfg.threads = it->second[1];
         pc->cfg.sleep = it->second[2];
@@ -220,7 +228,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
         all_cached = false;
         double best = 1e30;
         SchwarzCfg bestc = pc->cfg;
-        for (const SchwarzCfg& c : schwarz_candidates()) {
+        for (const SchwarzCfg& c : schwarz_candidates(pc->packets)) {
           pc->cfg = c;
           const double ms = time_ms([&] { return precond_apply_raw(pc, x.p, y.p, nrhs, s); }, reps, s);
           if (ms < best) { best = ms; bestc = c; }

@@ -19,8 +19,10 @@ Cache read_cache(const char* path);                  // empty when missing or un
 void write_cache(const char* path, const Cache& c);  // no-op for a null path
 int log2i(double v);
 std::string device_tag();                            // e.g. "gfx950-cu256"
-bool valid_schwarz(const std::vector<int>& v);       // a cached subdomain-solve entry
-std::vector<SchwarzCfg> schwarz_candidates();
+// a cached subdomain-solve entry, for preconditioners with or without the packet layout
+bool valid_schwarz(const std::vector<int>& v, bool packets);
+// candidate kernels; all candidates for one layout compute bit-identical results
+std::vector<SchwarzCfg> schwarz_candidates(bool packets);
 // mean milliseconds of `reps` launches of f after two warm-up launches
 double time_ms(const std::function<hipError_t()>& f, int reps, hipStream_t s);
 

@@ -20,11 +20,11 @@ from ._capi import check, lib
 class GrayScott:
     def __init__(self, band: cpm.Band, mu=(2e-5, 1e-5), F=0.04, k=0.06, dt=1.0, n_parts=1024,
                  kind="oras", precision="fp32", mode="mixed", rtol=1e-8, seed=5, device="cuda", tune=False,
-                 tune_cache=None):
+                 tune_cache=None, ordering="rcm"):
         self.band, self.mu, self.F, self.k, self.dt = band, tuple(mu), F, k, dt
         self.rtol, self.mode = rtol, mode
         self.ops = [cpm.Operator(band, 1.0 / (m * dt)) for m in self.mu]
-        self.pcs = [cpm.Precond(op, kind=kind, n_parts=n_parts, overlap=2.0, precision=precision)
+        self.pcs = [cpm.Precond(op, kind=kind, n_parts=n_parts, overlap=2.0, precision=precision, ordering=ordering)
                     for op in self.ops] if n_parts > 0 else [None, None]
         self.batch = cpm.Batch(self.ops, self.pcs, [1, 1])
         self.tuning = self.batch.autotune(cache=tune_cache) if tune else None

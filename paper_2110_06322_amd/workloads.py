@@ -54,14 +54,14 @@ def sphere(precision="fp64", kind="oras", h=0.02, n_parts=64, device="cuda") -> 
 
 
 def batched(n_each=16, hs=(0.04, 0.02, 0.01), nrhs=4, precision="fp32", kind="oras", seed=3,
-            n_sub_range=(32, 512), device="cuda") -> list[Instance]:
+            n_sub_range=(32, 512), device="cuda", ordering="rcm") -> list[Instance]:
     out = []
     for i, spec in enumerate(inputs.batch_instances(seed=seed, n_each=n_each, hs=hs)):
         box = inputs.domain_box(spec["kind"], spec["params"], 3, spec["h"], 3)
         b = cpm.Band(spec["kind"], spec["params"], 3, spec["h"], 3, lo=box[0], hi=box[1])
         op = cpm.Operator(b, spec["c"])
         ns = inputs.n_subdomains_for(b.n_active, *n_sub_range)
-        pc = cpm.Precond(op, kind=kind, n_parts=ns, overlap=2.0, precision=precision)
+        pc = cpm.Precond(op, kind=kind, n_parts=ns, overlap=2.0, precision=precision, ordering=ordering)
         keys = b.active_keys
         F = np.stack([inputs.normal(seed * 1000 + i, r, keys) for r in range(nrhs)], axis=1)
         f = torch.tensor(np.ascontiguousarray(F).reshape(-1), dtype=torch.float64, device=device)

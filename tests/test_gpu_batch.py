@@ -72,3 +72,24 @@ def test_batch_rejects_mixed_dimensions():
     ops = [cpm.Operator(b2, 1.0), cpm.Operator(b3, 1.0)]
     with pytest.raises(Exception):
         cpm.Batch(ops, None, [1, 1])
+
+
+def test_batch_packet_layout_equals_solo():
+    """Distance-ordered factors (packet kernel) in a batch: each system equals its solo solve."""
+    insts = workloads.batched(n_each=1, hs=(0.05,), nrhs=4, n_sub_range=(4, 8), ordering="distance")
+    b = cpm.Batch([i.op for i in insts], [i.pc for i in insts], [4] * len(insts))
+    assert b.autotune()["schwarz_variant"] in (2, 3)
+    us, stats = b.solve([i.f for i in insts], rtol=1e-8, mode="mixed", max_it=5000)
+    assert all(s["converged"] for s in stats), stats
+    for k, inst in enumerate(insts):
+        u1, st1 = cpm.solve(inst.op, inst.f, pc=inst.pc, nrhs=4, rtol=1e-8, mode="mixed", max_it=5000)
+        assert torch.equal(us[k], u1), k
+
+
+def test_batch_rejects_mixed_layouts():
+    G.ensure_built()
+    b = cpm.Band("sphere", (1.0,), 3, 0.1, 3)
+    op = cpm.Operator(b, 1.0)
+    pcs = [cpm.Precond(op, n_parts=4, ordering=o) for o in ("rcm", "distance")]
+    with pytest.raises(Exception):
+        cpm.Batch([op, op], pcs, [1, 1])

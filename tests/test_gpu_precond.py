@@ -74,9 +74,11 @@ def test_precond_parity_small(pc_kind, precision, subsolver, transpose, ordering
     assert np.array_equal(z, z2)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("ordering", ["rcm", "distance"])
 @pytest.mark.parametrize("nrhs", [2, 4])
-def test_precond_multi_rhs_matches_single(nrhs):
-    lb, ob, A, P, keys, pos, op, pc = _setup("torus", (1.0, 0.4), 0.05, 16, "oras", "fp32")
+def test_precond_multi_rhs_matches_single(nrhs, ordering, precision):
+    lb, ob, A, P, keys, pos, op, pc = _setup("torus", (1.0, 0.4), 0.05, 16, "oras", precision, ordering=ordering)
     X = np.stack([G.field(keys, 30 + r) for r in range(nrhs)], axis=1)
     z = pc.apply(torch.tensor(X.copy(), dtype=torch.float64, device=DEV).reshape(-1), nrhs=nrhs)
     z = z.cpu().numpy().reshape(-1, nrhs)

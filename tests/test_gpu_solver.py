@@ -155,3 +155,21 @@ def test_config2_oras_fp64_and_mixed():
         assert np.abs(out[name] - Y).max() < 0.05 * np.abs(Y).max()
     d = np.abs(out["fp64"] - out["mixed"]).max() / np.abs(out["fp64"]).max()
     print(f"mixed vs fp64 difference {d:.2e}")
+
+
+def test_set_shift_takes_effect_in_later_solves():
+    """A solve after cpm_operator_set_shift uses the new shift (the cached solve workspace is renewed)."""
+    lb = G.lib_band("sphere", (1.0,), 3, 0.1, 3)
+    ob3, _, _, A3, _ = G.oracle("sphere", (1.0,), 3, 0.1, 3, 3.0)
+    keys, pos = G.mapping(lb, ob3)
+    op = cpm.Operator(lb, 1.0)
+    _, cp, _ = lb.export()
+    f = _t(21.0 * inputs.sphere_y4(cp[:lb.n_active], 2))
+    u1, st1 = cpm.solve(op, f, rtol=1e-10)
+    op.set_shift(3.0)
+    u3, st3 = cpm.solve(op, f, rtol=1e-10)
+    assert st1["converged"] and st3["converged"]
+    assert not torch.equal(u1, u3)
+    fo = 21.0 * inputs.sphere_y4(ob3.cp_active, 2)
+    res = np.linalg.norm(fo - A3 @ u3.cpu().numpy()[np.argsort(pos)]) / np.linalg.norm(fo)
+    assert res <= 1e-10 * 1.01

@@ -89,3 +89,30 @@ def test_schwarz_variants_bit_identical(sphere, tmp_path, prec, nrhs):
     # restore the default choice for later users of the fixture
     _force(cache, "schwarz|", [1, 1024, 1])
     cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_packet_variants_bit_identical(sphere, tmp_path, prec, nrhs):
+    """Distance-ordered factors use the packet kernel only; its launch shapes agree bit for bit."""
+    b, op, _ = sphere
+    pc = cpm.Precond(op, kind="oras", n_parts=16, overlap=2.0, precision=prec, ordering="distance")
+    cache = tmp_path / "tune.json"
+    r = _vec(b, nrhs, 13)
+    res = cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
+    assert res["schwarz_variant"] in (2, 3) and res["schwarz_threads"] <= 512
+    ref = None
+    for cfg in ([2, 256, 0], [2, 256, 1], [2, 512, 0], [2, 512, 1], [2, 128, 1], [3, 256, 1], [3, 512, 0]):
+        _force(cache, "schwarz|", cfg)
+        res = cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
+        assert [res["schwarz_variant"], res["schwarz_threads"], res["schwarz_sleep"]] == cfg
+        z = pc.apply(r, nrhs=nrhs)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = z
+        else:
+            assert torch.equal(z, ref), cfg
+    # a cached row-kernel choice does not apply to packet factors: the class is timed again
+    _force(cache, "schwarz|", [1, 1024, 1])
+    res = cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
+    assert res["from_cache"] == 0 and res["schwarz_variant"] in (2, 3)
