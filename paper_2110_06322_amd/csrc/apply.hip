@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -390,25 +391,42 @@ struct PipeRec {
   uint64_t mA;
 };
 
+// A tile record travels as one vector load, lane j holding dword j of the
+// record, and is unpacked with readlane one iteration later: vector loads
+// complete in order, so unlike scalar loads they never hold up the LDS waits
+// of the extension rows.
+constexpr int kTileDwords = (int)(sizeof(DevTile) / 4);
+static_assert(sizeof(DevTile) % 4 == 0 && kTileDwords <= 64, "tile record must fit one dword per lane");
+
+__device__ __forceinline__ uint32_t pipe_rec_raw(const DevTile* __restrict__ wtiles, int w, int lane) {
+  return lane < kTileDwords ? reinterpret_cast<const uint32_t*>(wtiles + w)[lane] : 0u;
+}
+
 template <int D>
-__device__ __forceinline__ PipeRec pipe_rec(const DevTile* __restrict__ wtiles, int w, int wave, const Gate& gate) {
-  const DevTile& T = wtiles[w];
+__device__ __forceinline__ PipeRec pipe_unpack(uint32_t rw, int wave, const Gate& gate) {
+  auto f = [&](size_t byte_off) { return (int)__builtin_amdgcn_readlane(rw, (int)(byte_off / 4)); };
   PipeRec R;
-  R.inst = T.inst;
+  R.inst = f(offsetof(DevTile, inst));
   if (gate.act && gate_skip(gate, R.inst)) {   // an instance whose systems have stopped: an empty tile
     R.s0 = R.s1 = R.fbase = R.fb_off = R.fb_cnt = R.job_off = R.job_cnt = R.oA = 0;
     R.mA = 0ull;
     return R;
   }
-  R.s0 = T.fstr[0];
-  R.s1 = T.fstr[1];
-  R.fbase = T.fbase;
-  R.fb_off = T.fb_off;
-  R.fb_cnt = T.fb_cnt;
-  R.job_off = T.job_off;
-  R.job_cnt = T.job_cnt;
-  R.oA = wave < (1 << D) ? T.oA[wave] : 0;
-  R.mA = wave < (1 << D) ? T.mA[wave] : 0ull;
+  R.s0 = f(offsetof(DevTile, fstr));
+  R.s1 = f(offsetof(DevTile, fstr) + 4);
+  R.fbase = f(offsetof(DevTile, fbase));
+  R.fb_off = f(offsetof(DevTile, fb_off));
+  R.fb_cnt = f(offsetof(DevTile, fb_cnt));
+  R.job_off = f(offsetof(DevTile, job_off));
+  R.job_cnt = f(offsetof(DevTile, job_cnt));
+  R.oA = 0;
+  R.mA = 0ull;
+  if (wave < (1 << D)) {
+    R.oA = (int)__builtin_amdgcn_readlane(rw, (int)(offsetof(DevTile, oA) / 4) + wave);
+    const uint32_t lo = __builtin_amdgcn_readlane(rw, (int)(offsetof(DevTile, mA) / 4) + 2 * wave);
+    const uint32_t hi = __builtin_amdgcn_readlane(rw, (int)(offsetof(DevTile, mA) / 4) + 2 * wave + 1);
+    R.mA = ((uint64_t)hi << 32) | lo;
+  }
   return R;
 }
 
@@ -419,10 +437,40 @@ struct PipeList {
   uint32_t fbw;
 };
 
+// instance values a pipeline stage needs, kept in scalar registers and
+// reloaded only when the stage's tile belongs to another instance (tiles of
+// one instance are contiguous in the work list), so the steady state issues
+// no scalar loads
+struct InstView {
+  const double* tcp;
+  const Job* jobs;
+  const FootBrick* fbrec;
+  int64_t vec_off;
+  double diag, inv_h2;
+  int ntot, inst;
+};
+
+__device__ __forceinline__ void inst_refresh(InstView& v, const DevInst* __restrict__ insts, int i) {
+  if (i == v.inst) return;
+  const DevInst& I = insts[i];
+  v.tcp = I.tcp;
+  v.jobs = I.jobs;
+  v.fbrec = I.fbrec;
+  v.vec_off = I.vec_off;
+  v.diag = I.diag;
+  v.inv_h2 = I.inv_h2;
+  v.ntot = I.nA + I.nG;
+  v.inst = i;
+}
+
 template <int D>
-__device__ __forceinline__ PipeList pipe_list(const DevInst* __restrict__ insts, const PipeRec& R, int tid, int wave,
-                                              int lane) {
-  const DevInst& I = insts[R.inst];
+__device__ __forceinline__ void view_tcp(const InstView& V, int j, double* t) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) t[k] = V.tcp[(int64_t)k * V.ntot + j];
+}
+
+template <int D>
+__device__ __forceinline__ PipeList pipe_list(const InstView& I, const PipeRec& R, int tid, int wave, int lane) {
   PipeList L;
   L.node0 = 0; L.slot0 = -1; L.node1 = 0; L.slot1 = -1; L.fbw = 0;
   if (tid < R.job_cnt) {
@@ -451,14 +499,13 @@ struct PipeData {
 };
 
 template <int D>
-__device__ __forceinline__ void pipe_data(const DevInst* __restrict__ insts, const PipeRec& R, const PipeList& L,
+__device__ __forceinline__ void pipe_data(const InstView& I, const PipeRec& R, const PipeList& L,
                                           const double* __restrict__ x, const int* l, int wave, int lane,
                                           PipeData<D>& Dt) {
-  const DevInst& I = insts[R.inst];
   const double* xb = x + I.vec_off;
 #pragma unroll
   for (int k = 0; k < 3; ++k) Dt.t0[k] = 0.0;
-  if (L.slot0 >= 0) load_tcp<D>(I, L.node0, Dt.t0);
+  if (L.slot0 >= 0) view_tcp<D>(I, L.node0, Dt.t0);
   const int loff = lane_box_offset<D>(l, R.s0, R.s1);
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -508,19 +555,24 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     vi = vbox_index<D, 1>(ll);
   }
 
-  // prologue: data of tile w, lists of w+per, record of w+2per
-  PipeRec R0 = pipe_rec<D>(wtiles, w, wave, gate);
-  PipeList L0 = pipe_list<D>(insts, R0, tid, wave, lane);
+  // prologue: data of tile w, lists of w+per, raw record of w+2per
+  InstView V0, V1, V2;   // instance views of the stencil, data and list stages
+  V0.inst = V1.inst = V2.inst = -1;
+  PipeRec R0 = pipe_unpack<D>(pipe_rec_raw(wtiles, w, lane), wave, gate);
+  inst_refresh(V1, insts, R0.inst);
+  PipeList L0 = pipe_list<D>(V1, R0, tid, wave, lane);
   PipeData<D> D0;
-  pipe_data<D>(insts, R0, L0, x, l, wave, lane, D0);
+  pipe_data<D>(V1, R0, L0, x, l, wave, lane, D0);
   const bool v1 = w + per < w_end, v2 = w + 2 * per < w_end;
-  PipeRec R1 = v1 ? pipe_rec<D>(wtiles, w + per, wave, gate) : R0;
-  PipeList L1 = v1 ? pipe_list<D>(insts, R1, tid, wave, lane) : L0;
-  PipeRec R2 = v2 ? pipe_rec<D>(wtiles, w + 2 * per, wave, gate) : R1;
+  PipeRec R1 = v1 ? pipe_unpack<D>(pipe_rec_raw(wtiles, w + per, lane), wave, gate) : R0;
+  inst_refresh(V2, insts, R1.inst);
+  PipeList L1 = v1 ? pipe_list<D>(V2, R1, tid, wave, lane) : L0;
+  uint32_t W2 = v2 ? pipe_rec_raw(wtiles, w + 2 * per, lane) : 0u;
 
 #pragma unroll 1
   for (; w < w_end; w += per) {
-    const DevInst& I = insts[R0.inst];
+    inst_refresh(V0, insts, R0.inst);
+    const InstView& I = V0;
     // ---- stage this tile's footprint of x
 #pragma unroll
     for (int u = 0; u < 8; ++u)
@@ -536,16 +588,23 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     __syncthreads();
     // ---- next tiles' loads: data of w+per, lists of w+2per, record of w+3per
     const bool n1 = w + per < w_end, n2 = w + 2 * per < w_end, n3 = w + 3 * per < w_end;
-    if (n1) pipe_data<D>(insts, R1, L1, x, l, wave, lane, D0);
+    if (n1) {
+      inst_refresh(V1, insts, R1.inst);
+      pipe_data<D>(V1, R1, L1, x, l, wave, lane, D0);
+    }
+    PipeRec R2 = R1;
     PipeList L2 = L1;
-    if (n2) L2 = pipe_list<D>(insts, R2, tid, wave, lane);
-    PipeRec R3 = R2;
-    if (n3) R3 = pipe_rec<D>(wtiles, w + 3 * per, wave, gate);
+    if (n2) {
+      R2 = pipe_unpack<D>(W2, wave, gate);
+      inst_refresh(V2, insts, R2.inst);
+      L2 = pipe_list<D>(V2, R2, tid, wave, lane);
+    }
+    const uint32_t W3 = n3 ? pipe_rec_raw(wtiles, w + 3 * per, lane) : 0u;
     // ---- extension rows of this tile
     if (slot0 >= 0) V[slot0] = erow_lds<D, P>(t0, U, s0, s1, fbase);
     if (slot1 >= 0) {
       double t1[3];
-      load_tcp<D>(I, node1, t1);
+      view_tcp<D>(I, node1, t1);
       V[slot1] = erow_lds<D, P>(t1, U, s0, s1, fbase);
     }
     __syncthreads();
@@ -553,7 +612,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     if (has_row) yb[row] = stencil_row<D>(V, vi, diag, inv_h2, xi);
     R0 = R1; L0 = L1;
     R1 = R2; L1 = L2;
-    R2 = R3;
+    W2 = W3;
   }
 }
 
