@@ -452,7 +452,7 @@ __device__ __forceinline__ T row16_sum_to_15(T v) {
 // (forward publishes level 1, backward level 2); less local memory, one more
 // LDS round trip per dependency, the same arithmetic in the same order.
 template <class T, int NRHS, bool BACKWARD, bool SLEEP, bool FLAGS>
-__device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, const uint32_t* __restrict__ pk_,
+__device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int lane, const uint32_t* __restrict__ pk_,
                                         const uint64_t* __restrict__ rec_, const uint16_t* __restrict__ col_,
                                         const T* __restrict__ val_, const T* __restrict__ dinv_,
                                         const int32_t* __restrict__ gsched_, const double* __restrict__ rb_,
@@ -472,18 +472,20 @@ __device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, con
   const int g = lane >> 4, t = lane & 15;
   // schedule position of this lane group's row in a packet (clamped into the packet)
   auto posof = [&](uint32_t w) { return (int)(w >> 2) + min(g, (int)(w & 3u)); };
+  // Entries t, t+16, ... of the row, loaded unconditionally at immediate offsets
+  // from one address: slots past the row's end read the entries that follow it
+  // (the factor arrays are padded), and solve_row masks them out.
   auto fetch = [&](PacketRow<T, NRHS>& D, uint32_t w, uint64_t r, int gi) {
     D.rec = r;
-    const int len = (int)((r >> 32) & 0xffff);
     D.live = g <= (int)(w & 3u);
-    D.len = D.live ? len : 0;
-    const int64_t off = (int64_t)(r & 0xffffffffull);
-    const int hi = max(len - 1, 0);
+    D.len = D.live ? (int)((r >> 32) & 0xffff) : 0;
+    const int64_t e0 = (int64_t)(r & 0xffffffffull) + t;
+    const auto cp = col + e0;
+    const auto vp = val + e0;
 #pragma unroll
     for (int j = 0; j < kPacketEntries; ++j) {
-      const int64_t e = off + min(t + kPacketLanes * j, hi);
-      D.k[j] = col[e];
-      D.v[j] = val[e];
+      D.k[j] = cp[kPacketLanes * j];
+      D.v[j] = vp[kPacketLanes * j];
     }
     if (BACKWARD) {
       D.dq = dinv[(int)(r >> 48)];
@@ -499,6 +501,11 @@ __device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, con
 #pragma unroll
       for (int r = 0; r < NRHS; ++r) D.own[r] = yv[(size_t)q * NRHS + r];   // y_q, complete before this sweep
     }
+    // dependency slots; masked entries read slot n, which always holds 0 and is
+    // always complete, so every poll is unconditional
+    int kk[kPacketEntries];
+#pragma unroll
+    for (int j = 0; j < kPacketEntries; ++j) kk[j] = t + kPacketLanes * j < D.len ? (int)D.k[j] : n;
     // wait for every dependency: all polls issued together, pending ones re-polled
     Bits b[kPacketEntries];
     int spins = 0;
@@ -506,9 +513,7 @@ __device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, con
       int f[kPacketEntries];
 #pragma unroll
       for (int j = 0; j < kPacketEntries; ++j)
-        f[j] = t + kPacketLanes * j < D.len
-                   ? __hip_atomic_load(done + D.k[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                   : LEVEL;
+        f[j] = __hip_atomic_load(done + kk[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       for (;;) {
         bool pending = false;
 #pragma unroll
@@ -521,20 +526,17 @@ __device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, con
         }
 #pragma unroll
         for (int j = 0; j < kPacketEntries; ++j)
-          if (f[j] < LEVEL) f[j] = __hip_atomic_load(done + D.k[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (f[j] < LEVEL) f[j] = __hip_atomic_load(done + kk[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 #pragma unroll
-      for (int j = 0; j < kPacketEntries; ++j)
-        b[j] = t + kPacketLanes * j < D.len ? to_bits<T>(dst[(size_t)D.k[j] * NRHS]) : (Bits)0;
+      for (int j = 0; j < kPacketEntries; ++j) b[j] = to_bits<T>(dst[(size_t)kk[j] * NRHS]);
     } else {
       const Bits sent = Sentinel<T>::kBits;
 #pragma unroll
       for (int j = 0; j < kPacketEntries; ++j)
-        b[j] = t + kPacketLanes * j < D.len
-                   ? __hip_atomic_load(reinterpret_cast<Bits*>(dst + (size_t)D.k[j] * NRHS), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP)
-                   : (Bits)0;
+        b[j] = __hip_atomic_load(reinterpret_cast<Bits*>(dst + (size_t)kk[j] * NRHS), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
       for (;;) {
         bool pending = false;
 #pragma unroll
@@ -550,7 +552,7 @@ __device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, con
 #pragma unroll
         for (int j = 0; j < kPacketEntries; ++j)
           if (b[j] == sent)
-            b[j] = __hip_atomic_load(reinterpret_cast<Bits*>(dst + (size_t)D.k[j] * NRHS), __ATOMIC_RELAXED,
+            b[j] = __hip_atomic_load(reinterpret_cast<Bits*>(dst + (size_t)kk[j] * NRHS), __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
@@ -560,11 +562,10 @@ __device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, con
     for (int r = 0; r < NRHS; ++r) acc[r] = (T)0;
 #pragma unroll
     for (int j = 0; j < kPacketEntries; ++j) {
-      if (t + kPacketLanes * j < D.len) {
-        acc[0] += D.v[j] * bits_to<T>(b[j]);
+      const T vj = t + kPacketLanes * j < D.len ? D.v[j] : (T)0;
+      acc[0] += vj * bits_to<T>(b[j]);
 #pragma unroll
-        for (int r = 1; r < NRHS; ++r) acc[r] += D.v[j] * dst[(size_t)D.k[j] * NRHS + r];
-      }
+      for (int r = 1; r < NRHS; ++r) acc[r] += vj * dst[(size_t)kk[j] * NRHS + r];
     }
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) acc[r] = row16_sum_to_15(acc[r]);
@@ -587,6 +588,7 @@ __device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, con
     }
   };
   // packet words three packets ahead, records two ahead, entries one ahead
+  // (fetched right after the previous packet is published)
   PacketRow<T, NRHS> A, B;
   uint32_t w1 = pk[min(p + nw, last)], w2 = pk[min(p + 2 * nw, last)];
   uint64_t r1 = rec[posof(w1)];
@@ -599,9 +601,11 @@ __device__ __forceinline__ void sweep_p(int npk, int wave, int nw, int lane, con
     const uint64_t r2 = rec[posof(w2)];
     const int g2 = BACKWARD ? 0 : gsched[posof(w2)];
     const uint32_t w3 = pk[min(p + 3 * nw, last)];
-    fetch(nxt, w1, r1, g1);
+    // the next packet's entries are issued after this packet is published: they
+    // are not needed before its dependencies (a level later) are complete
     solve_row(cur);
     if (p + nw > last) return false;
+    fetch(nxt, w1, r1, g1);
     p += nw;
     w1 = w2;
     r1 = r2;
@@ -625,9 +629,11 @@ __global__ void __launch_bounds__(kPacketMaxThreads) k_schwarz_p(const DevPC* __
   const DevPC& P = pcs[wi.inst];
   const DevSub sub = P.subs[wi.idx];
   const int n = sub.n;
+  // slot n of each array is the always-complete zero the masked entries read
+  const int n1 = n + 1;
   T* yv = reinterpret_cast<T*>(smem_d);
-  T* zv = FLAGS ? yv : yv + (size_t)n * NRHS;                // FLAGS: solved in place
-  int* done = reinterpret_cast<int*>(yv + (size_t)n * NRHS); // FLAGS only
+  T* zv = FLAGS ? yv : yv + (size_t)n1 * NRHS;                // FLAGS: solved in place
+  int* done = reinterpret_cast<int*>(yv + (size_t)n1 * NRHS); // FLAGS only
   const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id(), nw = blockDim.x >> 6;
   const int32_t* out_idx = P.out_idx + sub.row_off;
   const T* lv = reinterpret_cast<const T*>(P.lval) + sub.lbase;
@@ -636,17 +642,19 @@ __global__ void __launch_bounds__(kPacketMaxThreads) k_schwarz_p(const DevPC* __
   const double* rb = rin + P.vec_off * NRHS;
   double* zb = zout + P.vec_off * NRHS;
   if (FLAGS) {
-    for (int q = tid; q < n; q += blockDim.x) done[q] = 0;
+    for (int q = tid; q < n1; q += blockDim.x) done[q] = q < n ? 0 : 2;
+    for (int r = tid; r < NRHS; r += blockDim.x) yv[(size_t)n * NRHS + r] = (T)0;
   } else {
     const T sent = bits_to<T>(Sentinel<T>::kBits);
-    for (int q = tid; q < 2 * n * NRHS; q += blockDim.x) yv[q] = sent;
+    for (int q = tid; q < 2 * n1 * NRHS; q += blockDim.x)
+      yv[q] = (q % (n1 * NRHS)) < n * NRHS ? sent : (T)0;
   }
   __syncthreads();
-  sweep_p<T, NRHS, false, SLEEP, FLAGS>(sub.npkL, wave, nw, lane, P.pk + sub.pk_off, P.recL + sub.row_off,
+  sweep_p<T, NRHS, false, SLEEP, FLAGS>(n, sub.npkL, wave, nw, lane, P.pk + sub.pk_off, P.recL + sub.row_off,
                                         P.lcol + sub.lbase, lv, nullptr, P.gL + sub.row_off, rb, nullptr, yv, done,
                                         P.error_flag);
   __syncthreads();
-  sweep_p<T, NRHS, true, SLEEP, FLAGS>(sub.npkU, wave, nw, lane, P.pk + sub.pk_off + sub.npkL,
+  sweep_p<T, NRHS, true, SLEEP, FLAGS>(n, sub.npkU, wave, nw, lane, P.pk + sub.pk_off + sub.npkL,
                                        P.recU + sub.row_off, P.ucol + sub.ubase, uv, di, nullptr, nullptr, yv, zv,
                                        done, P.error_flag);
   __syncthreads();
@@ -678,10 +686,11 @@ static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkIt
     // packet factors: the value form when its two arrays fit, else the flag form
     // (the same arithmetic); rows longer than a packet's lanes take are not packed
     if (max_len > kPacketLanes * kPacketEntries || threads > kPacketMaxThreads) return hipErrorInvalidValue;
+    // one extra slot per array: the always-complete zero of masked entries
     const bool flags = cfg.variant == kSchwarzPacketFlags ||
-                       schwarz_value_lds(max_rows, NRHS, sizeof(T)) > kSchwarzMaxLds;
-    const size_t shm = flags ? (size_t)max_rows * (NRHS * sizeof(T) + sizeof(int))
-                             : schwarz_value_lds(max_rows, NRHS, sizeof(T));
+                       schwarz_value_lds(max_rows + 1, NRHS, sizeof(T)) > kSchwarzMaxLds;
+    const size_t shm = flags ? (size_t)(max_rows + 1) * (NRHS * sizeof(T) + sizeof(int))
+                             : schwarz_value_lds(max_rows + 1, NRHS, sizeof(T));
     const void* kern = flags ? (cfg.sleep ? (const void*)k_schwarz_p<T, NRHS, true, true>
                                           : (const void*)k_schwarz_p<T, NRHS, false, true>)
                              : (cfg.sleep ? (const void*)k_schwarz_p<T, NRHS, true, false>

@@ -116,11 +116,13 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
       pc->total_nnz += s.nnz;
     }
     pc->total_rows = row_off;
-    // one zero entry past the end: the sweeps clamp their loads into the arrays
-    lcol.push_back(0);
-    ucol.push_back(0);
-    lval.push_back(0.0);
-    uval.push_back(0.0);
+    // zero entries past the end: the row sweeps clamp their loads into the arrays,
+    // the packet sweeps read up to a packet row's span past a row's first entry
+    const int pad = kPacketLanes * kPacketEntries;
+    lcol.insert(lcol.end(), pad, 0);
+    ucol.insert(ucol.end(), pad, 0);
+    lval.insert(lval.end(), pad, 0.0);
+    uval.insert(uval.end(), pad, 0.0);
     pc->d_subs.upload(subs);
     pc->d_in.upload(in_idx);
     pc->d_gL.upload(gL);
