@@ -322,9 +322,10 @@ std::vector<int32_t> rcm_order(int n, const std::vector<int64_t>& ptr, const std
 }
 
 // rows in increasing dependency level (a topological order of the sweep)
-// (levpos, when given, receives the level of the row at each schedule position)
+// (levpos, when given, receives the level of the row at each schedule position;
+// by_class orders the rows of a level by their packet length class first)
 std::vector<uint16_t> schedule(int n, const std::vector<int64_t>& ptr, const std::vector<uint16_t>& col, bool lower,
-                               int& nlev, std::vector<int32_t>* levpos = nullptr) {
+                               int& nlev, std::vector<int32_t>* levpos = nullptr, bool by_class = false) {
   std::vector<int> lev(n, 0);
   nlev = 0;
   for (int t = 0; t < n; ++t) {
@@ -338,6 +339,10 @@ std::vector<uint16_t> schedule(int n, const std::vector<int64_t>& ptr, const std
   std::iota(s.begin(), s.end(), 0);
   std::stable_sort(s.begin(), s.end(), [&](uint16_t a, uint16_t b) {
     if (lev[a] != lev[b]) return lev[a] < lev[b];
+    if (by_class) {
+      const int ca = packet_class(ptr[a + 1] - ptr[a]), cb = packet_class(ptr[b + 1] - ptr[b]);
+      if (ca != cb) return ca < cb;
+    }
     return lower ? a < b : a > b;
   });
   if (levpos) {
@@ -542,8 +547,9 @@ void build_schwarz_host(const cpm_band_s& B, double c, const cpm_precond_opts& o
           }
         }
         int ll = 0, lu = 0;
-        sub.schedL = schedule(n, sub.lptr, sub.lcol, true, ll, &sub.levL);
-        sub.schedU = schedule(n, sub.uptr, sub.ucol, false, lu, &sub.levU);
+        const bool by_class = o.ordering == CPM_ORDER_DISTANCE;   // rows are packed by length class
+        sub.schedL = schedule(n, sub.lptr, sub.lcol, true, ll, &sub.levL, by_class);
+        sub.schedU = schedule(n, sub.uptr, sub.ucol, false, lu, &sub.levU, by_class);
         sub.levels = std::max(ll, lu);
         for (int q = 0; q < n; ++q) local[om[q]] = -1;
       } catch (const Error& e) {

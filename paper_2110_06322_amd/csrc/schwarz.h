@@ -74,13 +74,17 @@ constexpr int kSchwarzFlags = 0;        // LDS value array plus per-row completi
 constexpr int kSchwarzValueFlags = 1;   // values double as flags (forward and backward arrays)
 constexpr int kSchwarzPacket = 2;       // values as flags, up to four same-level rows per wavefront
 constexpr int kSchwarzPacketFlags = 3;  // packets with per-row completion flags (less local memory)
-// Packet layout: consecutive schedule positions of one level are grouped into
-// packets of at most kPacketRows rows; a packet word holds its first position
-// (bits 2..31) and its row count minus one (bits 0..1). Each row is solved by
-// kPacketLanes lanes, each taking at most kPacketEntries of its entries.
+// Packet layout: consecutive schedule positions of one level and one length
+// class are grouped into packets of at most kPacketRows rows; a packet word
+// holds its first position (bits 4..31), its class (bits 2..3) and its row
+// count minus one (bits 0..1). Each row is solved by kPacketLanes lanes, each
+// taking at most packet_slots(class) of its entries (kPacketEntries at most).
 constexpr int kPacketRows = 4;
 constexpr int kPacketLanes = 16;
 constexpr int kPacketEntries = 12;
+// length class of a factor row: entry slots per lane 4, 8 or 12
+inline int packet_class(int64_t len) { return len <= 4 * kPacketLanes ? 0 : len <= 8 * kPacketLanes ? 1 : 2; }
+constexpr int packet_slots(int cls) { return 4 * (cls + 1); }
 constexpr int kPacketMaxThreads = 512;   // 32 rows in flight; leaves the kernel 256 registers per lane
 constexpr size_t kSchwarzMaxLds = 160 * 1024;
 struct SchwarzCfg {

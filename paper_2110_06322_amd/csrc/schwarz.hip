@@ -10,6 +10,8 @@
 // subdomain owns are written back: no two workgroups write the same entry.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "schwarz.h"
 
 namespace cpm {
@@ -420,8 +422,10 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz_v(const DevPC* __re
 // For orderings whose levels hold many rows (the distance order), a wavefront
 // takes a packet of up to four rows of one level at once: lane group g (16
 // lanes) solves the packet's row g, lane t of the group taking entries t,
-// t+16, ..., t+176 (rows of up to 192 entries). The dependencies of a row are all issued before the first
-// wait, re-polled together until none reads the sentinel, and the group's sum is
+// t+16, ... up to the packet's length class (4, 8 or 12 entries per lane, rows
+// of up to 64, 128 or 192 entries; the host packs rows of one class together,
+// and each class has its own unrolled code). The dependencies of a row are all
+// issued before the first wait, re-polled together until none reads the sentinel, and the group's sum is
 // formed in a fixed order (entries of a lane in increasing order, then a DPP
 // prefix sum over the 16 lanes). Rows of one packet never depend on each other,
 // and packets follow the level order, so the earliest unfinished packet always
@@ -431,6 +435,7 @@ struct PacketRow {
   uint64_t rec;
   int len;                     // stored entries of the group's row (0 for an empty slot)
   bool live;                   // the group has a row in this packet
+  int cls;                     // length class of the packet (wave-uniform)
   int k[kPacketEntries];
   T v[kPacketEntries];
   T own[NRHS];
@@ -471,11 +476,14 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
   const int last = npk - 1;
   const int g = lane >> 4, t = lane & 15;
   // schedule position of this lane group's row in a packet (clamped into the packet)
-  auto posof = [&](uint32_t w) { return (int)(w >> 2) + min(g, (int)(w & 3u)); };
+  auto posof = [&](uint32_t w) { return (int)(w >> 4) + min(g, (int)(w & 3u)); };
+  auto class_of = [&](uint32_t w) { return __builtin_amdgcn_readfirstlane((int)((w >> 2) & 3u)); };
   // Entries t, t+16, ... of the row, loaded unconditionally at immediate offsets
   // from one address: slots past the row's end read the entries that follow it
   // (the factor arrays are padded), and solve_row masks them out.
-  auto fetch = [&](PacketRow<T, NRHS>& D, uint32_t w, uint64_t r, int gi) {
+  // (NJc: the packet's entry slots per lane, a std::integral_constant)
+  auto fetch_n = [&](auto NJc, PacketRow<T, NRHS>& D, uint32_t w, uint64_t r, int gi) __attribute__((always_inline)) {
+    constexpr int NJ = decltype(NJc)::value;
     D.rec = r;
     D.live = g <= (int)(w & 3u);
     D.len = D.live ? (int)((r >> 32) & 0xffff) : 0;
@@ -483,7 +491,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
     const auto cp = col + e0;
     const auto vp = val + e0;
 #pragma unroll
-    for (int j = 0; j < kPacketEntries; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       D.k[j] = cp[kPacketLanes * j];
       D.v[j] = vp[kPacketLanes * j];
     }
@@ -495,7 +503,8 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
       for (int q = 0; q < NRHS; ++q) D.own[q] = (T)rb[(int64_t)gi * NRHS + q];
     }
   };
-  auto solve_row = [&](PacketRow<T, NRHS>& D) {
+  auto solve_n = [&](auto NJc, PacketRow<T, NRHS>& D) __attribute__((always_inline)) {
+    constexpr int NJ = decltype(NJc)::value;
     const int q = (int)(D.rec >> 48);
     if (BACKWARD) {
 #pragma unroll
@@ -503,21 +512,21 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
     }
     // dependency slots; masked entries read slot n, which always holds 0 and is
     // always complete, so every poll is unconditional
-    int kk[kPacketEntries];
+    int kk[NJ];
 #pragma unroll
-    for (int j = 0; j < kPacketEntries; ++j) kk[j] = t + kPacketLanes * j < D.len ? (int)D.k[j] : n;
+    for (int j = 0; j < NJ; ++j) kk[j] = t + kPacketLanes * j < D.len ? (int)D.k[j] : n;
     // wait for every dependency: all polls issued together, pending ones re-polled
-    Bits b[kPacketEntries];
+    Bits b[NJ];
     int spins = 0;
     if constexpr (FLAGS) {
-      int f[kPacketEntries];
+      int f[NJ];
 #pragma unroll
-      for (int j = 0; j < kPacketEntries; ++j)
+      for (int j = 0; j < NJ; ++j)
         f[j] = __hip_atomic_load(done + kk[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       for (;;) {
         bool pending = false;
 #pragma unroll
-        for (int j = 0; j < kPacketEntries; ++j) pending |= f[j] < LEVEL;
+        for (int j = 0; j < NJ; ++j) pending |= f[j] < LEVEL;
         if (!pending) break;
         if (SLEEP) __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
@@ -525,32 +534,32 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
           break;
         }
 #pragma unroll
-        for (int j = 0; j < kPacketEntries; ++j)
+        for (int j = 0; j < NJ; ++j)
           if (f[j] < LEVEL) f[j] = __hip_atomic_load(done + kk[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 #pragma unroll
-      for (int j = 0; j < kPacketEntries; ++j) b[j] = to_bits<T>(dst[(size_t)kk[j] * NRHS]);
+      for (int j = 0; j < NJ; ++j) b[j] = to_bits<T>(dst[(size_t)kk[j] * NRHS]);
     } else {
       const Bits sent = Sentinel<T>::kBits;
 #pragma unroll
-      for (int j = 0; j < kPacketEntries; ++j)
+      for (int j = 0; j < NJ; ++j)
         b[j] = __hip_atomic_load(reinterpret_cast<Bits*>(dst + (size_t)kk[j] * NRHS), __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
       for (;;) {
         bool pending = false;
 #pragma unroll
-        for (int j = 0; j < kPacketEntries; ++j) pending |= b[j] == sent;
+        for (int j = 0; j < NJ; ++j) pending |= b[j] == sent;
         if (!pending) break;
         if (SLEEP) __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
           __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
-          for (int j = 0; j < kPacketEntries; ++j) b[j] = 0;
+          for (int j = 0; j < NJ; ++j) b[j] = 0;
           break;
         }
 #pragma unroll
-        for (int j = 0; j < kPacketEntries; ++j)
+        for (int j = 0; j < NJ; ++j)
           if (b[j] == sent)
             b[j] = __hip_atomic_load(reinterpret_cast<Bits*>(dst + (size_t)kk[j] * NRHS), __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -561,7 +570,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) acc[r] = (T)0;
 #pragma unroll
-    for (int j = 0; j < kPacketEntries; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       const T vj = t + kPacketLanes * j < D.len ? D.v[j] : (T)0;
       acc[0] += vj * bits_to<T>(b[j]);
 #pragma unroll
@@ -586,6 +595,15 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
                            __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
+  };
+  auto fetch = [&](PacketRow<T, NRHS>& D, uint32_t w, uint64_t r, int gi) __attribute__((always_inline)) {
+    D.cls = class_of(w);
+    fetch_n(std::integral_constant<int, kPacketEntries>{}, D, w, r, gi);
+  };
+  auto solve_row = [&](PacketRow<T, NRHS>& D) __attribute__((always_inline)) {
+    if (D.cls == 0) solve_n(std::integral_constant<int, packet_slots(0)>{}, D);
+    else if (D.cls == 1) solve_n(std::integral_constant<int, packet_slots(1)>{}, D);
+    else solve_n(std::integral_constant<int, packet_slots(2)>{}, D);
   };
   // packet words three packets ahead, records two ahead, entries one ahead
   // (fetched right after the previous packet is published)

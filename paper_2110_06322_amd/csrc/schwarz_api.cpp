@@ -100,11 +100,15 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
       if (want_packets) {
         for (int lower = 1; lower >= 0; --lower) {
           const auto& lev = lower ? s.levL : s.levU;
+          const auto& sched = lower ? s.schedL : s.schedU;
+          const auto& ptr = lower ? s.lptr : s.uptr;
+          auto cls = [&](int t) { return packet_class(ptr[sched[t] + 1] - ptr[sched[t]]); };
           int32_t& count = lower ? subs[j].npkL : subs[j].npkU;
           for (int t = 0; t < s.n;) {
+            const int k = cls(t);
             int c = 1;
-            while (c < kPacketRows && t + c < s.n && lev[t + c] == lev[t]) ++c;
-            pk.push_back(((uint32_t)t << 2) | (uint32_t)(c - 1));
+            while (c < kPacketRows && t + c < s.n && lev[t + c] == lev[t] && cls(t + c) == k) ++c;
+            pk.push_back(((uint32_t)t << 4) | ((uint32_t)k << 2) | (uint32_t)(c - 1));
             ++count;
             t += c;
           }
