@@ -288,9 +288,11 @@ void cpm_batch_destroy(cpm_batch* batch);
  * Autotuning. Times the candidate kernel configurations of the operator's
  * apply (one right-hand side: persistent pipelined kernel or one workgroup
  * per tile) and, when pc is given, of its subdomain solves (completion flags
- * or values-as-flags; 256, 512 or 1024 threads per subdomain; with or
- * without back-off while waiting) on library-allocated scratch vectors, and
- * keeps the fastest. All candidates compute bit-identical results; only
+ * or values-as-flags; 256, 512 or 1024 threads per subdomain, for packet
+ * factors 256 or 512, or 768 with FP32 factors and 1-2 right-hand sides;
+ * with or without back-off while waiting) on library-allocated scratch
+ * vectors, and keeps the fastest. All candidates for one factor layout
+ * compute bit-identical results; only
  * speed differs. Choices are cached per shape class (device, d, p, nrhs and
  * power-of-two size classes) in the JSON file cache_path (NULL: no file; a
  * missing or unreadable file counts as empty; it is rewritten when a class is

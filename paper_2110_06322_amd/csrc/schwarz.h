@@ -85,7 +85,13 @@ constexpr int kPacketEntries = 12;
 // length class of a factor row: entry slots per lane 4, 8 or 12
 inline int packet_class(int64_t len) { return len <= 4 * kPacketLanes ? 0 : len <= 8 * kPacketLanes ? 1 : 2; }
 constexpr int packet_slots(int cls) { return 4 * (cls + 1); }
-constexpr int kPacketMaxThreads = 512;   // 32 rows in flight; leaves the kernel 256 registers per lane
+// threads of a packet workgroup at most: 768 (48 rows in flight, up to 170
+// registers per lane) where the kernel fits that register budget (FP32 factors
+// with 1 or 2 right-hand sides; the completion-flag form with one FP64
+// right-hand side), else 512 (up to 256 registers)
+constexpr int packet_max_threads(bool fp32, int nrhs, bool flags) {
+  return (fp32 && nrhs <= 2) || (nrhs == 1 && flags) ? 768 : 512;
+}
 constexpr size_t kSchwarzMaxLds = 160 * 1024;
 struct SchwarzCfg {
   int variant = kSchwarzValueFlags;

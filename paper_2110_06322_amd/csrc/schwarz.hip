@@ -636,7 +636,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
 }
 
 template <class T, int NRHS, bool SLEEP, bool FLAGS>
-__global__ void __launch_bounds__(kPacketMaxThreads) k_schwarz_p(const DevPC* __restrict__ pcs,
+__global__ void __launch_bounds__(packet_max_threads(sizeof(T) == 4, NRHS, FLAGS)) k_schwarz_p(const DevPC* __restrict__ pcs,
                                                               const WorkItem* __restrict__ work, int nwork,
                                                               const double* __restrict__ rin,
                                                               double* __restrict__ zout, Gate gate) {
@@ -703,10 +703,11 @@ static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkIt
   if (cfg.variant == kSchwarzPacket || cfg.variant == kSchwarzPacketFlags) {
     // packet factors: the value form when its two arrays fit, else the flag form
     // (the same arithmetic); rows longer than a packet's lanes take are not packed
-    if (max_len > kPacketLanes * kPacketEntries || threads > kPacketMaxThreads) return hipErrorInvalidValue;
     // one extra slot per array: the always-complete zero of masked entries
     const bool flags = cfg.variant == kSchwarzPacketFlags ||
                        schwarz_value_lds(max_rows + 1, NRHS, sizeof(T)) > kSchwarzMaxLds;
+    if (max_len > kPacketLanes * kPacketEntries || threads > packet_max_threads(sizeof(T) == 4, NRHS, flags))
+      return hipErrorInvalidValue;
     const size_t shm = flags ? (size_t)(max_rows + 1) * (NRHS * sizeof(T) + sizeof(int))
                              : schwarz_value_lds(max_rows + 1, NRHS, sizeof(T));
     const void* kern = flags ? (cfg.sleep ? (const void*)k_schwarz_p<T, NRHS, true, true>

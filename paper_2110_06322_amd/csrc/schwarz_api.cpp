@@ -137,7 +137,7 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     if (pc->packets) {
       pc->d_pk.upload(pk);
       pc->cfg.variant = kSchwarzPacket;
-      pc->cfg.threads = kPacketMaxThreads;
+      pc->cfg.threads = 512;
     }
     pc->d_lcol.upload(lcol);
     pc->d_ucol.upload(ucol);

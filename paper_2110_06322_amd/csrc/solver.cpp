@@ -653,7 +653,7 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
         return launch_schwarz(Bt.pc_cfg, Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.max_len, Bt.pc_fp32,
                               Bt.R, Bt.r.p, Bt.w.p, s);
       };
-      if (!force && it != cache.end() && tune::valid_schwarz(it->second, Bt.pc_packets)) {
+      if (!force && it != cache.end() && tune::valid_schwarz(it->second, Bt.pc_packets, Bt.pc_fp32 != 0, Bt.R)) {
         Bt.pc_cfg.variant = it->second[0];
         Bt.pc_cfg.threads = it->second[1];
         Bt.pc_cfg.sleep = it->second[2];
@@ -661,7 +661,7 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
         all_cached = false;
         double best = 1e30;
         SchwarzCfg bestc = Bt.pc_cfg;
-        for (const SchwarzCfg& c : tune::schwarz_candidates(Bt.pc_packets)) {
+        for (const SchwarzCfg& c : tune::schwarz_candidates(Bt.pc_packets, Bt.pc_fp32 != 0, Bt.R)) {
           Bt.pc_cfg = c;
           const double ms = tune::time_ms(run, reps, s);
           if (ms < best) { best = ms; bestc = c; }

@@ -97,25 +97,26 @@ void write_cache(const char* path, const Cache& c) {
 
 int log2i(double v) { return v <= 1 ? 0 : (int)std::lround(std::log2(v)); }
 
-bool valid_schwarz(const std::vector<int>& v, bool packets) {
+bool valid_schwarz(const std::vector<int>& v, bool packets, bool fp32, int nrhs) {
   if (v.size() != 3) return false;
   const bool variant_ok = packets ? (v[0] == kSchwarzPacket || v[0] == kSchwarzPacketFlags)
                                   : (v[0] == kSchwarzFlags || v[0] == kSchwarzValueFlags);
-  return variant_ok && v[1] >= 64 && v[1] <= (packets ? kPacketMaxThreads : 1024) && v[1] % 64 == 0 &&
+  return variant_ok && v[1] >= 64 && v[1] <= (packets ? packet_max_threads(fp32, nrhs, v[0] == kSchwarzPacketFlags) : 1024) && v[1] % 64 == 0 &&
          (v[2] == 0 || v[2] == 1);
 }
 
 // The packet kernels sum a row in another order than the two one-row-per-
 // wavefront kernels, so only they are candidates for a packet layout.
-std::vector<SchwarzCfg> schwarz_candidates(bool packets) {
+std::vector<SchwarzCfg> schwarz_candidates(bool packets, bool fp32, int nrhs) {
   std::vector<SchwarzCfg> out;
   const std::vector<int> variants = packets ? std::vector<int>{kSchwarzPacket, kSchwarzPacketFlags}
                                             : std::vector<int>{kSchwarzFlags, kSchwarzValueFlags};
   for (int variant : variants)
-    for (int threads : {256, 512, 1024})
+    for (int threads : {256, 512, 768, 1024})
       for (int sleep : {0, 1}) {
         if (variant == kSchwarzFlags && sleep == 0) continue;   // the flag kernel always backs off
-        if (packets && threads > kPacketMaxThreads) continue;
+        if (packets ? threads > packet_max_threads(fp32, nrhs, variant == kSchwarzPacketFlags) : threads == 768)
+          continue;
         SchwarzCfg c;
         c.variant = variant;
         c.threads = threads;
@@ -220,7 +221,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
                     pc->P.fp32 ? "fp32" : "fp64", pc->packets ? "|packets" : "", nrhs, log2i((double)pc->max_rows), log2i((double)pc->max_levels),
                     log2i((double)pc->host.nparts));
       auto it = cache.find(key);
-      if (!force && it != cache.end() && valid_schwarz(it->second, pc->packets)) {
+      if (!force && it != cache.end() && valid_schwarz(it->second, pc->packets, pc->P.fp32 != 0, nrhs)) {
         pc->cfg.variant = it->second[0];
         pc->cfg.threads = it->second[1];
         pc->cfg.sleep = it->second[2];
@@ -228,7 +229,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
         all_cached = false;
         double best = 1e30;
         SchwarzCfg bestc = pc->cfg;
-        for (const SchwarzCfg& c : schwarz_candidates(pc->packets)) {
+        for (const SchwarzCfg& c : schwarz_candidates(pc->packets, pc->P.fp32 != 0, nrhs)) {
           pc->cfg = c;
           const double ms = time_ms([&] { return precond_apply_raw(pc, x.p, y.p, nrhs, s); }, reps, s);
           if (ms < best) { best = ms; bestc = c; }

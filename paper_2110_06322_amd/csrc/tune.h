@@ -20,9 +20,9 @@ void write_cache(const char* path, const Cache& c);  // no-op for a null path
 int log2i(double v);
 std::string device_tag();                            // e.g. "gfx950-cu256"
 // a cached subdomain-solve entry, for preconditioners with or without the packet layout
-bool valid_schwarz(const std::vector<int>& v, bool packets);
+bool valid_schwarz(const std::vector<int>& v, bool packets, bool fp32, int nrhs);
 // candidate kernels; all candidates for one layout compute bit-identical results
-std::vector<SchwarzCfg> schwarz_candidates(bool packets);
+std::vector<SchwarzCfg> schwarz_candidates(bool packets, bool fp32, int nrhs);
 // mean milliseconds of `reps` launches of f after two warm-up launches
 double time_ms(const std::function<hipError_t()>& f, int reps, hipStream_t s);
 

@@ -100,9 +100,14 @@ def test_packet_variants_bit_identical(sphere, tmp_path, prec, nrhs):
     cache = tmp_path / "tune.json"
     r = _vec(b, nrhs, 13)
     res = cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
-    assert res["schwarz_variant"] in (2, 3) and res["schwarz_threads"] <= 512
+    assert res["schwarz_variant"] in (2, 3) and res["schwarz_threads"] <= (768 if nrhs <= 2 else 512)
     ref = None
-    for cfg in ([2, 256, 0], [2, 256, 1], [2, 512, 0], [2, 512, 1], [2, 128, 1], [3, 256, 1], [3, 512, 0]):
+    cfgs = [[2, 256, 0], [2, 256, 1], [2, 512, 0], [2, 512, 1], [2, 128, 1], [3, 256, 1], [3, 512, 0]]
+    if prec == "fp32" and nrhs <= 2:
+        cfgs += [[2, 768, 1], [3, 768, 0]]   # FP32 packets with 1-2 right-hand sides allow 768 threads
+    elif nrhs == 1:
+        cfgs += [[3, 768, 1]]                # so does the FP64 completion-flag form with one
+    for cfg in cfgs:
         _force(cache, "schwarz|", cfg)
         res = cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
         assert [res["schwarz_variant"], res["schwarz_threads"], res["schwarz_sleep"]] == cfg
