@@ -59,6 +59,5 @@ hipError_t vec_xupdate(int R, double* x, const double* Z0, int64_t zstride, cons
 hipError_t gmres_givens(const GmresState& S, int j, int ns, hipStream_t s);
 hipError_t gmres_hsolve(const GmresState& S, int ns, hipStream_t s);
 hipError_t gmres_cycle_init(const GmresState& S, int ns, hipStream_t s);
-hipError_t gmres_zero_col(const GmresState& S, int ns, hipStream_t s);
 
 }  // namespace cpm

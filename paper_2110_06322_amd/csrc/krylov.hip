@@ -87,8 +87,20 @@ __global__ void k_reduce(const double* __restrict__ part, int m, int nchunks, co
   if (t >= ns * m) return;
   const int s = t / m, i = t % m;
   const int inst = s / R, r = s % R;
+  // chunks summed in order; loads are issued eight at a time so that their
+  // latencies overlap instead of forming one chain
+  const double* pp = part + (int64_t)i * nchunks * R + r;
+  const int c0 = cbeg[inst], c1 = cbeg[inst + 1];
   double sum = 0.0;
-  for (int c = cbeg[inst]; c < cbeg[inst + 1]; ++c) sum += part[((int64_t)i * nchunks + c) * R + r];
+  int c = c0;
+  for (; c + 8 <= c1; c += 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = pp[(int64_t)(c + q) * R];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum += v[q];
+  }
+  for (; c < c1; ++c) sum += pp[(int64_t)c * R];
   out[(int64_t)s * ld + i] = sum;
   if (accum) accum[(int64_t)s * accum_ld + i] += sum;
 }
@@ -236,33 +248,37 @@ __global__ void __launch_bounds__(kVecThreads) k_xupdate(double* __restrict__ x,
   }
 }
 
-// Arnoldi column j of every active system: Givens rotations and the residual estimate.
+// Arnoldi column j of every active system: Givens rotations and the residual
+// estimate. The column accumulated by the two Gram-Schmidt passes is consumed
+// and cleared here (and at each cycle start), ready for the next step.
 __global__ void k_givens(GmresState S, int j, int ns) {
   __shared__ int cnt[1024 / 64];
   const int s = threadIdx.x;
   int alive = 0;
   if (s < ns && S.act[s]) {
     const int m = S.m, ldh = m + 1;
-    double* H = S.H + (int64_t)s * ldh * m;
+    double* __restrict__ Hj = S.H + (int64_t)s * ldh * m + (int64_t)j * ldh;
     double* g = S.g + (int64_t)s * (m + 1);
-    double* cs = S.cs + (int64_t)s * m;
-    double* sn = S.sn + (int64_t)s * m;
-    const double* col = S.hcol + (int64_t)s * (m + 1);
+    double* __restrict__ cs = S.cs + (int64_t)s * m;
+    double* __restrict__ sn = S.sn + (int64_t)s * m;
+    double* __restrict__ col = S.hcol + (int64_t)s * (m + 1);
     const double hn = sqrt(S.nrm2[s]);
-    for (int i = 0; i <= j; ++i) H[i + j * ldh] = col[i];
-    H[j + 1 + j * ldh] = hn;
+    // earlier rotations applied to the new column; only the running entry is
+    // carried, the other operands are independent loads
+    double carry = col[0];
     for (int i = 0; i < j; ++i) {
-      const double a = H[i + j * ldh], b = H[i + 1 + j * ldh];
-      H[i + j * ldh] = cs[i] * a + sn[i] * b;
-      H[i + 1 + j * ldh] = -sn[i] * a + cs[i] * b;
+      const double b = col[i + 1], c = cs[i], sv = sn[i];
+      Hj[i] = c * carry + sv * b;
+      carry = -sv * carry + c * b;
     }
-    const double a = H[j + j * ldh], b = H[j + 1 + j * ldh];
+    for (int i = 0; i <= j; ++i) col[i] = 0.0;
+    const double a = carry, b = hn;
     const double den = hypot(a, b);
     const double c = den > 0 ? a / den : 1.0, sv = den > 0 ? b / den : 0.0;
     cs[j] = c;
     sn[j] = sv;
-    H[j + j * ldh] = den;
-    H[j + 1 + j * ldh] = 0.0;
+    Hj[j] = den;
+    Hj[j + 1] = 0.0;
     g[j + 1] = -sv * g[j];
     g[j] = c * g[j];
     S.steps[s] = j + 1;
@@ -308,17 +324,12 @@ __global__ void k_cycle_init(GmresState S, int ns) {
   if (s >= ns) return;
   const int m = S.m;
   double* g = S.g + (int64_t)s * (m + 1);
+  double* col = S.hcol + (int64_t)s * (m + 1);
   for (int i = 0; i <= m; ++i) g[i] = 0.0;
+  for (int i = 0; i <= m; ++i) col[i] = 0.0;
   g[0] = S.beta[s];
   S.steps[s] = 0;
   S.scale[s] = S.beta[s] > 0 ? 1.0 / S.beta[s] : 0.0;
-}
-
-__global__ void k_zero_col(GmresState S, int ns) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ns) return;
-  double* col = S.hcol + (int64_t)s * (S.m + 1);
-  for (int i = 0; i <= S.m; ++i) col[i] = 0.0;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -396,11 +407,6 @@ hipError_t gmres_hsolve(const GmresState& S, int ns, hipStream_t s) {
 
 hipError_t gmres_cycle_init(const GmresState& S, int ns, hipStream_t s) {
   hipLaunchKernelGGL(k_cycle_init, dim3((ns + 63) / 64), dim3(64), 0, s, S, ns);
-  return hipGetLastError();
-}
-
-hipError_t gmres_zero_col(const GmresState& S, int ns, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_col, dim3((ns + 63) / 64), dim3(64), 0, s, S, ns);
   return hipGetLastError();
 }
 

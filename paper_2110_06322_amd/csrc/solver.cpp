@@ -259,7 +259,6 @@ void issue_step(cpm_batch_s& Bt, const GmresState& S, int m, int j, bool tr, hip
   if (ae) hip_check(hipEventRecord(ae[0], st), "event");
   batch_apply(Bt, Zj, Bt.w.p, tr, st, gate);
   if (ae) hip_check(hipEventRecord(ae[1], st), "event");
-  hip_check(gmres_zero_col(S, ns, st), "zero col");
   for (int pass = 0; pass < 2; ++pass) {
     hip_check(vec_dots(R, Bt.V.p, Ns, j + 1, Bt.w.p, Bt.d_chunks.p, Bt.nchunks, Bt.act.p, Bt.part.p, st), "dots");
     hip_check(vec_reduce(R, Bt.part.p, j + 1, Bt.nchunks, Bt.d_cbeg.p, ns, Bt.hv.p, m + 1, Bt.hcol.p, m + 1, st),
