@@ -9,7 +9,7 @@ namespace cpm {
 
 constexpr int kMaxRestart = 64;
 constexpr int kMaxSystems = 1024;
-constexpr int64_t kChunkNodes = 2048;
+constexpr int64_t kChunkNodes = 512;
 
 // a contiguous node range of one instance inside the packed vectors
 struct Chunk {

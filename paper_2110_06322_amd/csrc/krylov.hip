@@ -79,30 +79,28 @@ __global__ void __launch_bounds__(kVecThreads) k_dots(const double* __restrict__
   }
 }
 
-// out[s*ld + i] (= or +=) sum over the chunks of inst(s) of part[(i*nchunks + c)*R + r]
+// out[s*ld + i] (= or +=) sum over the chunks of inst(s) of part[(i*nchunks + c)*R + r].
+// One wavefront per (s, i): lane l adds chunks l, l+64, ... in order, then a
+// fixed butterfly over the lanes; the order depends only on the instance's
+// chunk count, so a batch reproduces each solo solve.
 template <int R>
-__global__ void k_reduce(const double* __restrict__ part, int m, int nchunks, const int32_t* __restrict__ cbeg,
-                         int ns, double* __restrict__ out, int ld, double* __restrict__ accum, int accum_ld) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ns * m) return;
+__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ part, int m, int nchunks,
+                                                const int32_t* __restrict__ cbeg, int ns, double* __restrict__ out,
+                                                int ld, double* __restrict__ accum, int accum_ld) {
+  const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (t >= ns * m) return;   // uniform over the wavefront
+  const int lane = __lane_id();
   const int s = t / m, i = t % m;
   const int inst = s / R, r = s % R;
-  // chunks summed in order; loads are issued eight at a time so that their
-  // latencies overlap instead of forming one chain
   const double* pp = part + (int64_t)i * nchunks * R + r;
   const int c0 = cbeg[inst], c1 = cbeg[inst + 1];
   double sum = 0.0;
-  int c = c0;
-  for (; c + 8 <= c1; c += 8) {
-    double v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = pp[(int64_t)(c + q) * R];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) sum += v[q];
+  for (int c = c0 + lane; c < c1; c += 64) sum += pp[(int64_t)c * R];
+  sum = wave_sum(sum);
+  if (lane == 0) {
+    out[(int64_t)s * ld + i] = sum;
+    if (accum) accum[(int64_t)s * accum_ld + i] += sum;
   }
-  for (; c < c1; ++c) sum += pp[(int64_t)c * R];
-  out[(int64_t)s * ld + i] = sum;
-  if (accum) accum[(int64_t)s * accum_ld + i] += sum;
 }
 
 // w -= sum_{i<m} hv[s][i] V_i; optionally norm partials of the new w
@@ -353,7 +351,7 @@ hipError_t vec_reduce(int R, const double* part, int m, int nchunks, const int32
                       int ld, double* accum, int accum_ld, hipStream_t s) {
   const int n = ns * m;
   if (n == 0) return hipSuccess;
-  CPM_R_DISPATCH(R, hipLaunchKernelGGL((k_reduce<RR>), dim3((n + 127) / 128), dim3(128), 0, s, part, m, nchunks,
+  CPM_R_DISPATCH(R, hipLaunchKernelGGL((k_reduce<RR>), dim3((n + 3) / 4), dim3(256), 0, s, part, m, nchunks,
                                        cbeg, ns, out, ld, accum, accum_ld));
   return hipGetLastError();
 }
