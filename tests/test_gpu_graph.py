@@ -76,3 +76,19 @@ def test_graph_rejects_profile(sphere):
     b, op, f, pcs = sphere
     with pytest.raises(CpmError):
         cpm.solve(op, f, pc=pcs["fp64"], rtol=1e-8, use_graph=True, profile=True)
+
+
+def test_graph_packet_layout_equals_eager(sphere):
+    """Distance-ordered factors (packet subdomain solves) inside captured cycles."""
+    b, op, f, _ = sphere
+    pc = cpm.Precond(op, kind="oras", n_parts=16, overlap=2.0, precision="fp32", ordering="distance")
+    u0, s0 = cpm.solve(op, f, pc=pc, rtol=1e-9, mode="mixed", max_it=3000)
+    assert s0["converged"]
+    for _ in range(2):
+        u1, s1 = cpm.solve(op, f, pc=pc, rtol=1e-9, mode="mixed", max_it=3000, use_graph=True)
+        torch.cuda.synchronize()
+        assert s1["iterations"] == s0["iterations"]
+        assert torch.equal(u1, u0)
+        y = op.apply(u1)
+        torch.cuda.synchronize()
+        assert torch.isfinite(y).all()

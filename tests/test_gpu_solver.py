@@ -48,13 +48,13 @@ def test_config1_unpreconditioned_gmres():
     assert err < 0.01
 
 
-@pytest.mark.parametrize("pc_kind", ["ras", "oras"])
-def test_preconditioned_solve_small_sphere(pc_kind):
+@pytest.mark.parametrize("pc_kind,ordering", [("ras", "rcm"), ("oras", "rcm"), ("ras", "distance"), ("oras", "distance")])
+def test_preconditioned_solve_small_sphere(pc_kind, ordering):
     lb = G.lib_band("sphere", (1.0,), 3, 0.1, 3)
     ob, E, O, A, P = G.oracle("sphere", (1.0,), 3, 0.1, 3, 1.0)
     keys, pos = G.mapping(lb, ob)
     op = cpm.Operator(lb, 1.0)
-    pc = cpm.Precond(op, kind=pc_kind, n_parts=8)
+    pc = cpm.Precond(op, kind=pc_kind, n_parts=8, ordering=ordering)
     _, cp, _ = lb.export()
     f = 21.0 * inputs.sphere_y4(cp[:lb.n_active], 2)
     u, st = cpm.solve(op, _t(f), pc=pc, rtol=1e-12)
@@ -131,8 +131,10 @@ def test_failure_modes():
     assert e.value.status == "CPM_ERR_ARG"
 
 
-def test_config2_oras_fp64_and_mixed():
-    """Unit sphere, h = 0.02, p = 3, c = 1, f = 21 Y_4 (seed 2), 64 ORAS boxes, overlap 2h."""
+@pytest.mark.parametrize("ordering", ["rcm", "distance"])
+def test_config2_oras_fp64_and_mixed(ordering):
+    """Unit sphere, h = 0.02, p = 3, c = 1, f = 21 Y_4 (seed 2), 64 ORAS boxes, overlap 2h
+    (distance order: the packet subdomain solves the bench times)."""
     lb = G.lib_band("sphere", (1.0,), 3, 0.02, 3)
     ob, E, O, A, P = G.oracle("sphere", (1.0,), 3, 0.02, 3, 1.0)
     keys, pos = G.mapping(lb, ob)
@@ -144,7 +146,8 @@ def test_config2_oras_fp64_and_mixed():
     fo = 21.0 * inputs.sphere_y4(ob.cp_active, 2)
     out = {}
     for name, prec, mode in [("fp64", "fp64", "fp64"), ("mixed", "fp32", "mixed")]:
-        pc = cpm.Precond(op, kind="oras", n_parts=64, precision=prec)
+        pc = cpm.Precond(op, kind="oras", n_parts=64, precision=prec, ordering=ordering)
+        cpm.autotune(op, pc)
         u, st = cpm.solve(op, _t(f), pc=pc, rtol=1e-8, mode=mode, max_it=20000)
         print(name, st, flush=True)
         assert st["converged"], st
