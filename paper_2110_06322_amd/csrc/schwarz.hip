@@ -424,12 +424,14 @@ __global__ void __launch_bounds__(kSchwarzThreads) k_schwarz_v(const DevPC* __re
 // lanes) solves the packet's row g, lane t of the group taking entries t,
 // t+16, ... up to the packet's length class (4, 8 or 12 entries per lane, rows
 // of up to 64, 128 or 192 entries; the host packs rows of one class together,
-// and each class has its own unrolled code). The dependencies of a row are all
-// issued before the first wait, re-polled together until none reads the sentinel, and the group's sum is
-// formed in a fixed order (entries of a lane in increasing order, then a DPP
-// prefix sum over the 16 lanes). Rows of one packet never depend on each other,
-// and packets follow the level order, so the earliest unfinished packet always
-// has its inputs: the sweep always advances.
+// and each class has its own unrolled poll and sum code, while entries are
+// always fetched as 12 slots, which keeps the two row buffers in registers).
+// The dependencies of a row are all issued before the first wait and re-polled
+// together until none reads the sentinel, and the group's sum is formed in a
+// fixed order (entries of a lane in increasing order, then a DPP prefix sum
+// over the 16 lanes). Rows of one packet never depend on each other, and
+// packets follow the level order, so the earliest unfinished packet always has
+// its inputs: the sweep always advances.
 template <class T, int NRHS>
 struct PacketRow {
   uint64_t rec;
@@ -481,7 +483,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
   // Entries t, t+16, ... of the row, loaded unconditionally at immediate offsets
   // from one address: slots past the row's end read the entries that follow it
   // (the factor arrays are padded), and solve_row masks them out.
-  // (NJc: the packet's entry slots per lane, a std::integral_constant)
+  // (NJc: entry slots per lane, a std::integral_constant)
   auto fetch_n = [&](auto NJc, PacketRow<T, NRHS>& D, uint32_t w, uint64_t r, int gi) __attribute__((always_inline)) {
     constexpr int NJ = decltype(NJc)::value;
     D.rec = r;
