@@ -494,8 +494,10 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
     const auto vp = val + e0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      D.k[j] = cp[kPacketLanes * j];
-      D.v[j] = vp[kPacketLanes * j];
+      if (j < packet_slots(1) || D.cls == 2) {   // uniform: the last four slots only for the longest class
+        D.k[j] = cp[kPacketLanes * j];
+        D.v[j] = vp[kPacketLanes * j];
+      }
     }
     if (BACKWARD) {
       D.dq = dinv[(int)(r >> 48)];
