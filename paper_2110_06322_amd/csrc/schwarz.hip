@@ -494,7 +494,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
     const auto vp = val + e0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      if (j < packet_slots(1) || D.cls == 2) {   // uniform: the last four slots only for the longest class
+      if (j < packet_slots(D.cls)) {   // uniform: only the slots of the packet's class
         D.k[j] = cp[kPacketLanes * j];
         D.v[j] = vp[kPacketLanes * j];
       }
