@@ -710,8 +710,10 @@ static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkIt
     // one extra slot per array: the always-complete zero of masked entries
     const bool flags = cfg.variant == kSchwarzPacketFlags ||
                        schwarz_value_lds(max_rows + 1, NRHS, sizeof(T)) > kSchwarzMaxLds;
-    if (max_len > kPacketLanes * kPacketEntries || threads > packet_max_threads(sizeof(T) == 4, NRHS, flags))
-      return hipErrorInvalidValue;
+    if (max_len > kPacketLanes * kPacketEntries) return hipErrorInvalidValue;
+    // the flag form may stand in for the value form: keep within its register
+    // budget (the thread count does not change results)
+    const int pthreads = min(threads, packet_max_threads(sizeof(T) == 4, NRHS, flags));
     const size_t shm = flags ? (size_t)(max_rows + 1) * (NRHS * sizeof(T) + sizeof(int))
                              : schwarz_value_lds(max_rows + 1, NRHS, sizeof(T));
     const void* kern = flags ? (cfg.sleep ? (const void*)k_schwarz_p<T, NRHS, true, true>
@@ -721,16 +723,16 @@ static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkIt
     hipError_t e = lds_ok(kern, shm);
     if (e != hipSuccess) return e;
     if (flags && cfg.sleep)
-      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, true, true>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r,
+      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, true, true>), dim3(nwork), dim3(pthreads), shm, s, pcs, work, nwork, r,
                          z, gate);
     else if (flags)
-      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, false, true>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r,
+      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, false, true>), dim3(nwork), dim3(pthreads), shm, s, pcs, work, nwork, r,
                          z, gate);
     else if (cfg.sleep)
-      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, true, false>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork, r,
+      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, true, false>), dim3(nwork), dim3(pthreads), shm, s, pcs, work, nwork, r,
                          z, gate);
     else
-      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, false, false>), dim3(nwork), dim3(threads), shm, s, pcs, work, nwork,
+      hipLaunchKernelGGL((k_schwarz_p<T, NRHS, false, false>), dim3(nwork), dim3(pthreads), shm, s, pcs, work, nwork,
                          r, z, gate);
     return hipGetLastError();
   }
