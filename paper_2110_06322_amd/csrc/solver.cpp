@@ -662,8 +662,13 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
         SchwarzCfg bestc = Bt.pc_cfg;
         for (const SchwarzCfg& c : tune::schwarz_candidates(Bt.pc_packets, Bt.pc_fp32 != 0, Bt.R)) {
           Bt.pc_cfg = c;
+          if (!tune::launchable(run)) continue;
           const double ms = tune::time_ms(run, reps, s);
           if (ms < best) { best = ms; bestc = c; }
+        }
+        if (best >= 1e30) {
+          Bt.pc_cfg = bestc;
+          fail(CPM_ERR_ARG, "subdomains too large for the local-memory budget at this nrhs/precision");
         }
         Bt.pc_cfg = bestc;
         cache[key] = {bestc.variant, bestc.threads, bestc.sleep};

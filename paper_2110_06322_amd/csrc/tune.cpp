@@ -136,6 +136,13 @@ std::string device_tag() {
   return name + "-cu" + std::to_string(prop.multiProcessorCount);
 }
 
+bool launchable(const std::function<hipError_t()>& f) {
+  const hipError_t e = f();
+  if (e == hipErrorInvalidConfiguration) return false;   // rejected before any launch
+  hip_check(e, "tune launch");
+  return true;
+}
+
 double time_ms(const std::function<hipError_t()>& f, int reps, hipStream_t s) {
   hipEvent_t a, b;
   hip_check(hipEventCreate(&a), "tune");
@@ -231,8 +238,14 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
         SchwarzCfg bestc = pc->cfg;
         for (const SchwarzCfg& c : schwarz_candidates(pc->packets, pc->P.fp32 != 0, nrhs)) {
           pc->cfg = c;
-          const double ms = time_ms([&] { return precond_apply_raw(pc, x.p, y.p, nrhs, s); }, reps, s);
+          auto run = [&] { return precond_apply_raw(pc, x.p, y.p, nrhs, s); };
+          if (!launchable(run)) continue;
+          const double ms = time_ms(run, reps, s);
           if (ms < best) { best = ms; bestc = c; }
+        }
+        if (best >= 1e30) {
+          pc->cfg = bestc;
+          fail(CPM_ERR_ARG, "subdomains too large for the local-memory budget at this nrhs/precision");
         }
         pc->cfg = bestc;
         cache[key] = {bestc.variant, bestc.threads, bestc.sleep};

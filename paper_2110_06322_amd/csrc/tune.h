@@ -23,6 +23,9 @@ std::string device_tag();                            // e.g. "gfx950-cu256"
 bool valid_schwarz(const std::vector<int>& v, bool packets, bool fp32, int nrhs);
 // candidate kernels; all candidates for one layout compute bit-identical results
 std::vector<SchwarzCfg> schwarz_candidates(bool packets, bool fp32, int nrhs);
+// false when f's kernel cannot be launched at this size (its local memory
+// exceeds the limit); other launch errors throw
+bool launchable(const std::function<hipError_t()>& f);
 // mean milliseconds of `reps` launches of f after two warm-up launches
 double time_ms(const std::function<hipError_t()>& f, int reps, hipStream_t s);
 
