@@ -121,3 +121,19 @@ def test_packet_variants_bit_identical(sphere, tmp_path, prec, nrhs):
     _force(cache, "schwarz|", [1, 1024, 1])
     res = cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
     assert res["from_cache"] == 0 and res["schwarz_variant"] in (2, 3)
+
+
+def test_tuner_skips_kernels_that_do_not_fit_local_memory():
+    """FP64 with 4 right-hand sides on config 2's subdomains (about 4400 rows): the value
+    kernel's two arrays exceed the LDS and its configurations run the completion-flag kernel,
+    which fits; with 16 subdomains nothing fits and the tuner says so instead of failing a
+    launch."""
+    G.ensure_built()
+    b = G.lib_band("sphere", (1.0,), 3, 0.02, 3)
+    op = cpm.Operator(b, 1.0)
+    pc = cpm.Precond(op, kind="oras", n_parts=64, precision="fp64")
+    r = cpm.autotune(op, pc, nrhs=4)
+    assert r["schwarz_variant"] in (0, 1) and r["precond_ms"] > 0
+    big = cpm.Precond(op, kind="oras", n_parts=16, precision="fp64")
+    with pytest.raises(Exception, match="local-memory"):
+        cpm.autotune(op, big, nrhs=4)
