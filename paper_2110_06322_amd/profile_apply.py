@@ -1,8 +1,10 @@
-"""Short, profiler-friendly driver: a fixed number of operator applies on one
-workload and a device-to-device copy of known size (the copy calibrates the
-hardware byte counters against a kernel whose traffic is exactly known).
+"""Short, profiler-friendly driver: a fixed number of operator applies (or,
+with a fourth argument, ORAS preconditioner applies with that local row order
+and FP32 factors, 64 subdomains, overlap 2h) on one workload and a
+device-to-device copy of known size (the copy calibrates the hardware byte
+counters against a kernel whose traffic is exactly known).
 
-Usage: python -m paper_2110_06322_amd.profile_apply [sphere|torus] [h] [reps]
+Usage: python -m paper_2110_06322_amd.profile_apply [sphere|torus] [h] [reps] [rcm|distance]
 """
 from __future__ import annotations
 
@@ -22,8 +24,15 @@ def main():
     op = cpm.Operator(band, 1.0)
     x = torch.tensor(inputs.normal(1, 0, band.active_keys), dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
-    for _ in range(reps):
-        op.apply(x, out=y)
+    ordering = sys.argv[4] if len(sys.argv) > 4 else None
+    if ordering:
+        pc = cpm.Precond(op, kind="oras", n_parts=64, overlap=2.0, precision="fp32", ordering=ordering)
+        cpm.autotune(op, pc)
+        for _ in range(reps):
+            pc.apply(x, out=y)
+    else:
+        for _ in range(reps):
+            op.apply(x, out=y)
     a = torch.zeros(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")  # 64 MiB
     b = torch.empty_like(a)
     for _ in range(4):
