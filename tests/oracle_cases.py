@@ -32,7 +32,7 @@ def matrices(kind: str, params: tuple, d: int, h: float, p: int, c: float, box=N
     return bd, E, Om, O.values_on_pattern(A, P), P
 
 
-def config1():
+def circle_h005():
     """2-D unit circle, h = 0.05, p = 2, c = 1, f = (c+1) sin(theta(cp))."""
     return matrices("circle", (1.0,), 2, 0.05, 2, 1.0)
 

@@ -77,7 +77,7 @@ def test_band_matches_oracle(kind, params, d, h, p):
     assert np.array_equal(cl, co) or kind == "ellipsoid"
 
 
-def test_band_config2_sizes_and_bitwise_cp():
+def test_band_sphere_h002_sizes_and_bitwise_cp():
     lb, ob, cl, co = _compare("sphere", (1.0,), 3, 0.02, 3)
     assert (lb.n_band, lb.n_active, lb.n_ghost) == (260062, 187924, 52424)
     assert np.array_equal(cl, co)

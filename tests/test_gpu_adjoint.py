@@ -53,7 +53,7 @@ def test_adjoint_matches_oracle_direct_small():
     assert abs(gc - gco) <= 1e-9 * abs(gco)
 
 
-def test_adjoint_config4_finite_differences():
+def test_adjoint_torus_h001_finite_differences():
     """Torus R=1, r=0.4, h=0.01, p=3, c=1: gradient in f at 16 seeded nodes and in c vs central differences."""
     lb = G.lib_band("torus", (1.0, 0.4), 3, 0.01, 3)
     _, cp, _ = lb.export()

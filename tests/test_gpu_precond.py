@@ -88,7 +88,7 @@ def test_precond_multi_rhs_matches_single(nrhs, ordering, precision):
 
 
 @pytest.mark.parametrize("ordering", ["rcm", "distance"])
-def test_precond_config2_sampled_subdomains(ordering):
+def test_precond_sphere_h002_sampled_subdomains(ordering):
     """Sphere h = 0.02, p = 3, ORAS with 64 boxes, overlap 2h: partition exact, three subdomains' solves."""
     lb, ob, A, P, keys, pos, op, pc = _setup("sphere", (1.0,), 0.02, 64, "oras", ordering=ordering)
     owner, ptr, idx = pc.export_partition()

@@ -25,7 +25,7 @@ def _t(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
 
 
-def test_config1_unpreconditioned_gmres():
+def test_circle_h005_unpreconditioned_gmres():
     """2-D unit circle, h = 0.05, p = 2, c = 1, f = 2 sin(theta(cp)), GMRES(30) to 1e-10."""
     lb = G.lib_band("circle", (1.0,), 2, 0.05, 2)
     ob, E, O, A, P = G.oracle("circle", (1.0,), 2, 0.05, 2, 1.0)
@@ -132,7 +132,7 @@ def test_failure_modes():
 
 
 @pytest.mark.parametrize("ordering", ["rcm", "distance"])
-def test_config2_oras_fp64_and_mixed(ordering):
+def test_sphere_h002_oras_fp64_and_mixed(ordering):
     """Unit sphere, h = 0.02, p = 3, c = 1, f = 21 Y_4 (seed 2), 64 ORAS boxes, overlap 2h
     (distance order: the packet subdomain solves the bench times)."""
     lb = G.lib_band("sphere", (1.0,), 3, 0.02, 3)

@@ -124,7 +124,7 @@ def test_packet_variants_bit_identical(sphere, tmp_path, prec, nrhs):
 
 
 def test_tuner_skips_kernels_that_do_not_fit_local_memory():
-    """FP64 with 4 right-hand sides on config 2's subdomains (about 4400 rows): the value
+    """FP64 with 4 right-hand sides on the unit-sphere h = 0.02 subdomains (about 4400 rows): the value
     kernel's two arrays exceed the LDS and its configurations run the completion-flag kernel,
     which fits; with 16 subdomains nothing fits and the tuner says so instead of failing a
     launch."""

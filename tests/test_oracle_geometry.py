@@ -112,7 +112,7 @@ def test_band_size_matches_tube_volume(kind, params, d, h, p, area):
     assert abs(bd.n_band - vol) / vol < 0.01
 
 
-def test_band_config1_sizes():
+def test_band_circle_h005_sizes():
     bd = C.band("circle", (1.0,), 2, 0.05, 2)
     assert (bd.n_band, bd.n_active, bd.n_ghost) == (732, 464, 228)
 

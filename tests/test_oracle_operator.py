@@ -81,7 +81,7 @@ def test_A_constant_vector(kind, params, d, h, p, c):
 def test_A_2d_matches_semidiscrete_form():
     """d = 2: (A u)_i = c u_i + 4/h^2 u_i - h^-2 sum_{4 nbrs} (E u)(nbr)  (Sec. 3.1.2, eq. semiDisc),
     checked on a field that is constant along normals, where (E u)(nbr) = u(cp(nbr)) up to O(h^3)."""
-    bd, E, Om, A, P = C.config1()
+    bd, E, Om, A, P = C.circle_h005()
     h = bd.h
     u = inputs.circle_sin(bd.cp_active)
     nb_cp = []

@@ -20,8 +20,8 @@ from paper_2110_06322_amd import inputs
 from tests import oracle_cases as C
 
 
-def test_gmres_matches_dense_solve_config1():
-    bd, E, Om, A, P = C.config1()
+def test_gmres_matches_dense_solve_circle_h005():
+    bd, E, Om, A, P = C.circle_h005()
     f = 2.0 * inputs.circle_sin(bd.cp_active)
     x, info = krylov.fgmres(A, f, restart=30, rtol=1e-10)
     xd = np.linalg.solve(A.toarray(), f)
