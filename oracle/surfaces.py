@@ -18,8 +18,11 @@ def cp_sphere(x: np.ndarray, center, R: float) -> np.ndarray:
         n = np.sqrt(q[:, 0] * q[:, 0] + q[:, 1] * q[:, 1])
     else:
         n = np.sqrt(q[:, 0] * q[:, 0] + q[:, 1] * q[:, 1] + q[:, 2] * q[:, 2])
-    s = R / n
-    return np.asarray(center, dtype=np.float64) + s[:, None] * q
+    # the centre itself has no unique closest point; its NaN lies far outside
+    # any band and is never used
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = R / n
+        return np.asarray(center, dtype=np.float64) + s[:, None] * q
 
 
 def cp_torus(x: np.ndarray, R: float, r: float) -> np.ndarray:
