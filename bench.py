@@ -369,7 +369,9 @@ def main():
                              "achieved": round(b_pc / (ms_pc * 1e-3) / 1e9, 1) if ms_pc > 0 else None,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(b_pc / (ms_pc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms_pc > 0 else None,
-                             "bytes_per_launch": int(b_pc), "max_levels": int(pci.max_levels)},
+                             "bytes_per_launch": int(b_pc), "max_levels": int(pci.max_levels),
+                             "limited_by": "dependency levels and instruction issue: one workgroup per "
+                                           "subdomain, so 64 of the 256 CUs work"},
     }
     if a.batched:
         from paper_2110_06322_amd import workloads
