@@ -219,12 +219,24 @@ def cpu_baseline(seconds_budget=20.0):
                       f"N_A={bd.n_active}) in {el:.1f} s"}
 
 
+APPLY_SOURCES = ("apply.hip", "operator.cpp", "device.h")
+
+
+def apply_sources_sha():
+    """First 16 hex digits of the SHA-256 of the apply kernel's source and the host code
+    that lays out its tiles and work list, concatenated in APPLY_SOURCES order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in APPLY_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2110_06322_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per apply launch from the committed counter summary, or None when the
-    kernel source changed since the counters were taken."""
-    import hashlib
+    kernel source, or the host code that builds its tiles and work order, changed since
+    the counters were taken."""
     f = os.path.join(ROOT, "profiles", "k_apply_pipe_sphere_h0.02_counters.md")
-    src = os.path.join(ROOT, "paper_2110_06322_amd", "csrc", "apply.hip")
     if not os.path.exists(f):
         return None
     vals = {}
@@ -232,8 +244,7 @@ def measured_traffic():
         if ":" in line and line.split(":")[0].strip() in ("traffic_bytes_per_launch", "kernel_source_sha256_16"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if vals.get("kernel_source_sha256_16") != sha:
+    if vals.get("kernel_source_sha256_16") != apply_sources_sha():
         return None
     return int(vals["traffic_bytes_per_launch"])
 

@@ -66,6 +66,10 @@ hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* z
 inline int vbox_nodes(int d) { return d == 3 ? 10 * 10 * 10 : 18 * 18; }
 // footprint bricks a tile may stage in the pipelined apply (8 per wavefront)
 constexpr int kMaxFootBricks = 64;
+// operators with at most this many LDS-path tiles order them by cost (up to
+// 16 rounds of the persistent apply's 512 workgroups; beyond that the balance
+// gained is small and brick order's L2 locality is worth more)
+constexpr int kCostOrderMaxTiles = 8192;
 
 // LDS of the fused apply besides the footprint: the tile's box of extension values
 inline size_t tile_lds_extra_bytes(int d) { return (size_t)vbox_nodes(d) * 8; }

@@ -282,6 +282,21 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
         slow.push_back(WorkItem{0, (int32_t)t});
       }
     }
+    // Few tiles per persistent workgroup: the slowest workgroup sets the
+    // time. Within each of the eight per-XCD ranges of the work list the
+    // tiles then go heaviest first (most extension rows), so the last,
+    // partial round of tiles is the lightest. Larger operators keep brick
+    // order, which keeps concurrently processed tiles neighbours in L2.
+    if (fast.size() <= (size_t)kCostOrderMaxTiles) {
+      const size_t nw = fast.size();
+      for (size_t x = 0; x < 8; ++x) {
+        const size_t s = nw * x / 8, e = nw * (x + 1) / 8;
+        std::stable_sort(fast.begin() + (ptrdiff_t)s, fast.begin() + (ptrdiff_t)e,
+                         [&](const WorkItem& a, const WorkItem& b) {
+                           return op->tiles[a.idx].job_cnt > op->tiles[b.idx].job_cnt;
+                         });
+      }
+    }
     op->d_work.upload(fast);
     {
       std::vector<DevTile> wt;
