@@ -529,7 +529,8 @@ __device__ __forceinline__ void pipe_data(const InstView& I, const PipeRec& R, c
 
 template <int D, int P>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_apply_pipe(const DevInst* __restrict__ insts,
-                                                    const DevTile* __restrict__ wtiles, int nwork, int ucap,
+                                                    const DevTile* __restrict__ wtiles,
+                                                    const PipeSpan* __restrict__ plan, int ucap,
                                                     const double* __restrict__ x, double* __restrict__ y,
                                                     Gate gate) {
   extern __shared__ double smem[];
@@ -541,9 +542,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   int l[3];
   local_of<D>(lane, l);
-  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
-  const int w_end = (int)(((int64_t)nwork * (xcd + 1)) >> 3);
-  int w = (int)(((int64_t)nwork * xcd) >> 3) + (blockIdx.x >> 3);
+  const PipeSpan span = plan[blockIdx.x];
+  const int per = span.step, w_end = span.end;
+  int w = span.first;
   if (w >= w_end) return;  // uniform over the workgroup, before any barrier
 
   // slot in V of this thread's stencil row (fixed: wavefront = tile brick, lane = node)
@@ -778,15 +779,15 @@ static int pipe_grid(int nwork, size_t shm, const void* kern) {
 }
 
 template <int D, int P, int NRHS>
-static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkItem* work, const DevTile* wtiles,
+static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkItem* work, const PipeWork& pw,
                                  int nwork, int ucap, const WorkItem* fb, int nfb, const double* x, double* y,
                                  hipStream_t s, const Gate& gate) {
   if (nwork > 0) {
     const size_t shm = (size_t)ucap * sizeof(double) + tile_lds_extra<D>();
     if (NRHS == 1 && variant == kApplyPipelined) {
-      if (!wtiles) return hipErrorInvalidValue;
-      const int grid = pipe_grid(nwork, shm, (const void*)k_apply_pipe<D, P>);
-      hipLaunchKernelGGL((k_apply_pipe<D, P>), dim3(grid), dim3(512), shm, s, insts, wtiles, nwork, ucap, x, y, gate);
+      if (!pw.wtiles || !pw.plan || pw.nplan <= 0) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_apply_pipe<D, P>), dim3(pw.nplan), dim3(512), shm, s, insts, pw.wtiles, pw.plan, ucap, x,
+                         y, gate);
     } else {
       hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(nwork), dim3(512), shm, s, insts, work, nwork, ucap, x,
                          y, gate);
@@ -798,11 +799,11 @@ static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkIt
 }
 
 hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work,
-                        const DevTile* wtiles, int nwork, int ucap, const WorkItem* fb, int nfb, const double* x,
+                        const PipeWork& pw, int nwork, int ucap, const WorkItem* fb, int nfb, const double* x,
                         double* y, hipStream_t s, const Gate& gate) {
 #define CPM_CASE(D, P, R) \
   if (d == D && p == P && nrhs == R)                                                              \
-    return launch_apply_t<D, P, R>(variant, insts, work, wtiles, nwork, ucap, fb, nfb, x, y, s, gate);
+    return launch_apply_t<D, P, R>(variant, insts, work, pw, nwork, ucap, fb, nfb, x, y, s, gate);
   CPM_CASE(3, 3, 1) CPM_CASE(3, 3, 2) CPM_CASE(3, 3, 4)
   CPM_CASE(3, 2, 1) CPM_CASE(3, 2, 2) CPM_CASE(3, 2, 4)
   CPM_CASE(3, 1, 1) CPM_CASE(3, 1, 2) CPM_CASE(3, 1, 4)
@@ -811,6 +812,15 @@ hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* inst
   CPM_CASE(2, 1, 1) CPM_CASE(2, 1, 2) CPM_CASE(2, 1, 4)
 #undef CPM_CASE
   return hipErrorInvalidValue;
+}
+
+int apply_pipe_grid(int d, int p, int nwork, int ucap) {
+#define CPM_CASE(D, P)                                                                             \
+  if (d == D && p == P)                                                                            \
+    return pipe_grid(nwork, (size_t)ucap * sizeof(double) + tile_lds_extra<D>(), (const void*)k_apply_pipe<D, P>);
+  CPM_CASE(3, 3) CPM_CASE(3, 2) CPM_CASE(3, 1) CPM_CASE(2, 3) CPM_CASE(2, 2) CPM_CASE(2, 1)
+#undef CPM_CASE
+  return 0;
 }
 
 hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream_t s) {

@@ -54,11 +54,21 @@ struct DevBuf {
 
 // kernel launchers (apply.hip)
 // gate: lets Krylov cycles skip instances whose systems have stopped (see Gate)
-// wtiles[w]: copy of the tile of work item w (with its instance), read by the
-// pipelined kernel in one load instead of a work item -> instance -> tile chain
 hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work,
-                        const DevTile* wtiles, int nwork, int ucap, const WorkItem* fb, int nfb, const double* x,
+                        const PipeWork& pw, int nwork, int ucap, const WorkItem* fb, int nfb, const double* x,
                         double* y, hipStream_t s, const Gate& gate = Gate{});
+// workgroups of the persistent apply for a work list (a multiple of 8: as many
+// as are resident at once, at most one per work item, rounded up)
+int apply_pipe_grid(int d, int p, int nwork, int ucap);
+// Orders a work list for the persistent apply and gives each of `grid`
+// workgroups its span (workgroup b runs on XCD b mod 8 and takes tiles of that
+// XCD's eighth of the list). Lists of at most kCostOrderMaxTiles items are
+// balanced by cost (heaviest first, each to the least loaded workgroup of its
+// XCD, whose tiles then lie contiguous); longer lists keep their order and the
+// workgroups of an XCD walk its eighth with a stride, so that tiles processed
+// at the same time are neighbours in L2.
+void plan_pipe(std::vector<WorkItem>& work, const std::vector<int32_t>& cost, int grid,
+               std::vector<PipeSpan>& plan);
 hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream_t s);
 hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* zscratch, double* y,
                           hipStream_t s, const Gate& gate = Gate{}, int inst = 0);
@@ -66,10 +76,12 @@ hipError_t launch_apply_T(const DevInst& I, int nrhs, const double* x, double* z
 inline int vbox_nodes(int d) { return d == 3 ? 10 * 10 * 10 : 18 * 18; }
 // footprint bricks a tile may stage in the pipelined apply (8 per wavefront)
 constexpr int kMaxFootBricks = 64;
-// operators with at most this many LDS-path tiles order them by cost (up to
-// 16 rounds of the persistent apply's 512 workgroups; beyond that the balance
+// work lists of at most this many tiles are balanced by cost (up to 16 tiles
+// per workgroup of a 512-workgroup persistent apply; beyond that the balance
 // gained is small and brick order's L2 locality is worth more)
 constexpr int kCostOrderMaxTiles = 8192;
+// fixed cost of a tile in the balance, in extension rows
+constexpr int kTileCostBase = 128;
 
 // LDS of the fused apply besides the footprint: the tile's box of extension values
 inline size_t tile_lds_extra_bytes(int d) { return (size_t)vbox_nodes(d) * 8; }
@@ -93,6 +105,9 @@ struct cpm_operator_s {
   std::vector<int32_t> tile_fvol;           // footprint nodes per tile
   cpm::DevBuf<cpm::WorkItem> d_work, d_fb;      // (instance 0, tile) lists: LDS path / fallback
   cpm::DevBuf<cpm::DevTile> d_wtiles;           // tiles of d_work in work order
+  cpm::DevBuf<cpm::PipeSpan> d_plan;            // spans of the persistent apply's workgroups
+  int nplan = 0;
+  cpm::PipeWork pipe() const { return cpm::PipeWork{d_wtiles.p, d_plan.p, nplan}; }
   std::vector<cpm::WorkItem> h_work, h_fb;
   int nwork = 0, nfb = 0, ucap = 0;
   int apply_variant = cpm::kApplyPipelined;   // one-RHS apply kernel (tunable)

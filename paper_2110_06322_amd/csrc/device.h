@@ -78,4 +78,19 @@ struct WorkItem {
   int32_t inst, idx;
 };
 
+// work items one workgroup of the persistent apply takes: positions first,
+// first + step, ... below end of the work list
+struct PipeSpan {
+  int32_t first, end, step, pad;
+};
+
+// persistent apply's view of a work list: wtiles[w] is a copy of the tile of
+// work item w (with its instance), read in one load instead of a work item ->
+// instance -> tile chain; plan[b] the span of workgroup b (nplan workgroups)
+struct PipeWork {
+  const DevTile* wtiles = nullptr;
+  const PipeSpan* plan = nullptr;
+  int nplan = 0;
+};
+
 }  // namespace cpm

@@ -210,6 +210,43 @@ void build_buckets(const cpm_band_s& B, std::vector<int32_t>& ptr, std::vector<i
 
 }  // namespace
 
+void cpm::plan_pipe(std::vector<WorkItem>& work, const std::vector<int32_t>& cost, int grid,
+               std::vector<PipeSpan>& plan) {
+  plan.clear();
+  const int64_t n = (int64_t)work.size();
+  if (n == 0 || grid <= 0) return;
+  const int per = grid / 8;
+  plan.assign((size_t)per * 8, PipeSpan{0, 0, 1, 0});
+  const bool by_cost = n <= kCostOrderMaxTiles;
+  std::vector<WorkItem> out(work.size());
+  for (int x = 0; x < 8; ++x) {
+    const int64_t s = n * x / 8, e = n * (x + 1) / 8;
+    if (!by_cost) {
+      for (int j = 0; j < per; ++j) plan[(size_t)j * 8 + x] = PipeSpan{(int32_t)(s + j), (int32_t)e, per, 0};
+      for (int64_t i = s; i < e; ++i) out[i] = work[i];
+      continue;
+    }
+    std::vector<int64_t> idx((size_t)(e - s));
+    for (int64_t i = s; i < e; ++i) idx[i - s] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    std::vector<int64_t> load(per, 0);
+    std::vector<std::vector<int64_t>> bins(per);
+    for (int64_t i : idx) {
+      int best = 0;
+      for (int j = 1; j < per; ++j)
+        if (load[j] < load[best]) best = j;
+      bins[best].push_back(i);
+      load[best] += kTileCostBase + cost[i];
+    }
+    int64_t pos = s;
+    for (int j = 0; j < per; ++j) {
+      plan[(size_t)j * 8 + x] = PipeSpan{(int32_t)pos, (int32_t)(pos + (int64_t)bins[j].size()), 1, 0};
+      for (int64_t i : bins[j]) out[pos++] = work[i];
+    }
+  }
+  work.swap(out);
+}
+
 cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out) {
   (void)stream;
   try {
@@ -282,20 +319,13 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
         slow.push_back(WorkItem{0, (int32_t)t});
       }
     }
-    // Few tiles per persistent workgroup: the slowest workgroup sets the
-    // time. Within each of the eight per-XCD ranges of the work list the
-    // tiles then go heaviest first (most extension rows), so the last,
-    // partial round of tiles is the lightest. Larger operators keep brick
-    // order, which keeps concurrently processed tiles neighbours in L2.
-    if (fast.size() <= (size_t)kCostOrderMaxTiles) {
-      const size_t nw = fast.size();
-      for (size_t x = 0; x < 8; ++x) {
-        const size_t s = nw * x / 8, e = nw * (x + 1) / 8;
-        std::stable_sort(fast.begin() + (ptrdiff_t)s, fast.begin() + (ptrdiff_t)e,
-                         [&](const WorkItem& a, const WorkItem& b) {
-                           return op->tiles[a.idx].job_cnt > op->tiles[b.idx].job_cnt;
-                         });
-      }
+    {
+      std::vector<int32_t> cost(fast.size());
+      for (size_t i = 0; i < fast.size(); ++i) cost[i] = op->tiles[fast[i].idx].job_cnt;
+      std::vector<PipeSpan> plan;
+      plan_pipe(fast, cost, fast.empty() ? 0 : apply_pipe_grid(d, B.p, (int)fast.size(), ucap), plan);
+      op->d_plan.upload(plan);
+      op->nplan = (int)plan.size();
     }
     op->d_work.upload(fast);
     {
@@ -363,7 +393,7 @@ cpm_status cpm_apply(const cpm_operator* op, const double* x, double* y, int32_t
     if (!op || !x || !y) fail(CPM_ERR_ARG, "null argument");
     if (nrhs != 1 && nrhs != 2 && nrhs != 4) fail(CPM_ERR_ARG, "nrhs must be 1, 2 or 4");
     if (x == y) fail(CPM_ERR_ARG, "x and y must not alias");
-    hip_check(launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->d_wtiles.p, op->nwork, op->ucap,
+    hip_check(launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->pipe(), op->nwork, op->ucap,
                            op->d_fb.p, op->nfb, x, y, (hipStream_t)stream),
               "cpm_apply");
     return CPM_OK;

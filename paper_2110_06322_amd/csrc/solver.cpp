@@ -34,7 +34,10 @@ struct cpm_batch_s {
   DevBuf<DevInst> d_insts;
   DevBuf<WorkItem> d_work, d_fb;
   DevBuf<DevTile> d_wtiles;   // tiles of d_work in work order, with their instance
+  DevBuf<PipeSpan> d_plan;     // spans of the persistent apply's workgroups
+  int nplan = 0;
   int nwork = 0, nfb = 0, ucap = 0;
+  PipeWork pipe() const { return PipeWork{d_wtiles.p, d_plan.p, nplan}; }
   int apply_variant = kApplyPipelined;
   SchwarzCfg pc_cfg;
   // preconditioners
@@ -129,6 +132,14 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
   }
   Bt.Ntot = Bt.off[n];
   Bt.d_insts.upload(Bt.hinst);
+  {
+    std::vector<int32_t> cost(fast.size());
+    for (size_t i = 0; i < fast.size(); ++i) cost[i] = ops[fast[i].inst]->tiles[fast[i].idx].job_cnt;
+    std::vector<PipeSpan> plan;
+    plan_pipe(fast, cost, fast.empty() ? 0 : apply_pipe_grid(Bt.d, Bt.p, (int)fast.size(), Bt.ucap), plan);
+    Bt.d_plan.upload(plan);
+    Bt.nplan = (int)plan.size();
+  }
   Bt.d_work.upload(fast);
   {
     std::vector<DevTile> wt;
@@ -218,7 +229,7 @@ GmresState state_of(cpm_batch_s& Bt, int m) {
 void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hipStream_t s,
                  const Gate& gate = Gate{}) {
   if (!transpose) {
-    hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.d_wtiles.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
+    hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.pipe(), Bt.nwork, Bt.ucap, Bt.d_fb.p,
                            Bt.nfb, x, y, s, gate),
               "operator apply");
     return;
@@ -621,7 +632,7 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
           Bt.apply_variant = v;
           const double ms = tune::time_ms(
               [&] {
-                return launch_apply(Bt.d, Bt.p, Bt.R, v, Bt.d_insts.p, Bt.d_work.p, Bt.d_wtiles.p, Bt.nwork, Bt.ucap, Bt.d_fb.p,
+                return launch_apply(Bt.d, Bt.p, Bt.R, v, Bt.d_insts.p, Bt.d_work.p, Bt.pipe(), Bt.nwork, Bt.ucap, Bt.d_fb.p,
                                     Bt.nfb, Bt.r.p, Bt.w.p, s);
               },
               reps, s);
@@ -634,7 +645,7 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
       out->apply_variant = Bt.apply_variant;
       out->apply_ms = tune::time_ms(
           [&] {
-            return launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.d_wtiles.p, Bt.nwork, Bt.ucap,
+            return launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.pipe(), Bt.nwork, Bt.ucap,
                                 Bt.d_fb.p, Bt.nfb, Bt.r.p, Bt.w.p, s);
           },
           reps, s);

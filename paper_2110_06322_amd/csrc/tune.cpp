@@ -203,7 +203,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
           const int v = cand[c];
           const double ms = time_ms(
               [&] {
-                return launch_apply(op->I.d, op->I.p, nrhs, v, op->d_inst.p, op->d_work.p, op->d_wtiles.p, op->nwork, op->ucap,
+                return launch_apply(op->I.d, op->I.p, nrhs, v, op->d_inst.p, op->d_work.p, op->pipe(), op->nwork, op->ucap,
                                     op->d_fb.p, op->nfb, x.p, y.p, s);
               },
               reps, s);
@@ -215,7 +215,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
       }
       out->apply_variant = op->apply_variant;
       auto f = [&] {
-        return launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->d_wtiles.p, op->nwork,
+        return launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->pipe(), op->nwork,
                             op->ucap, op->d_fb.p, op->nfb, x.p, y.p, s);
       };
       out->apply_ms = time_ms(f, reps, s);

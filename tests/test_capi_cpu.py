@@ -110,3 +110,21 @@ def test_band_reaching_the_medial_axis_is_rejected_by_both():
 def test_gamma_default_matches_formula():
     b = cpm.Band("sphere", (1.0,), 3, 0.1, 3)
     assert abs(b.gamma - inputs.ruuth_merriman_gamma(3, 3, 0.1)) < 1e-15
+
+
+def test_apply_work_plan_covers_every_tile_once(tmp_path):
+    """The persistent apply's work plan (host code in the library): each work
+    item goes to exactly one workgroup of its own XCD share, for cost-balanced
+    and strided plans alike (a small C++ driver linked against the library)."""
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    exe = str(tmp_path / "plan_pipe_check")
+    src = os.path.join(ROOT, "tests", "cpp", "plan_pipe_check.cpp")
+    lib_dir = os.path.dirname(_capi.LIB_PATH)
+    subprocess.run(["g++", "-O1", "-std=c++17", "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include", "-o", exe, src,
+                    _capi.LIB_PATH, f"-Wl,-rpath,{lib_dir}"], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
