@@ -220,23 +220,30 @@ def cpu_baseline(seconds_budget=20.0):
 
 
 APPLY_SOURCES = ("apply.hip", "operator.cpp", "device.h")
+SCHWARZ_SOURCES = ("schwarz.hip", "schwarz_api.cpp", "schwarz.cpp", "schwarz.h")
 
 
-def apply_sources_sha():
-    """First 16 hex digits of the SHA-256 of the apply kernel's source and the host code
-    that lays out its tiles and work list, concatenated in APPLY_SOURCES order."""
+def sources_sha(names):
+    """First 16 hex digits of the SHA-256 of the named library sources, concatenated in
+    the given order."""
     import hashlib
     h = hashlib.sha256()
-    for name in APPLY_SOURCES:
+    for name in names:
         h.update(open(os.path.join(ROOT, "paper_2110_06322_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per apply launch from the committed counter summary, or None when the
-    kernel source, or the host code that builds its tiles and work order, changed since
-    the counters were taken."""
-    f = os.path.join(ROOT, "profiles", "k_apply_pipe_sphere_h0.02_counters.md")
+def apply_sources_sha():
+    """Hash of the apply kernel's source and the host code that lays out its tiles and
+    work plan."""
+    return sources_sha(APPLY_SOURCES)
+
+
+def measured_traffic(summary="k_apply_pipe_sphere_h0.02_counters.md", sources=APPLY_SOURCES):
+    """HBM bytes per launch from a committed counter summary, or None when the kernel's
+    sources (for the apply also the host code that builds its tiles and work plan)
+    changed since the counters were taken."""
+    f = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(f):
         return None
     vals = {}
@@ -244,7 +251,7 @@ def measured_traffic():
         if ":" in line and line.split(":")[0].strip() in ("traffic_bytes_per_launch", "kernel_source_sha256_16"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != apply_sources_sha():
+    if vals.get("kernel_source_sha256_16") != sources_sha(sources):
         return None
     return int(vals["traffic_bytes_per_launch"])
 
@@ -381,6 +388,8 @@ def main():
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(b_pc / (ms_pc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms_pc > 0 else None,
                              "bytes_per_launch": int(b_pc), "max_levels": int(pci.max_levels),
+                             "traffic": (measured_traffic("k_schwarz_p_sphere_h0.02_counters.md", SCHWARZ_SOURCES)
+                                         if tune32["schwarz_variant"] == 2 else None),
                              "limited_by": "dependency levels and instruction issue: one workgroup per "
                                            "subdomain, so 64 of the 256 CUs work"},
     }
