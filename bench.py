@@ -366,7 +366,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "unit sphere h=0.02 on [-2,2]^3, p=3, c=1, f=21*Y4 (seed 2), "
                                f"{a.pc.upper()} 64 boxes overlap 2h, local {a.subsolver} ({a.ordering} order)",
-                   "n_active": nA, "n_ghost": nG, "n_band": band.n_band},
+                   "n_active": nA, "n_ghost": nG, "n_band": band.n_band,
+                   "cache": "resident: about 16 MB of HBM traffic per apply against a 256 MB last-level "
+                            "cache; apply_scaling gives HBM-cold tori with rotating buffers"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": apply_kernel, "bytes_per_node": round(b_alg, 2)},

@@ -5,6 +5,10 @@
   python -m paper_2110_06322_amd.profile_summary counter <results.db> <kernel-substring>
       per-dispatch value of the collected counter for matching kernels and for
       the device-to-device copy kernel used for calibration
+  python -m paper_2110_06322_amd.profile_summary bursts <results.db> <kernel-substring> [min_run]
+      launches of matching kernels that come in runs of at least min_run (default
+      50) back-to-back dispatches with no other kernel between them (the
+      bench's apply bursts), with their average duration
 """
 from __future__ import annotations
 
@@ -39,8 +43,34 @@ def counter(db, pattern):
               f"grid={grid} {name}")
 
 
+def bursts(db, pattern, min_run=50):
+    """Average duration of matching launches inside runs of >= min_run consecutive
+    matching dispatches (start-time order over all kernels)."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, duration from kernels order by start").fetchall()
+    runs, cur = [], []
+    for name, dur in rows:
+        if pattern in name:
+            cur.append(dur)
+        elif cur:
+            runs.append(cur)
+            cur = []
+    if cur:
+        runs.append(cur)
+    sel = [r for r in runs if len(r) >= min_run]
+    durs = [d for r in sel for d in r]
+    total = sum(len(r) for r in runs)
+    if not durs:
+        print(f"no runs of {min_run} or more launches of '{pattern}' ({total} launches in all)")
+        return
+    print(f"runs={len(sel)} launches={len(durs)} of {total} avg_us={sum(durs) / len(durs) / 1e3:.3f} "
+          f"median_us={statistics.median(durs) / 1e3:.3f} kernel~'{pattern}'")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2])
+    elif sys.argv[1] == "bursts":
+        bursts(sys.argv[2], sys.argv[3], int(sys.argv[4]) if len(sys.argv) > 4 else 50)
     else:
         counter(sys.argv[2], sys.argv[3])
