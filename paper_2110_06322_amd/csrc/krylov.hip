@@ -16,6 +16,8 @@
 namespace cpm {
 
 constexpr int kVecThreads = 256;
+// chunk count (of kChunkNodes nodes) from which the dot kernel groups basis vectors
+constexpr int kDotsGroupChunks = 4096;
 
 template <int R>
 __device__ __forceinline__ bool inst_active(const int32_t* act, int inst) {
@@ -52,30 +54,45 @@ __device__ __forceinline__ void block_sum(double* acc, double* red) {
   }
 }
 
-// part[(i*nchunks + c)*R + r] = <V_i, w> over chunk c
-template <int R>
+// part[(i*nchunks + c)*R + r] = <V_i, w> over chunk c, for the MB basis
+// vectors i = blockIdx.y*MB + b < m of this block. Every (i, c) sum is formed
+// in the same order whatever MB is (thread t adds nodes t, t + blockDim, ...,
+// then the fixed block reduction), so MB only trades blocks for reuse of w.
+template <int R, int MB>
 __global__ void __launch_bounds__(kVecThreads) k_dots(const double* __restrict__ V0, int64_t vstride,
                                                       const double* __restrict__ w, const Chunk* __restrict__ chunks,
-                                                      int nchunks, const int32_t* __restrict__ act,
+                                                      int nchunks, int m, const int32_t* __restrict__ act,
                                                       double* __restrict__ part) {
-  __shared__ double red[16 * R];
-  const int c = blockIdx.x, i = blockIdx.y;
+  __shared__ double red[16 * R * MB];
+  const int c = blockIdx.x, i0 = blockIdx.y * MB;
   const Chunk ch = chunks[c];
-  double acc[R];
+  double acc[MB * R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  for (int k = 0; k < MB * R; ++k) acc[k] = 0.0;
   if (inst_active<R>(act, ch.inst)) {
-    const double* v = V0 + (int64_t)i * vstride;
     for (int64_t n = threadIdx.x; n < ch.nodes; n += blockDim.x) {
       const int64_t e = (ch.node0 + n) * R;
+      double wv[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += v[e + r] * w[e + r];
+      for (int r = 0; r < R; ++r) wv[r] = w[e + r];
+#pragma unroll
+      for (int b = 0; b < MB; ++b) {
+        if (i0 + b < m) {
+          const double* v = V0 + (int64_t)(i0 + b) * vstride;
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[b * R + r] += v[e + r] * wv[r];
+        }
+      }
     }
   }
-  block_sum<R>(acc, red);
+  block_sum<MB * R>(acc, red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) part[((int64_t)i * nchunks + c) * R + r] = acc[r];
+    for (int b = 0; b < MB; ++b)
+      if (i0 + b < m) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) part[((int64_t)(i0 + b) * nchunks + c) * R + r] = acc[b * R + r];
+      }
   }
 }
 
@@ -342,8 +359,16 @@ __global__ void k_cycle_init(GmresState S, int ns) {
 hipError_t vec_dots(int R, const double* V0, int64_t vstride, int m, const double* w, const Chunk* chunks,
                     int nchunks, const int32_t* act, double* part, hipStream_t s) {
   if (nchunks == 0 || m == 0) return hipSuccess;
-  CPM_R_DISPATCH(R, hipLaunchKernelGGL((k_dots<RR>), dim3(nchunks, m), dim3(kVecThreads), 0, s, V0, vstride, w,
-                                       chunks, nchunks, act, part));
+  // Large packed vectors: one block per chunk and group of 8 basis vectors, so
+  // that w is read once per group and the launch holds 8x fewer blocks; small
+  // ones keep a block per (chunk, vector) to fill the chip.
+  if (nchunks >= kDotsGroupChunks) {
+    CPM_R_DISPATCH(R, hipLaunchKernelGGL((k_dots<RR, 8>), dim3(nchunks, (m + 7) / 8), dim3(kVecThreads), 0, s, V0,
+                                         vstride, w, chunks, nchunks, m, act, part));
+  } else {
+    CPM_R_DISPATCH(R, hipLaunchKernelGGL((k_dots<RR, 1>), dim3(nchunks, m), dim3(kVecThreads), 0, s, V0, vstride,
+                                         w, chunks, nchunks, m, act, part));
+  }
   return hipGetLastError();
 }
 
