@@ -66,10 +66,21 @@ __global__ void __launch_bounds__(kVecThreads) k_dots(const double* __restrict__
   __shared__ double red[16 * R * MB];
   const int c = blockIdx.x, i0 = blockIdx.y * MB;
   const Chunk ch = chunks[c];
+  if (!inst_active<R>(act, ch.inst)) {   // uniform over the block: a stopped instance's sums are 0
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int b = 0; b < MB; ++b)
+        if (i0 + b < m) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) part[((int64_t)(i0 + b) * nchunks + c) * R + r] = 0.0;
+        }
+    }
+    return;
+  }
   double acc[MB * R];
 #pragma unroll
   for (int k = 0; k < MB * R; ++k) acc[k] = 0.0;
-  if (inst_active<R>(act, ch.inst)) {
+  {
     for (int64_t n = threadIdx.x; n < ch.nodes; n += blockDim.x) {
       const int64_t e = (ch.node0 + n) * R;
       double wv[R];
@@ -130,6 +141,13 @@ __global__ void __launch_bounds__(kVecThreads) k_update(const double* __restrict
   __shared__ double hs[kMaxRestart * R];
   const int c = blockIdx.x;
   const Chunk ch = chunks[c];
+  if (!inst_active<R>(act, ch.inst)) {   // uniform over the block: nothing to update, norms 0
+    if (part_norm && threadIdx.x == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) part_norm[(int64_t)c * R + r] = 0.0;
+    }
+    return;
+  }
   bool on[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) on[r] = act[ch.inst * R + r] != 0;
