@@ -194,7 +194,7 @@ def apply_scaling(cpm, inputs, torch, dev, hs=(0.005, 0.0025), reps=40, copies=4
 def cpu_baseline(seconds_budget=20.0):
     """The CPU oracle's assembled operator applied to a vector, on the same workload, FP64.
 
-    Sample: the oracle assembles A for the full config-2 band (not timed) and
+    Sample: the oracle assembles A for the full unit-sphere h = 0.02 band (not timed) and
     times repeated SciPy CSR matvecs for about the budget; reported as active
     nodes per second. SciPy's sparse matvec runs on one core.
     """
