@@ -135,7 +135,7 @@ cpm_status cpm_apply_T(const cpm_operator* op, const double* x, double* y, int32
 /* ---------------------------------------------------------------------
  * Restricted (RAS) and optimized restricted (ORAS) additive Schwarz
  * preconditioners (Sec. 2.2, eq. ddIter and the restricted recombination;
- * Sec. 4.1.1: alpha = 4, alpha_cross = 20, "one level incomplete LU").
+ * Sec. 4.1.1: alpha = 4, alpha_cross = 20, ILU(0) local solves by default).
  *   partition : recursive coordinate bisection of Sigma_A by closest point
  *               (axis of largest extent, split value = floor(n/2)-th smallest
  *               coordinate, cp < split goes first); n_parts a power of two;

@@ -20,6 +20,8 @@ Modules
 Pins (what fixes each part independently of itself) live in tests/test_oracle_*.py.
 Parity unpinned: none of the paper's printed numbers (Tables 1-3) can be
 reproduced here (torus radii, input files, ParMETIS partitions, hardware are
-unavailable); the ORAS Robin lumping is a stated reading, pinned only by its
-alpha -> infinity limit (RAS) and by leaving the solution unchanged.
+unavailable). The ORAS Robin lumping is a stated reading (no passage gives
+its discrete form); the pins check that reading on a hand-worked case, by
+the Robin substitution row by row, by its alpha -> infinity limit (RAS) and
+by leaving the solution unchanged.
 """

@@ -3,11 +3,12 @@
 Definitions followed (the paper gives the properties, this module the sets):
   * grid nodes x_i = lo + i h, i in {0..n-1}^d;
   * B_gamma  = nodes with |x - cp(x)| <= gamma (1 + 1e-10) (inclusive radius);
-  * Sigma_A  = union over x in B_gamma of the (p+1)^d interpolation cube of cp(x):
-               "Sigma_A contains the union of all (p+1)^d cubes of grid points
-               needed to perform this extension" (Sec. 2.1);
+  * Sigma_A  = union over x in B_gamma of the (p+1)^d interpolation cube of cp(x)
+               (Sec. 2.1: the active set must hold every cube the extension
+               reads);
   * Sigma_G  = grid neighbours (+-e_k) of Sigma_A that are not in Sigma_A
-               ("the points neighboring the members of Sigma_A", Sec. 2.1);
+               (Sec. 2.1: the ghost set completes the finite-difference
+               stencils of the active nodes);
   * closure  = every node of Sigma_A u Sigma_G has its cube inside Sigma_A
                (the extension is evaluated at all of them); a closure loop
                adds missing cube nodes, at most once, else raises.

@@ -1,5 +1,5 @@
 """Restarted, right-preconditioned flexible GMRES (the paper's default Krylov method,
-Sec. 4.1.1: "GMRES is the default choice").
+Sec. 4.1.1 names GMRES as the default solver).
 
 Textbook form (Saad, "Iterative Methods for Sparse Linear Systems", 2nd ed.,
 Alg. 9.6 FGMRES): modified Gram-Schmidt Arnoldi on z_j = M^-1 v_j, Givens

@@ -5,8 +5,8 @@ grow them into overlapping pieces, solve local problems with Dirichlet
 (T = identity, RAS) or Robin (T = d/dq + alpha, ORAS) transmission
 conditions, and recombine each local solution only on its own disjoint piece
 (eq. ddIter and the restricted sum after it). As a preconditioner (Sec. 4.1.1)
-the local problems are solved by "one level incomplete LU", read here as
-ILU(0) on the structural pattern.
+the local problems are solved by an incomplete LU factorization with one
+level, read here as ILU(0) (no fill) on the structural pattern.
 
 Readings (the paper fixes none of these discretely):
   * partition: recursive coordinate bisection of the active nodes by their

@@ -226,3 +226,95 @@ def test_distance_order_cases_and_short_chains():
     pd = schwarz.distance_order(dist[idx])
     assert np.all(np.diff(dist[idx][pd]) <= 0)
     assert 3 * chain(pd) < chain(schwarz.rcm_order(Aj))
+
+
+def _toy_9pt_grid():
+    """4 x 4 grid of points (x, y), keys 4x + y, a 9-point stencil matrix with
+    diagonal 10, edge couplings -1 and corner couplings -0.5."""
+    pts = np.array([(x, y) for x in range(4) for y in range(4)], dtype=np.float64)
+    n = len(pts)
+    A = np.zeros((n, n))
+    for i, (x, y) in enumerate(pts):
+        A[i, i] = 10.0
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                if (dx, dy) == (0, 0) or not (0 <= x + dx < 4 and 0 <= y + dy < 4):
+                    continue
+                k = int((x + dx) * 4 + (y + dy))
+                A[i, k] = -1.0 if dx == 0 or dy == 0 else -0.5
+    return pts, sp.csr_matrix(A)
+
+
+def test_oras_robin_alpha_selection_hand_worked():
+    """ORAS Robin lumping on a case worked out by hand (reading of eq. transRob).
+
+    RCB of the 4 x 4 points into 4 parts cuts x at 2, then y at 2: owners are the
+    quadrants {x<2,y<2}, {x<2,y>=2}, {x>=2,y<2}, {x>=2,y>=2}. With overlap 0 the
+    closed boxes give Omega_0 = {x<=2, y<=2} and Omega_3 = {x>=2, y>=2}. Dropped
+    couplings and their owners, h = 0.5 (1/(1 + 4h) = 1/3, 1/(1 + 20h) = 1/11):
+      Omega_0 row (0,2): (0,3) edge, (1,3) corner -> owner {1}        -> 10 - 1.5/3
+      Omega_0 row (1,2): (0,3), (2,3) corners, (1,3) edge -> {1, 3}   -> 10 - 2/11
+      Omega_0 row (2,2): (1,3),(3,3),(3,1) corners, (2,3),(3,2) edges
+                         -> owners {1, 2, 3}                          -> 10 - 3.5/11
+      Omega_0 row (2,0): (3,0) edge, (3,1) corner -> {2}              -> 10 - 1.5/3
+      Omega_0 row (2,1): (3,0),(3,2) corners, (3,1) edge -> {2, 3}    -> 10 - 2/11
+      Omega_3 row (2,2): (1,1),(1,3),(3,1) corners, (1,2),(2,1) edges
+                         -> {0, 1, 2}                                 -> 10 - 3.5/11
+      Omega_3 rows (2,3), (3,2): one edge + one corner, one owner     -> 10 - 1.5/3
+    Swapping alpha and alpha_cross, counting one owner as a cross point, or
+    dropping h from 1 + alpha h each change at least one of these values.
+    """
+    pts, A = _toy_9pt_grid()
+    keys = (pts[:, 0] * 4 + pts[:, 1]).astype(np.int64)
+    S = schwarz.build_schwarz(A, A, pts, keys, 0.5, 4, 0.0, kind="oras", alpha=4.0, alpha_cross=20.0,
+                              subsolver="lu")
+    quad = (pts[:, 0] >= 2).astype(int) * 2 + (pts[:, 1] >= 2).astype(int)
+    assert np.array_equal(S.owner, quad)
+    want0 = {(0, 0): 10.0, (0, 1): 10.0, (0, 2): 10.0 - 1.5 / 3, (1, 0): 10.0, (1, 1): 10.0,
+             (1, 2): 10.0 - 2.0 / 11, (2, 0): 10.0 - 1.5 / 3, (2, 1): 10.0 - 2.0 / 11, (2, 2): 10.0 - 3.5 / 11}
+    want3 = {(2, 2): 10.0 - 3.5 / 11, (2, 3): 10.0 - 1.5 / 3, (3, 2): 10.0 - 1.5 / 3, (3, 3): 10.0}
+    for j, want in ((0, want0), (3, want3)):
+        idx = S.omegas[j]
+        got = {tuple(int(v) for v in pts[i]): S.local[j].diagonal()[li] for li, i in enumerate(idx)}
+        assert set(got) == set(want)
+        for q, v in want.items():
+            assert abs(got[q] - v) <= 1e-15 * 10, (j, q, got[q], v)
+        # off-diagonal entries of the local matrix are A's own
+        Ad = A.toarray()[np.ix_(idx, idx)]
+        Ld = S.local[j].toarray()
+        off = ~np.eye(idx.size, dtype=bool)
+        assert np.array_equal(Ld[off], Ad[off])
+
+
+def test_oras_local_rows_follow_robin_substitution_sphere():
+    """On a CPM band (sphere h = 0.2, p = 3, 8 parts, overlap 2h) every local ORAS row
+    equals A's row applied to the local vector extended outside Omega_j by the
+    discrete Robin relation u_k = u_i / (1 + alpha_i h), alpha_i chosen by the
+    number of distinct owners of the row's dropped columns (found here from the
+    dense matrix by set operations)."""
+    bd, E, Om, A, P = C.matrices("sphere", (1.0,), 3, 0.2, 3, 1.0)
+    h, al, alx = 0.2, 4.0, 20.0
+    S = schwarz.build_schwarz(A, P, bd.cp_active, bd.active_keys, h, 8, 2.0, kind="oras", alpha=al,
+                              alpha_cross=alx, subsolver="lu")
+    Ad = A.toarray()
+    Pd = P.toarray() != 0
+    rng = np.random.default_rng(11)
+    n_cross = n_single = 0
+    for j, idx in enumerate(S.omegas):
+        inside = set(int(i) for i in idx)
+        uloc = rng.standard_normal(idx.size)
+        got = S.local[j] @ uloc
+        for li, i in enumerate(idx):
+            dropped = [k for k in np.nonzero(Pd[i])[0] if int(k) not in inside]
+            owners = {int(S.owner[k]) for k in dropped}
+            assert j not in owners
+            a = alx if len(owners) >= 2 else al
+            w = np.zeros(A.shape[0])
+            w[idx] = uloc
+            for k in dropped:
+                w[k] = uloc[li] / (1.0 + a * h)
+            want = Ad[i] @ w
+            assert abs(got[li] - want) <= 1e-12 * (np.abs(Ad[i]) @ np.abs(w) + 1e-300)
+            n_cross += len(owners) >= 2
+            n_single += len(owners) == 1
+    assert n_cross > 0 and n_single > 0
