@@ -132,6 +132,18 @@ cpm_status cpm_extend_apply(const cpm_operator* op, const double* u, double* v, 
 cpm_status cpm_apply(const cpm_operator* op, const double* x, double* y, int32_t nrhs, void* stream);
 cpm_status cpm_apply_T(const cpm_operator* op, const double* x, double* y, int32_t nrhs, void* stream);
 
+/* dL/dc for u = A(c)^-1 f (Sec. 2.1, eq. lapBel: A(c) = c I + K with K
+ * independent of c): with lambda the adjoint solution of A^T lambda = dL/du,
+ * grad[0] = -sum_i lambda_i u_i over all N_A * nrhs entries (for nrhs > 1 the
+ * right-hand sides share c, so their contributions add).
+ * lambda, u: device [N_A * nrhs]; grad: device, one double (written
+ * asynchronously on the stream). The sum is reduced in a fixed order, so
+ * repeated calls give identical bits. Uses an operator-owned buffer of chunk
+ * sums (allocated on first use): calls on one operator must not overlap.
+ * nrhs in {1, 2, 4}. */
+cpm_status cpm_shift_gradient(const cpm_operator* op, const double* lambda, const double* u, int32_t nrhs,
+                              double* grad, void* stream);
+
 /* ---------------------------------------------------------------------
  * Restricted (RAS) and optimized restricted (ORAS) additive Schwarz
  * preconditioners (Sec. 2.2, eq. ddIter and the restricted recombination;

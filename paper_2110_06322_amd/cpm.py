@@ -31,10 +31,46 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def _dptr(t):
-    if not t.is_cuda or t.dtype != _torch().float64 or not t.is_contiguous():
-        raise ValueError("expected a contiguous float64 CUDA tensor")
-    return C.c_void_p(t.data_ptr())
+def check_vec(t, n: int, what: str = "vector", on_device: bool = False):
+    """Validate a vector before its address goes to the library: a torch tensor,
+    float64, contiguous, exactly n elements and (on_device, checked when the
+    address is taken, after every argument's size) on a CUDA (HIP) device.
+    Raises TypeError / ValueError; nothing is passed on when a check fails."""
+    torch = _torch()
+    if not torch.is_tensor(t):
+        raise TypeError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{what}: expected float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{what}: expected {n} elements, got {t.numel()}")
+    if on_device and not t.is_cuda:
+        raise ValueError(f"{what}: must be a CUDA (HIP) device tensor")
+    return t
+
+
+def check_nrhs(nrhs: int):
+    if nrhs not in (1, 2, 4):
+        raise ValueError(f"nrhs must be 1, 2 or 4, got {nrhs}")
+    return int(nrhs)
+
+
+def check_disjoint(a, b, what: str):
+    """The library's outputs must not overlap its inputs."""
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    if a.numel() and b.numel() and a0 < b0 + b.numel() * b.element_size() and b0 < a0 + a.numel() * a.element_size():
+        raise ValueError(f"{what} must not overlap")
+
+
+def check_count(seq, n: int, what: str):
+    if len(seq) != n:
+        raise ValueError(f"{what}: expected {n} entries (one per instance), got {len(seq)}")
+    return list(seq)
+
+
+def _dptr(t, n: int, what: str = "vector"):
+    return C.c_void_p(check_vec(t, n, what, on_device=True).data_ptr())
 
 
 def device_count() -> int:
@@ -116,26 +152,45 @@ class Operator:
     def set_shift(self, c: float):
         check(lib().cpm_operator_set_shift(self._h, float(c)))
 
-    def _out(self, x, nrhs, out):
+    def _io(self, x, out, nrhs):
         torch = _torch()
-        return torch.empty_like(x) if out is None else out
+        n = self.n_active * check_nrhs(nrhs)
+        check_vec(x, n, "x")
+        y = torch.empty_like(x) if out is None else check_vec(out, n, "out")
+        check_disjoint(x, y, "x and out")
+        return x, y, n
 
     def apply(self, x, out=None, nrhs: int = 1, stream=None):
-        y = self._out(x, nrhs, out)
-        check(lib().cpm_apply(self._h, _dptr(x), _dptr(y), nrhs, _stream(stream)))
+        x, y, n = self._io(x, out, nrhs)
+        check(lib().cpm_apply(self._h, _dptr(x, n), _dptr(y, n), nrhs, _stream(stream)))
         return y
 
     def apply_T(self, x, out=None, nrhs: int = 1, stream=None):
-        y = self._out(x, nrhs, out)
-        check(lib().cpm_apply_T(self._h, _dptr(x), _dptr(y), nrhs, _stream(stream)))
+        x, y, n = self._io(x, out, nrhs)
+        check(lib().cpm_apply_T(self._h, _dptr(x, n), _dptr(y, n), nrhs, _stream(stream)))
         return y
 
     def extend(self, u, out=None, stream=None):
         torch = _torch()
         n = self.band.n_active + self.band.n_ghost
-        v = torch.empty(n, dtype=torch.float64, device=u.device) if out is None else out
-        check(lib().cpm_extend_apply(self._h, _dptr(u), _dptr(v), _stream(stream)))
+        check_vec(u, self.n_active, "u")
+        v = torch.empty(n, dtype=torch.float64, device=u.device) if out is None else check_vec(out, n, "out")
+        check_disjoint(u, v, "u and out")
+        check(lib().cpm_extend_apply(self._h, _dptr(u, self.n_active), _dptr(v, n), _stream(stream)))
         return v
+
+    def shift_gradient(self, lam, u, nrhs: int = 1, out=None, stream=None):
+        """dL/dc = -lambda . u as a one-element device tensor (reduced by the library in a
+        fixed order), for u = A(c)^-1 f and the adjoint solution lambda."""
+        torch = _torch()
+        n = self.n_active * check_nrhs(nrhs)
+        check_vec(lam, n, "lambda")
+        check_vec(u, n, "u")
+        g = torch.empty(1, dtype=torch.float64, device=u.device) if out is None else check_vec(out, 1, "out")
+        check_disjoint(lam, g, "lambda and out")
+        check_disjoint(u, g, "u and out")
+        check(lib().cpm_shift_gradient(self._h, _dptr(lam, n), _dptr(u, n), nrhs, _dptr(g, 1), _stream(stream)))
+        return g
 
     def __del__(self):
         try:
@@ -197,8 +252,11 @@ class Precond:
 
     def apply(self, r, out=None, nrhs: int = 1, stream=None):
         torch = _torch()
-        z = torch.empty_like(r) if out is None else out
-        check(lib().cpm_precond_apply(self._h, _dptr(r), _dptr(z), nrhs, _stream(stream)))
+        n = self.op.n_active * check_nrhs(nrhs)
+        check_vec(r, n, "r")
+        z = torch.empty_like(r) if out is None else check_vec(out, n, "out")
+        check_disjoint(r, z, "r and out")
+        check(lib().cpm_precond_apply(self._h, _dptr(r, n), _dptr(z, n), nrhs, _stream(stream)))
         return z
 
     def __del__(self):
@@ -257,10 +315,15 @@ def solve(op: Operator, f, pc: Precond | None = None, u=None, nrhs: int = 1, opt
     """Solve A u = f (or A^T u = f) with restarted FGMRES on the GPU; returns (u, stats)."""
     torch = _torch()
     opts = opts or SolveOptions(**kw)
-    u = torch.zeros_like(f) if u is None else u
+    n = op.n_active * check_nrhs(nrhs)
+    check_vec(f, n, "f")
+    u = torch.zeros_like(f) if u is None else check_vec(u, n, "u")
+    check_disjoint(f, u, "f and u")
+    if pc is not None and pc.op is not op:
+        raise ValueError("the preconditioner was built for another operator")
     st = _capi.SolveStats()
     co = opts.to_c()
-    code = lib().cpm_solve(op._h, pc._h if pc is not None else None, _dptr(f), _dptr(u), nrhs,
+    code = lib().cpm_solve(op._h, pc._h if pc is not None else None, _dptr(f, n), _dptr(u, n), nrhs,
                            C.byref(co), C.byref(st), _stream(stream))
     if code not in (_capi.CPM_OK, 6) or (raise_on_fail and code != _capi.CPM_OK):
         check(code)
@@ -272,10 +335,14 @@ class Batch:
 
     def __init__(self, ops, pcs=None, nrhs=None):
         n = len(ops)
-        pcs = pcs or [None] * n
-        nrhs = nrhs or [1] * n
+        pcs = check_count(pcs or [None] * n, n, "pcs")
+        nrhs = [check_nrhs(r) for r in check_count(nrhs or [1] * n, n, "nrhs")]
+        for o, p in zip(ops, pcs):
+            if p is not None and p.op is not o:
+                raise ValueError("a preconditioner was built for another operator")
         self._ops, self._pcs = list(ops), list(pcs)
         self.nrhs = list(nrhs)
+        self.sizes = [o.n_active * r for o, r in zip(self._ops, self.nrhs)]
         oa = (C.c_void_p * n)(*[o._h.value for o in ops])
         pa = (C.c_void_p * n)(*[(p._h.value if p is not None else None) for p in pcs])
         ra = (C.c_int32 * n)(*nrhs)
@@ -286,10 +353,15 @@ class Batch:
     def solve(self, fs, us=None, opts: SolveOptions | None = None, stream=None, **kw):
         torch = _torch()
         opts = opts or SolveOptions(**kw)
-        us = us or [torch.zeros_like(f) for f in fs]
-        n = len(fs)
-        fa = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
-        ua = (C.c_void_p * n)(*[u.data_ptr() for u in us])
+        n = len(self._ops)
+        fs = check_count(fs, n, "fs")
+        us = [torch.zeros_like(f) for f in fs] if us is None else check_count(us, n, "us")
+        for i, (f, u, m) in enumerate(zip(fs, us, self.sizes)):
+            check_vec(f, m, f"fs[{i}]")
+            check_vec(u, m, f"us[{i}]")
+            check_disjoint(f, u, f"fs[{i}] and us[{i}]")
+        fa = (C.c_void_p * n)(*[_dptr(f, m).value for f, m in zip(fs, self.sizes)])
+        ua = (C.c_void_p * n)(*[_dptr(u, m).value for u, m in zip(us, self.sizes)])
         nsys = sum(self.nrhs)
         st = (_capi.SolveStats * nsys)()
         co = opts.to_c()
@@ -307,10 +379,15 @@ class Batch:
 
     def apply(self, xs, ys=None, stream=None):
         torch = _torch()
-        ys = ys or [torch.empty_like(x) for x in xs]
-        n = len(xs)
-        xa = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
-        ya = (C.c_void_p * n)(*[y.data_ptr() for y in ys])
+        n = len(self._ops)
+        xs = check_count(xs, n, "xs")
+        ys = [torch.empty_like(x) for x in xs] if ys is None else check_count(ys, n, "ys")
+        for i, (x, y, m) in enumerate(zip(xs, ys, self.sizes)):
+            check_vec(x, m, f"xs[{i}]")
+            check_vec(y, m, f"ys[{i}]")
+            check_disjoint(x, y, f"xs[{i}] and ys[{i}]")
+        xa = (C.c_void_p * n)(*[_dptr(x, m).value for x, m in zip(xs, self.sizes)])
+        ya = (C.c_void_p * n)(*[_dptr(y, m).value for y, m in zip(ys, self.sizes)])
         check(lib().cpm_batch_apply(self._h, xa, ya, _stream(stream)))
         return ys
 
@@ -328,23 +405,27 @@ class CPMSolve(torch.autograd.Function):
     A(c) = c I + K with K independent of c, so for a loss L(u) with
     g = dL/du: A^T lambda = g, dL/df = lambda, dL/dc = -lambda . u.
     Forward and backward both run GPU FGMRES; the backward solve uses A^T and
-    a preconditioner built on A^T when one is given. Call as
+    a preconditioner built on A^T when one is given, and dL/dc comes from the
+    library's fixed-order reduction (cpm_shift_gradient). Call as
     CPMSolve.apply(f, c, op, pc, pc_T, opts, adjoint_rtol) with c a 0-d tensor;
     adjoint_rtol (default opts.rtol) sets the A^T solve's tolerance, since the
     attainable residual of either solve is about eps |A| |u| / |f|.
+    The operator's shift is set to c for each solve and restored afterwards;
+    pc and pc_T keep the factors they were built with (built at another shift
+    they are preconditioners of a nearby operator: the solution is unchanged,
+    the iteration count may grow).
     """
 
     @staticmethod
     def forward(ctx, f, c, op, pc=None, pc_T=None, opts=None, adjoint_rtol=None):
         opts = opts or SolveOptions(rtol=1e-12)
         cval = float(c)
-        if op.c != cval:
-            op.set_shift(cval)
-        u, st = solve(op, f.detach().contiguous(), pc=pc, opts=opts)
+        with _shift(op, cval):
+            u, st = solve(op, f.detach().contiguous(), pc=pc, opts=opts)
         if not st["converged"]:
             raise RuntimeError(f"forward solve did not converge: {st}")
         ctx.save_for_backward(u)
-        ctx.op, ctx.pc_T, ctx.opts = op, pc_T, opts
+        ctx.op, ctx.pc_T, ctx.opts, ctx.c = op, pc_T, opts, cval
         ctx.adjoint_rtol = opts.rtol if adjoint_rtol is None else float(adjoint_rtol)
         ctx.c_meta = (c.device, c.dtype) if torch.is_tensor(c) else (u.device, u.dtype)
         return u
@@ -355,8 +436,27 @@ class CPMSolve(torch.autograd.Function):
         o = ctx.opts
         ot = SolveOptions(restart=o.restart, rtol=ctx.adjoint_rtol, atol=o.atol, max_it=o.max_it, mode="fp64",
                           transpose=True, stagnation_cycles=o.stagnation_cycles)
-        lam, st = solve(ctx.op, g.contiguous(), pc=ctx.pc_T, opts=ot)
+        with _shift(ctx.op, ctx.c):
+            lam, st = solve(ctx.op, g.contiguous(), pc=ctx.pc_T, opts=ot)
         if not st["converged"]:
             raise RuntimeError(f"adjoint solve did not converge: {st}")
-        gc = -torch.dot(lam, u)
+        gc = ctx.op.shift_gradient(lam, u)
         return lam, gc.reshape(()).to(device=ctx.c_meta[0], dtype=ctx.c_meta[1]), None, None, None, None, None
+
+
+class _shift:
+    """Sets an operator's shift for the duration of a block, then restores it."""
+
+    def __init__(self, op: Operator, c: float):
+        self.op, self.c = op, float(c)
+
+    def __enter__(self):
+        self.old = self.op.c
+        if self.old != self.c:
+            self.op.set_shift(self.c)
+        return self.op
+
+    def __exit__(self, *exc):
+        if self.op.c != self.old:
+            self.op.set_shift(self.old)
+        return False

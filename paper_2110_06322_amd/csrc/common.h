@@ -115,5 +115,6 @@ struct cpm_operator_s {
   mutable std::shared_ptr<cpm_batch_s> solve_cache;
   mutable int64_t solve_cache_key = -1;
   mutable cpm::DevBuf<double> d_z;          // transpose scratch [(nA+nG) * 4]
+  mutable cpm::DevBuf<double> d_part;       // chunk sums of cpm_shift_gradient
   int64_t nA() const { return band->nA; }
 };

@@ -43,10 +43,11 @@ def test_adjoint_matches_oracle_direct_small():
     lb = G.lib_band(kind, params, 2, h, 3)
     ob, E, O, A, P = G.oracle(kind, params, 2, h, 3, 1.5)
     keys, pos = G.mapping(lb, ob)
-    op = cpm.Operator(lb, 1.5)
+    op = cpm.Operator(lb, 2.0)   # CPMSolve runs at c = 1.5 and restores the operator's shift
     f = torch.tensor(G.field(keys, 1), dtype=torch.float64, device=DEV)
     ut = torch.tensor(G.field(keys, 2), dtype=torch.float64, device=DEV)
     L, gf, gc = _loss(op, f, 1.5, ut, None, None)
+    assert op.c == 2.0
     Lo, uo, gfo, gco = adjoint.quadratic_loss_grads(A, G.field(ob.active_keys, 1), G.field(ob.active_keys, 2))
     assert abs(L - Lo) <= 1e-9 * Lo
     assert np.abs(gf.cpu().numpy() - gfo[pos]).max() <= 1e-9 * np.abs(gfo).max()
@@ -95,3 +96,31 @@ def test_adjoint_torus_h001_finite_differences():
     op.set_shift(1.0)
     print(f"dL/dc fd {fd:.12e} adjoint {gc:.12e}", flush=True)
     assert abs(fd - gc) <= 1e-6 * abs(gc), (fd, gc)
+
+
+@pytest.mark.parametrize("case", [("circle", (1.0,), 2, 0.05, 3), ("torus", (1.0, 0.4), 3, 0.05, 3)])
+def test_shift_gradient_capi_matches_oracle(case):
+    """dL/dc through the C ABI (cpm_shift_gradient) against the oracle's direct adjoint
+    -lambda . u; several reduction chunks and a ragged tail on the torus; two right-hand
+    sides add; repeated calls give the same bits."""
+    kind, params, d, h, p = case
+    c = 1.5
+    lb = G.lib_band(kind, params, d, h, p)
+    ob, E, O, A, P = G.oracle(kind, params, d, h, p, c)
+    keys, pos = G.mapping(lb, ob)
+    op = cpm.Operator(lb, c)
+    Lo, uo, lamo, gco = adjoint.quadratic_loss_grads(A, G.field(ob.active_keys, 1), G.field(ob.active_keys, 2))
+    u = torch.tensor(uo[pos], dtype=torch.float64, device=DEV)
+    lam = torch.tensor(lamo[pos], dtype=torch.float64, device=DEV)
+    g1 = op.shift_gradient(lam, u)
+    g2 = op.shift_gradient(lam, u)
+    torch.cuda.synchronize()
+    scale = float(np.abs(lamo) @ np.abs(uo))
+    print(f"{kind} N_A={lb.n_active} dL/dc {float(g1):.15e} oracle {gco:.15e}", flush=True)
+    assert abs(float(g1) - gco) <= 64 * G.EPS * scale
+    assert torch.equal(g1, g2)
+    # two interleaved right-hand sides: (lambda, u) and (2 lambda, u / 4) -> 1.5 times the single value
+    lam2 = torch.stack([lam, 2.0 * lam], dim=1).reshape(-1).contiguous()
+    u2 = torch.stack([u, 0.25 * u], dim=1).reshape(-1).contiguous()
+    g3 = op.shift_gradient(lam2, u2, nrhs=2)
+    assert abs(float(g3) - 1.5 * gco) <= 128 * G.EPS * scale
