@@ -15,7 +15,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-from .band import Band, cube_offsets, keys_of, stencil_base, _wrap
+from .band import Band, coords, cube_offsets, ijk_of, keys_of, stencil_base, _wrap
 
 
 def bary_weights_1d(t: np.ndarray, p: int) -> np.ndarray:
@@ -136,3 +136,64 @@ def values_on_pattern(A: sp.csr_matrix, P: sp.csr_matrix) -> sp.csr_matrix:
     if hit.sum() != A.nnz:
         raise RuntimeError("A has entries outside the structural pattern")
     return sp.csr_matrix((vals, P.indices.copy(), P.indptr.copy()), shape=P.shape)
+
+
+def apply_rows(cpfun, d: int, p: int, h: float, lo, shape, c: float, row_keys, u_keys, u_vals,
+               chunk: int = 20000, magnitude: bool = False) -> np.ndarray:
+    """(A u)_i = (c + 2d/h^2) u_i - h^-2 sum_{n in N(i)} (E u)_n for the grid nodes with
+    keys row_keys, straight from the definitions (eq. lapBel) without assembling A:
+    each neighbour's closest point cp(x_n) is evaluated by `cpfun`, its cube and
+    barycentric weights come from extension_rows, and u is read at the cube nodes.
+
+    u is given as values u_vals [(N, R) or (N,)] at the sorted grid keys u_keys (the
+    active nodes); a cube node missing from u_keys raises (the band was not closed).
+    Rows are processed `chunk` at a time. Returns an array shaped like u_vals[row].
+    magnitude=True returns instead the sum of the magnitudes of the terms,
+    (c + 2d/h^2)|u_i| + h^-2 sum_n sum_alpha |w_alpha| |u|, the forward-error
+    scale of row i for any summation order.
+    """
+    row_keys = np.asarray(row_keys, dtype=np.int64)
+    u_keys = np.asarray(u_keys, dtype=np.int64)
+    uv = np.asarray(u_vals, dtype=np.float64)
+    if magnitude:
+        uv = np.abs(uv)
+    one = uv.ndim == 1
+    uv = uv.reshape(uv.shape[0], -1)
+    if np.any(np.diff(u_keys) <= 0):
+        raise ValueError("u_keys must be strictly increasing")
+    lo = np.asarray(lo, dtype=np.float64)
+    offs = cube_offsets(d, p)
+    h2 = h * h
+    ntot = int(np.prod(np.asarray(shape, dtype=np.int64)))
+    if ntot <= 100_000_000:   # dense key -> position map
+        where = np.full(ntot, -1, dtype=np.int64)
+        where[u_keys] = np.arange(u_keys.size)
+
+        def find(keys):
+            pos = where[keys]
+            if (pos < 0).any():
+                raise RuntimeError("node missing from the band (closure violated)")
+            return pos
+    else:
+        def find(keys):
+            return _lookup(u_keys, keys)
+
+    out = np.empty((row_keys.size, uv.shape[1]))
+    for s in range(0, row_keys.size, chunk):
+        rk = row_keys[s:s + chunk]
+        ijk = ijk_of(rk, shape)
+        acc = np.zeros((rk.size, uv.shape[1]))
+        for k in range(d):
+            for sg in (-1, 1):
+                nb = ijk.copy()
+                nb[:, k] += sg
+                b, W = extension_rows(cpfun(coords(nb, lo, h)), lo, h, p)
+                if magnitude:
+                    W = np.abs(W)
+                pts = (b[:, None, :] + offs[None, :, :]).reshape(-1, d)
+                if (pts < 0).any() or (pts >= np.asarray(shape)[None, :]).any():
+                    raise RuntimeError("interpolation cube leaves the grid")
+                vals = uv[find(keys_of(pts, shape))].reshape(rk.size, offs.shape[0], uv.shape[1])
+                acc += np.einsum("nq,nqr->nr", W, vals)
+        out[s:s + rk.size] = (c + 2.0 * d / h2) * uv[find(rk)] + (acc if magnitude else -acc) / h2
+    return out[:, 0] if one else out

@@ -169,3 +169,32 @@ def test_quartic_harmonics_are_harmonic_and_homogeneous():
     L = (4 * lap(f, x, 0.05) - lap(f, x, 0.1)) / 3
     assert np.abs(L).max() < 1e-8
     assert np.abs(f(2.0 * x) - 16.0 * f(x)).max() < 1e-12
+
+
+@pytest.mark.parametrize("kind,params,d,h,p", [("circle", (1.0,), 2, 0.05, 2), ("sphere", (1.0,), 3, 0.2, 3),
+                                               ("torus", (1.0, 0.4), 3, 0.1, 2),
+                                               ("ellipsoid", (1.2, 1.0, 0.9), 3, 0.1, 2)])
+def test_matrix_free_rows_equal_assembled_A(kind, params, d, h, p):
+    """The oracle's matrix-free row apply (closest points of the neighbours evaluated on
+    the fly, no band) equals the assembled A, which the pins above fix, on every row and
+    for two right-hand sides at once; applied to 1 it returns c (A 1 = c 1); in magnitude
+    mode it is the sum of |terms|, (c + 2d/h^2)|u| + h^-2 O |E| |u|."""
+    c = 2.3
+    bd, E, Om, A, P = C.matrices(kind, params, d, h, p, c)
+    keys = bd.active_keys
+    cpf = surfaces.make_cp(kind, params)
+    U = np.stack([inputs.normal(8, r, keys) for r in range(2)], axis=1)
+    AU = O.apply_rows(cpf, d, p, h, bd.lo, bd.shape, c, keys, keys, U, chunk=97)
+    ref = A @ U
+    scale = np.abs(ref).max()
+    assert np.abs(AU - ref).max() <= 1e-13 * scale
+    one = O.apply_rows(cpf, d, p, h, bd.lo, bd.shape, c, keys, keys, np.ones(keys.size))
+    assert np.abs(one - c).max() <= 1e-12 * (c + 2 * d / h ** 2)
+    S = O.apply_rows(cpf, d, p, h, bd.lo, bd.shape, c, keys, keys, U[:, 0], magnitude=True)
+    Sref = (c + 2 * d / h ** 2) * np.abs(U[:, 0]) + (Om @ (abs(E) @ np.abs(U[:, 0]))) / h ** 2
+    assert np.abs(S - Sref).max() <= 1e-13 * Sref.max()
+    assert (S >= np.abs(ref[:, 0]) * (1 - 1e-12)).all()
+    # a subset of rows in any order
+    sel = np.random.default_rng(3).choice(keys.size, 50, replace=False)
+    sub = O.apply_rows(cpf, d, p, h, bd.lo, bd.shape, c, keys[sel], keys, U[:, 1])
+    assert np.abs(sub - ref[sel, 1]).max() <= 1e-13 * scale
