@@ -20,12 +20,23 @@ from ._capi import check, lib
 class GrayScott:
     def __init__(self, band: cpm.Band, mu=(2e-5, 1e-5), F=0.04, k=0.06, dt=1.0, n_parts=1024,
                  kind="oras", precision="fp32", mode="mixed", rtol=1e-8, seed=5, device="cuda", tune=False,
-                 tune_cache=None, ordering="rcm"):
+                 tune_cache=None, ordering="rcm", ops=None, pcs=None):
+        """ops / pcs: existing operators (shifts 1/(mu_w dt)) and preconditioners to share, e.g.
+        to run the same system with factors of another precision; otherwise they are built
+        here (n_parts = 0: no preconditioner)."""
         self.band, self.mu, self.F, self.k, self.dt = band, tuple(mu), F, k, dt
         self.rtol, self.mode = rtol, mode
-        self.ops = [cpm.Operator(band, 1.0 / (m * dt)) for m in self.mu]
-        self.pcs = [cpm.Precond(op, kind=kind, n_parts=n_parts, overlap=2.0, precision=precision, ordering=ordering)
-                    for op in self.ops] if n_parts > 0 else [None, None]
+        self.ops = list(ops) if ops is not None else [cpm.Operator(band, 1.0 / (m * dt)) for m in self.mu]
+        for op, m in zip(self.ops, self.mu):
+            if abs(op.c - 1.0 / (m * dt)) > 1e-12 * op.c:
+                raise ValueError("operator shift does not match 1/(mu dt)")
+        if pcs is not None:
+            self.pcs = list(pcs)
+        elif n_parts > 0:
+            from .workloads import preconditioners
+            self.pcs = preconditioners(self.ops, [n_parts] * len(self.ops), precision, ordering, kind=kind)
+        else:
+            self.pcs = [None, None]
         self.batch = cpm.Batch(self.ops, self.pcs, [1, 1])
         self.tuning = self.batch.autotune(cache=tune_cache) if tune else None
         u0, v0 = inputs.gray_scott_ic(band.active_keys, seed)

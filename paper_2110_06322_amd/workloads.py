@@ -18,6 +18,7 @@ right-hand sides on the GPU). Inputs come from the seeded generators of
 """
 from __future__ import annotations
 
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -53,10 +54,27 @@ def sphere(precision="fp64", kind="oras", h=0.02, n_parts=64, device="cuda") -> 
     return Instance(b, op, pc, f, 1, {"rtol": 1e-8})
 
 
+# host threads for independent setups: the library's host code releases the GIL
+# (ctypes) and each setup also runs its own OpenMP loops
+SETUP_THREADS = 4
+
+
+def preconditioners(ops, n_parts, precision="fp32", ordering="rcm", kind="oras", overlap=2.0,
+                    threads=SETUP_THREADS):
+    """(O)RAS preconditioners for several operators, built concurrently, in order."""
+    def one(args):
+        op, ns = args
+        return cpm.Precond(op, kind=kind, n_parts=ns, overlap=overlap, precision=precision, ordering=ordering)
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        return list(ex.map(one, zip(ops, n_parts)))
+
+
 def batched(n_each=16, hs=(0.04, 0.02, 0.01), nrhs=4, precision="fp32", kind="oras", seed=3,
-            n_sub_range=(32, 512), device="cuda", ordering="rcm") -> list[Instance]:
-    out = []
-    for i, spec in enumerate(inputs.batch_instances(seed=seed, n_each=n_each, hs=hs)):
+            n_sub_range=(32, 512), device="cuda", ordering="rcm", threads=SETUP_THREADS) -> list[Instance]:
+    specs = list(inputs.batch_instances(seed=seed, n_each=n_each, hs=hs))
+
+    def one(item):
+        i, spec = item
         box = inputs.domain_box(spec["kind"], spec["params"], 3, spec["h"], 3)
         b = cpm.Band(spec["kind"], spec["params"], 3, spec["h"], 3, lo=box[0], hi=box[1])
         op = cpm.Operator(b, spec["c"])
@@ -65,8 +83,13 @@ def batched(n_each=16, hs=(0.04, 0.02, 0.01), nrhs=4, precision="fp32", kind="or
         keys = b.active_keys
         F = np.stack([inputs.normal(seed * 1000 + i, r, keys) for r in range(nrhs)], axis=1)
         f = torch.tensor(np.ascontiguousarray(F).reshape(-1), dtype=torch.float64, device=device)
-        out.append(Instance(b, op, pc, f, nrhs, dict(spec, n_sub=ns, box=box)))
-    return out
+        return Instance(b, op, pc, f, nrhs, dict(spec, n_sub=ns, box=box))
+
+    # largest first, so that the long setups start early; results keep the spec order
+    order = sorted(range(len(specs)), key=lambda i: specs[i]["h"])
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        built = dict(zip(order, ex.map(one, [(i, specs[i]) for i in order])))
+    return [built[i] for i in range(len(specs))]
 
 
 def adjoint_torus(h=0.01, n_parts=128, device="cuda"):
