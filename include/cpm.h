@@ -346,6 +346,64 @@ cpm_status cpm_gray_scott_rhs(int64_t n, const double* u, const double* v, doubl
                               double mu_u, double mu_v, double* fu, double* fv, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Additive Runge-Kutta IMEX time stepping of surface reaction-diffusion
+ * systems w_t = F_E(t, w) + mu Lap_S w (Sec. 1, eq. rdsys): the diffusion
+ * implicit, the rest explicit. Sec. 4.1.3 (heat equation, eq. heat) and
+ * Sec. 4.1.5 (Gray-Scott, eq. grayscott) run with a third-order additive
+ * Runge-Kutta IMEX integrator by default; CPM_IMEX_ARK3 is ARK3(2)4L[2]SA
+ * (Kennedy & Carpenter, Appl. Numer. Math. 44, 2003: explicit tableau A^E,
+ * L-stable stiffly accurate ESDIRK tableau A^I with diagonal gamma), and
+ * CPM_IMEX_EULER is forward/backward Euler. A step computes
+ *   W_1 = w^n,
+ *   (I - dt gamma mu Lap) W_i = w^n + dt sum_{j<i} (aE_ij KE_j + aI_ij KI_j),
+ *   KE_j = F_E(t + c_j dt, W_j), KI_j = mu Lap_S^h W_j,
+ *   w^{n+1} = w^n + dt sum_j (bE_j KE_j + bI_j KI_j),
+ * each stage solve being A(c_w) W_i = rhs/(dt gamma mu_w) with the species'
+ * operator at shift c_w = 1/(dt gamma mu_w) (cpm_imex_shift), and
+ * Lap_S^h x = c_w x - A(c_w) x. The species' stage solves run as one batch,
+ * warm-started from the previous stage.
+ *   kind GRAY_SCOTT: 2 species, F_E = (-u v^2 + F(1-u), u v^2 - (F+k) v);
+ *   kind HEAT:       1 species, F_E = cos(t) g1 + sin(t) g2 (eq. htForce has
+ *                    this form), g1, g2 given at create.
+ * ------------------------------------------------------------------- */
+typedef enum { CPM_IMEX_EULER = 0, CPM_IMEX_ARK3 = 1 } cpm_imex_scheme;
+typedef enum { CPM_RD_GRAY_SCOTT = 0, CPM_RD_HEAT = 1 } cpm_rd_kind;
+
+typedef struct {
+  int32_t scheme;         /* cpm_imex_scheme (default ARK3) */
+  int32_t kind;           /* cpm_rd_kind (default GRAY_SCOTT) */
+  int32_t nspecies;       /* 2 (Gray-Scott) or 1 (heat) */
+  double dt;              /* time step, > 0 */
+  double mu[2];           /* diffusion coefficient of each species, > 0 */
+  double F, k;            /* Gray-Scott feed and kill rates */
+  int32_t tune;           /* 1: autotune the stage solves' kernels at creation */
+} cpm_imex_opts;
+
+typedef struct cpm_imex_s cpm_imex;
+
+cpm_status cpm_imex_opts_default(cpm_imex_opts* opts);
+/* The shift 1/(dt gamma mu_species) the species' operator must carry (0 on
+ * bad arguments). */
+double cpm_imex_shift(const cpm_imex_opts* opts, int32_t species);
+/* ops[s] (and pcs[s], may be NULL or hold NULLs): borrowed, one per species,
+ * on one band, shifts as cpm_imex_shift gives (else CPM_ERR_ARG); they must
+ * outlive the integrator. forcing: HEAT only, device {g1, g2}, each [N_A],
+ * copied at creation. Allocates stage buffers of 2 s nspecies N_A + 3 N_A
+ * doubles (s stages). */
+cpm_status cpm_imex_create(const cpm_operator* const* ops, const cpm_precond* const* pcs,
+                           const cpm_imex_opts* opts, const double* const* forcing, cpm_imex** out);
+/* Advances w[s] (device [N_A] each, in place) by nsteps steps from time t.
+ * Stage solves use sopts (FP64 or MIXED_IR; not transposed). stats: host
+ * array of nspecies entries or NULL (iterations, restarts, apply and
+ * preconditioner counts, time summed over all stage solves; relres the
+ * largest; converged only if all were). Blocks until done. Returns
+ * CPM_NOT_CONVERGED (w holds the last completed step) when a stage solve
+ * fails to converge. */
+cpm_status cpm_imex_step(cpm_imex* im, double t, double* const* w, int32_t nsteps, const cpm_solve_opts* sopts,
+                         cpm_solve_stats* stats, void* stream);
+void cpm_imex_destroy(cpm_imex* im);
+
+/* ---------------------------------------------------------------------
  * Misc
  * ------------------------------------------------------------------- */
 const char* cpm_last_error(void);

@@ -60,6 +60,11 @@ class SolveStats(C.Structure):
                 ("n_apply", C.c_int32)]
 
 
+class ImexOpts(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("kind", C.c_int32), ("nspecies", C.c_int32), ("dt", C.c_double),
+                ("mu", C.c_double * 2), ("F", C.c_double), ("k", C.c_double), ("tune", C.c_int32)]
+
+
 class TuneResult(C.Structure):
     _fields_ = [("apply_variant", C.c_int32), ("schwarz_variant", C.c_int32), ("schwarz_threads", C.c_int32),
                 ("schwarz_sleep", C.c_int32), ("apply_ms", C.c_double), ("precond_ms", C.c_double),
@@ -101,6 +106,11 @@ SIGNATURES = [
     ("cpm_autotune", I32, [P, P, I32, C.c_char_p, I32, P, C.POINTER(TuneResult)]),
     ("cpm_batch_autotune", I32, [P, C.c_char_p, I32, P, C.POINTER(TuneResult)]),
     ("cpm_gray_scott_rhs", I32, [I64, P, P, D, D, D, D, D, P, P, P]),
+    ("cpm_imex_opts_default", I32, [C.POINTER(ImexOpts)]),
+    ("cpm_imex_shift", D, [C.POINTER(ImexOpts), I32]),
+    ("cpm_imex_create", I32, [C.POINTER(P), C.POINTER(P), C.POINTER(ImexOpts), C.POINTER(P), C.POINTER(P)]),
+    ("cpm_imex_step", I32, [P, D, C.POINTER(P), I32, C.POINTER(SolveOpts), C.POINTER(SolveStats), P]),
+    ("cpm_imex_destroy", None, [P]),
     ("cpm_last_error", C.c_char_p, []),
     ("cpm_version", I32, []),
     ("cpm_device_count", I32, []),

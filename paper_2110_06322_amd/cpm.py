@@ -460,3 +460,83 @@ class _shift:
         if self.op.c != self.old:
             self.op.set_shift(self.old)
         return False
+
+
+IMEX_SCHEME = {"euler": 0, "ark3": 1}
+RD_KIND = {"gray_scott": 0, "heat": 1}
+
+
+def imex_options(scheme="ark3", kind="gray_scott", dt=1.0, mu=(2e-5, 1e-5), F=0.04, k=0.06, tune=False):
+    o = _capi.ImexOpts()
+    check(lib().cpm_imex_opts_default(C.byref(o)))
+    o.scheme = IMEX_SCHEME[scheme]
+    o.kind = RD_KIND[kind]
+    o.nspecies = 2 if kind == "gray_scott" else 1
+    o.dt = float(dt)
+    for s, m in enumerate(tuple(mu)[:2]):
+        o.mu[s] = float(m)
+    o.F, o.k = float(F), float(k)
+    o.tune = int(bool(tune))
+    return o
+
+
+def imex_shift(scheme="ark3", dt=1.0, mu=1.0) -> float:
+    """The shift c = 1/(dt gamma mu) that a species' operator needs for the scheme's stage
+    solves (gamma: the implicit tableau's diagonal), as the library defines it."""
+    o = imex_options(scheme, "heat", dt, (mu, mu))
+    c = float(lib().cpm_imex_shift(C.byref(o), 0))
+    if not c > 0:
+        raise ValueError("bad IMEX scheme, dt or mu")
+    return c
+
+
+class Imex:
+    """Additive Runge-Kutta IMEX integrator of a surface reaction-diffusion system (ARK3(2)4L[2]SA
+    or IMEX Euler), the stage solves batched over the species. ops: one operator per species at
+    shift imex_shift(scheme, dt, mu_s); forcing (heat only): two device fields g1, g2 of the
+    forcing cos(t) g1 + sin(t) g2."""
+
+    def __init__(self, ops, pcs=None, scheme="ark3", kind="gray_scott", dt=1.0, mu=(2e-5, 1e-5), F=0.04, k=0.06,
+                 forcing=None, tune=False):
+        self.opts = imex_options(scheme, kind, dt, mu, F, k, tune)
+        ns = self.opts.nspecies
+        self._ops = check_count(ops, ns, "ops")
+        self._pcs = check_count(pcs if pcs is not None else [None] * ns, ns, "pcs")
+        self.n = self._ops[0].n_active
+        for o, p in zip(self._ops, self._pcs):
+            if o.n_active != self.n:
+                raise ValueError("the species' operators must share one band")
+            if p is not None and p.op is not o:
+                raise ValueError("a preconditioner was built for another operator")
+        oa = (C.c_void_p * ns)(*[o._h.value for o in self._ops])
+        pa = (C.c_void_p * ns)(*[(p._h.value if p is not None else None) for p in self._pcs])
+        fa = None
+        if kind == "heat":
+            forcing = check_count(forcing or [], 2, "forcing")
+            fa = (C.c_void_p * 2)(*[_dptr(g, self.n, "forcing").value for g in forcing])
+        h_ = C.c_void_p()
+        check(lib().cpm_imex_create(oa, pa, C.byref(self.opts), fa, C.byref(h_)))
+        self._h = h_
+
+    def step(self, ws, t=0.0, nsteps=1, opts: SolveOptions | None = None, stream=None, **kw):
+        """Advance the species' states ws (device vectors, in place) by nsteps steps from time t;
+        returns one stats dict per species (summed over the stage solves)."""
+        opts = opts or SolveOptions(**kw)
+        ns = self.opts.nspecies
+        ws = check_count(ws, ns, "ws")
+        for i, w in enumerate(ws):
+            check_vec(w, self.n, f"ws[{i}]")
+        wa = (C.c_void_p * ns)(*[_dptr(w, self.n).value for w in ws])
+        st = (_capi.SolveStats * ns)()
+        co = opts.to_c()
+        code = lib().cpm_imex_step(self._h, float(t), wa, int(nsteps), C.byref(co), st, _stream(stream))
+        if code not in (_capi.CPM_OK, 6):
+            check(code)
+        return [_stats_dict(s) for s in st]
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) is not None and self._h.value:
+                lib().cpm_imex_destroy(self._h)
+        except Exception:
+            pass

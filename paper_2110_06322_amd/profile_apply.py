@@ -1,10 +1,12 @@
 """Short, profiler-friendly driver: a fixed number of operator applies (or,
 with a fourth argument, ORAS preconditioner applies with that local row order
-and FP32 factors, 64 subdomains, overlap 2h) on one workload and a
-device-to-device copy of known size (the copy calibrates the hardware byte
-counters against a kernel whose traffic is exactly known).
+and FP32 factors, 64 subdomains, overlap 2h, or with `transpose` transpose
+applies) on one workload and a device-to-device copy of known size (the copy
+calibrates the hardware byte counters against a kernel whose traffic is
+exactly known). Applies rotate through four input/output pairs, as the
+benchmark's do.
 
-Usage: python -m paper_2110_06322_amd.profile_apply [sphere|torus] [h] [reps] [rcm|distance]
+Usage: python -m paper_2110_06322_amd.profile_apply [sphere|torus] [h] [reps] [rcm|distance|transpose]
 """
 from __future__ import annotations
 
@@ -22,17 +24,22 @@ def main():
     params = (1.0,) if kind == "sphere" else (1.0, 0.4)
     band = cpm.Band(kind, params, 3, h, 3)
     op = cpm.Operator(band, 1.0)
-    x = torch.tensor(inputs.normal(1, 0, band.active_keys), dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    ordering = sys.argv[4] if len(sys.argv) > 4 else None
-    if ordering:
-        pc = cpm.Precond(op, kind="oras", n_parts=64, overlap=2.0, precision="fp32", ordering=ordering)
+    xs = [torch.tensor(inputs.normal(10 + i, 0, band.active_keys), dtype=torch.float64, device="cuda")
+          for i in range(4)]
+    ys = [torch.empty_like(x) for x in xs]
+    mode = sys.argv[4] if len(sys.argv) > 4 else None
+    if mode in ("rcm", "distance"):
+        pc = cpm.Precond(op, kind="oras", n_parts=64, overlap=2.0, precision="fp32", ordering=mode)
         cpm.autotune(op, pc)
-        for _ in range(reps):
-            pc.apply(x, out=y)
+        for r in range(reps):
+            pc.apply(xs[r % 4], out=ys[r % 4])
+    elif mode == "transpose":
+        for r in range(reps):
+            op.apply_T(xs[r % 4], out=ys[r % 4])
     else:
-        for _ in range(reps):
-            op.apply(x, out=y)
+        cpm.autotune(op, None)
+        for r in range(reps):
+            op.apply(xs[r % 4], out=ys[r % 4])
     a = torch.zeros(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")  # 64 MiB
     b = torch.empty_like(a)
     for _ in range(4):
