@@ -271,3 +271,49 @@ def build_schwarz(A: sp.csr_matrix, pattern: sp.csr_matrix, cp: np.ndarray, keys
             S.perms.append(None)
             S.factors.append(spla.splu(sp.csc_matrix(Aj)))
     return S
+
+
+# ---------------------------------------------------------------------------------------------
+# Two-level Schwarz: a coarse-grid correction added to the one-level (O)RAS preconditioner.
+# The paper's weak-scaling runs (Sec. 5, Table 3) show the one-level method's iteration count
+# growing with the number of subdomains; a coarse space is the standard remedy. Reading taken
+# here (the paper names none): the piecewise-constant coarse space of Nicolaides (SIAM J.
+# Numer. Anal. 24, 1987), one basis vector per subdomain equal to 1 on the nodes it owns,
+# R0 (N_S x N_A); Galerkin coarse matrix A0 = R0 A R0^T; combined with the one-level
+# preconditioner M1^-1 either additively, z = M1^-1 r + R0^T A0^-1 R0 r, or multiplicatively
+# (coarse first):  z_c = R0^T A0^-1 R0 r,  z = z_c + M1^-1 (r - A z_c).
+
+
+def coarse_space(owner: np.ndarray, n_parts: int) -> sp.csr_matrix:
+    """R0[j, i] = 1 when node i is owned by subdomain j."""
+    n = owner.size
+    return sp.csr_matrix((np.ones(n), (np.asarray(owner, dtype=np.int64), np.arange(n))), shape=(n_parts, n))
+
+
+@dataclass
+class TwoLevel:
+    one: Schwarz
+    A: sp.csr_matrix
+    R0: sp.csr_matrix
+    A0: np.ndarray
+    lu0: tuple
+    mode: str = "hybrid"
+
+    def coarse(self, r: np.ndarray) -> np.ndarray:
+        import scipy.linalg as sla
+        return self.R0.T @ sla.lu_solve(self.lu0, self.R0 @ r)
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        if self.mode == "additive":
+            return self.one.apply(r) + self.coarse(r)
+        zc = self.coarse(r)
+        return zc + self.one.apply(r - self.A @ zc)
+
+
+def build_two_level(A: sp.csr_matrix, one: Schwarz, mode: str = "hybrid") -> TwoLevel:
+    import scipy.linalg as sla
+    if mode not in ("additive", "hybrid"):
+        raise ValueError("mode must be 'additive' or 'hybrid'")
+    R0 = coarse_space(one.owner, len(one.omegas))
+    A0 = (R0 @ sp.csr_matrix(A) @ R0.T).toarray()
+    return TwoLevel(one=one, A=sp.csr_matrix(A), R0=R0, A0=A0, lu0=sla.lu_factor(A0), mode=mode)

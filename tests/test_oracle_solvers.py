@@ -318,3 +318,50 @@ def test_oras_local_rows_follow_robin_substitution_sphere():
             n_cross += len(owners) >= 2
             n_single += len(owners) == 1
     assert n_cross > 0 and n_single > 0
+
+
+def test_two_level_coarse_matrix_brute_force_and_galerkin():
+    """A0[j, k] = sum of A over (rows owned by j) x (columns owned by k), by explicit loops on a
+    small band; the hybrid correction leaves a residual with zero coarse component
+    (R0 (r - A z_c) = 0); P = R0^T A0^-1 R0 A is a projection that fixes the coarse space."""
+    bd, E, Om, A, P = C.matrices("circle", (1.0,), 2, 0.1, 2, 1.0)
+    one = schwarz.build_schwarz(A, P, bd.cp_active, bd.active_keys, 0.1, 4, 2.0, kind="ras", subsolver="lu")
+    tl = schwarz.build_two_level(A, one, "hybrid")
+    Ad = A.toarray()
+    owner = one.owner
+    for j in range(4):
+        for k in range(4):
+            s = 0.0
+            for i in np.nonzero(owner == j)[0]:
+                for l_ in np.nonzero(owner == k)[0]:
+                    s += Ad[i, l_]
+            assert abs(tl.A0[j, k] - s) <= 1e-12 * np.abs(Ad).sum()
+    r = np.random.default_rng(5).standard_normal(bd.n_active)
+    zc = tl.coarse(r)
+    assert np.abs(tl.R0 @ (r - A @ zc)).max() <= 1e-12 * np.abs(tl.R0 @ r).max()
+    Pm = lambda x: tl.coarse(A @ x)
+    x = np.random.default_rng(6).standard_normal(bd.n_active)
+    assert np.abs(Pm(Pm(x)) - Pm(x)).max() <= 1e-12 * np.abs(Pm(x)).max()
+    e = np.random.default_rng(7).standard_normal(4)
+    assert np.abs(Pm(tl.R0.T @ e) - tl.R0.T @ e).max() <= 1e-12 * np.abs(e).max()
+
+
+def test_two_level_keeps_iterations_flat_under_weak_scaling():
+    """Unit sphere, exact local solves, subdomains growing with the unknowns (h = 0.1 with 8
+    boxes, h = 0.05 with 32): one-level RAS needs more FGMRES iterations as N_S grows, the
+    hybrid two-level preconditioner fewer, with a smaller growth; the solution is unchanged."""
+    res = {}
+    for h, ns in ((0.1, 8), (0.05, 32)):
+        bd, E, Om, A, P = C.matrices("sphere", (1.0,), 3, h, 3, 1.0)
+        f = 21.0 * inputs.sphere_y4(bd.cp_active, 2)
+        one = schwarz.build_schwarz(A, P, bd.cp_active, bd.active_keys, h, ns, 2.0, kind="ras", subsolver="lu")
+        tl = schwarz.build_two_level(A, one, "hybrid")
+        x1, i1 = krylov.fgmres(A, f, M=one.apply, rtol=1e-8, max_it=3000)
+        x2, i2 = krylov.fgmres(A, f, M=tl.apply, rtol=1e-8, max_it=3000)
+        assert i1["converged"] and i2["converged"]
+        assert np.abs(x1 - x2).max() <= 1e-6 * np.abs(x1).max()
+        res[h] = (i1["iters"], i2["iters"])
+    print(res)
+    (a1, a2), (b1, b2) = res[0.1], res[0.05]
+    assert a2 <= a1 and b2 < b1
+    assert b2 - a2 < b1 - a1
