@@ -131,6 +131,17 @@ cpm_status cpm_extend_apply(const cpm_operator* op, const double* u, double* v, 
  * without atomics (each output gathers the extension rows that reach it). */
 cpm_status cpm_apply(const cpm_operator* op, const double* x, double* y, int32_t nrhs, void* stream);
 cpm_status cpm_apply_T(const cpm_operator* op, const double* x, double* y, int32_t nrhs, void* stream);
+/* The same y = A^T x for callers that cannot allocate device memory (code
+ * under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): cpm_apply_T allocates its (N_A+N_G) * nrhs intermediate sums on
+ * first use, this call keeps them in a static device array of 4,194,304
+ * doubles (32 MiB per GPU, held until the process ends) and calls no
+ * allocator. Larger (N_A+N_G) * nrhs is refused with CPM_ERR_ARG before any
+ * launch. All calls on one GPU share that array: calls that overlap on one GPU
+ * (concurrent streams or threads) race and must be ordered by the caller.
+ * The current device must be the operator's. Same arguments and results as
+ * cpm_apply_T (identical bits). */
+cpm_status cpm_apply_T_noalloc(const cpm_operator* op, const double* x, double* y, int32_t nrhs, void* stream);
 
 /* dL/dc for u = A(c)^-1 f (Sec. 2.1, eq. lapBel: A(c) = c I + K with K
  * independent of c): with lambda the adjoint solution of A^T lambda = dL/du,

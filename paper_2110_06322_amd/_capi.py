@@ -90,6 +90,7 @@ SIGNATURES = [
     ("cpm_extend_apply", I32, [P, P, P, P]),
     ("cpm_apply", I32, [P, P, P, I32, P]),
     ("cpm_apply_T", I32, [P, P, P, I32, P]),
+    ("cpm_apply_T_noalloc", I32, [P, P, P, I32, P]),
     ("cpm_shift_gradient", I32, [P, P, P, I32, P, P]),
     ("cpm_precond_create", I32, [P, C.POINTER(PrecondOpts), C.POINTER(P)]),
     ("cpm_precond_get_info", I32, [P, C.POINTER(PrecondInfo)]),

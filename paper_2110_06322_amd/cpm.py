@@ -170,6 +170,13 @@ class Operator:
         check(lib().cpm_apply_T(self._h, _dptr(x, n), _dptr(y, n), nrhs, _stream(stream)))
         return y
 
+    def apply_T_noalloc(self, x, out, nrhs: int = 1, stream=None):
+        """y = A^T x through the allocation-free entry point (its intermediate sums live in
+        a static device array shared by every call on the GPU); `out` must be given."""
+        x, y, n = self._io(x, out, nrhs)
+        check(lib().cpm_apply_T_noalloc(self._h, _dptr(x, n), _dptr(y, n), nrhs, _stream(stream)))
+        return y
+
     def extend(self, u, out=None, stream=None):
         torch = _torch()
         n = self.band.n_active + self.band.n_ghost
