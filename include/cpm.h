@@ -84,6 +84,7 @@ typedef struct {
   int32_t shape[3];       /* grid points per axis */
   int64_t n_bricks;       /* 4x4x4 (d=3) or 8x8 (d=2) node bricks holding band nodes */
   int32_t closure_iterations;
+  int32_t reach;          /* the ghost set's reach along an axis (1, or 2 for fourth-order stencils) */
 } cpm_band_info;
 
 /* Build the band on the host. Grid nodes x_i = lo + i h, i_k in
@@ -91,18 +92,48 @@ typedef struct {
  * Sigma_A = union over x in B_gamma of the cube b + {0..p}^d with
  * b = floor((cp(x)-lo)/h - (p-1)/2); Sigma_G = grid neighbours of Sigma_A not
  * in Sigma_A. gamma <= 0 selects h sqrt((d-1)((p+1)/2)^2 + (1+(p+1)/2)^2).
- * d in {2,3}, p in {1,2,3}. Errors: CPM_ERR_ARG (bad sizes / surface),
+ * d in {2,3}, p in 1..5 (the fused second-order apply takes p <= 3; p = 4, 5
+ * run the two-kernel path of cpm_operator_create_order). Errors: CPM_ERR_ARG (bad sizes / surface),
  * CPM_ERR_BAND (a cube or neighbour leaves the grid box, or closure needs
  * more than one extra pass). lo/hi: host arrays of d doubles. */
 cpm_status cpm_band_build(const cpm_surface* surface, int32_t d, double h, int32_t p,
                           const double* lo, const double* hi, double gamma,
                           cpm_band** out);
+/* Closest points supplied by the caller (Sec. 2.1: the library takes
+ * user-defined closest point functions; Sec. 4.1.6: an open, user-defined
+ * hemisphere with mixed boundary conditions). The callback receives n points
+ * x [n][d] (host) and writes their closest points cp [n][d] and flags
+ * flag [n]: 1 when the closest point lies on a part of the surface's boundary
+ * carrying homogeneous Dirichlet conditions, else 0 (interior points, and
+ * boundary points with the natural homogeneous Neumann treatment). It returns
+ * 0 on success; anything else aborts the build with CPM_ERR_ARG. It is called
+ * from the building thread only, with batches of up to 2^20 points.
+ * A node x whose closest point c is flagged takes the extension
+ * -(E u)(cp(2c - x)): interpolation at the closest point of its mirror image
+ * through c, negated (second-order homogeneous Dirichlet). The band is then
+ * built as by cpm_band_build with these interpolation points. */
+typedef int32_t (*cpm_cp_callback)(int64_t n, const double* x, double* cp, int32_t* flag, void* ctx);
+cpm_status cpm_band_build_user(cpm_cp_callback cp, void* ctx, int32_t d, double h, int32_t p, const double* lo,
+                               const double* hi, double gamma, cpm_band** out);
+/* Either builder with a wider ghost set (Sec. 3.1.2: the fourth-order
+ * Laplace-Beltrami grid function's stencil reaches two nodes along each
+ * axis): Sigma_G = the grid nodes within `reach` steps along an axis of
+ * Sigma_A that are not in Sigma_A, reach in {1, 2}; gamma <= 0 selects
+ * h sqrt((d-1)((p+1)/2)^2 + (reach+(p+1)/2)^2). Exactly one of surface and
+ * cp is given (ctx goes with cp). Errors as for the builders above. */
+cpm_status cpm_band_build_reach(const cpm_surface* surface, cpm_cp_callback cp, void* ctx, int32_t d, double h,
+                                int32_t p, const double* lo, const double* hi, double gamma, int32_t reach,
+                                cpm_band** out);
 cpm_status cpm_band_get_info(const cpm_band* band, cpm_band_info* info);
 /* Export the library's node order: Sigma_A first (indices 0..N_A-1, the
  * unknowns), then Sigma_G. Host arrays, caller-owned, any may be NULL:
  * gidx [(N_A+N_G) x d] int32 grid indices, cp [(N_A+N_G) x d] closest
  * points, kind [N_A+N_G] (0 active, 1 ghost). Row-major [node][axis]. */
 cpm_status cpm_band_export(const cpm_band* band, int32_t* gidx, double* cp, uint8_t* kind);
+/* The extension rows' interpolation points ip [(N_A+N_G) x d] and signs
+ * sign [N_A+N_G] (+1, or -1 for mirrored Dirichlet rows), same order as
+ * cpm_band_export; host arrays, either may be NULL. */
+cpm_status cpm_band_export_interp(const cpm_band* band, double* ip, double* sign);
 void cpm_band_destroy(cpm_band* band);
 
 /* ---------------------------------------------------------------------
@@ -114,6 +145,24 @@ typedef struct cpm_operator_s cpm_operator;
 /* Uploads the band (closest points, brick map, tiles) to device memory
  * owned by the operator. The band may be destroyed afterwards. c > 0. */
 cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out);
+/* The stabilized operator of a chosen stencil order (Sec. 3.1.2: built-in
+ * second- and fourth-order Laplace-Beltrami grid functions):
+ *   order 2: A = (c + 2d/h^2) I - h^-2 O1 E (as cpm_operator_create);
+ *   order 4: A = (c + 30d/(12h^2)) I - (12h^2)^-1 (16 O1 - O2) E, with O1 the
+ *            sum over the 2d nearest grid neighbours and O2 over the 2d nodes
+ *            two steps away along an axis (the five-point fourth-order second
+ *            difference per axis, the node's own term un-extended);
+ *            needs a band of reach 2 (cpm_band_build_reach).
+ * Order 2 with p <= 3 runs the fused apply; order 4, or p = 4 or 5, runs two
+ * kernels (every extension row into an operator-owned vector of (N_A+N_G) * 4
+ * doubles, then the stencil). With degree-p interpolation the surface
+ * solution's error is O(h^order) + O(h^(p-1)): order 4 needs p = 5 for fourth
+ * order. Such operators support everything but the transposed apply (and so
+ * transposed solves); a preconditioner built on them is the (O)RAS of the
+ * second-order operator with degree min(p, 3) interpolation at the same
+ * shift, a spectrally equivalent approximation. */
+cpm_status cpm_operator_create_order(const cpm_band* band, double c, int32_t order, void* stream,
+                                     cpm_operator** out);
 /* Changes the shift c (> 0) of A = (c + 2d/h^2) I - h^-2 O E. Synchronizes
  * the device. Later cpm_solve calls use the new shift; a batch takes its
  * operators' shifts when it is created, so create batches after this call. */
@@ -185,6 +234,14 @@ typedef enum { CPM_PREC_FP64 = 0, CPM_PREC_FP32 = 1 } cpm_precision;
  * entries (3-D p = 3 rows have at most 176), else the rows are solved one per
  * wavefront. */
 typedef enum { CPM_ORDER_RCM = 0, CPM_ORDER_DISTANCE = 1 } cpm_ordering;
+/* Coarse level (two-level Schwarz; the one-level method's iteration count grows
+ * with the number of subdomains, Sec. 5 Table 3): the piecewise-constant coarse
+ * space of one vector per subdomain (1 on the nodes it owns, R0), the Galerkin
+ * coarse matrix A0 = R0 A R0^T (built with the operator, inverted densely), and
+ *   ADDITIVE:     z = M1^-1 r + R0^T A0^-1 R0 r,
+ *   COARSE_FIRST: z_c = R0^T A0^-1 R0 r, z = z_c + M1^-1 (r - A z_c),
+ * M1 the one-level (O)RAS. Not with transpose = 1. */
+typedef enum { CPM_COARSE_NONE = 0, CPM_COARSE_ADDITIVE = 1, CPM_COARSE_FIRST = 2 } cpm_coarse;
 
 typedef struct {
   int32_t kind;           /* cpm_pc_kind */
@@ -196,6 +253,7 @@ typedef struct {
   int32_t precision;      /* cpm_precision of the factors and local solves */
   int32_t transpose;      /* 1: build on A^T (for adjoint solves) */
   int32_t ordering;       /* cpm_ordering (ILU(0) only) */
+  int32_t coarse;         /* cpm_coarse (default NONE; n_parts <= 4096) */
 } cpm_precond_opts;
 
 typedef struct cpm_precond_s cpm_precond;
@@ -259,6 +317,20 @@ typedef struct {
   double inner_rtol;      /* MIXED_IR: per-cycle reduction target (default 1e-4) */
   int32_t stagnation_cycles; /* cycles without 1% progress before giving up (default 50) */
   int32_t profile;        /* 1: time operator / preconditioner kernels with hipEvents (adds syncs) */
+  /* Operator algebra (Sec. 3.1.2, grid functions added and composed; Sec. 4.1.2, the
+   * shifted biharmonic equation): poly_n = 0 solves A u = f. poly_n in 1..5 solves
+   * P(L) u = f instead, P(L) = sum_{k < poly_n} poly_coef[k] L^k, where L = c I - A(c)
+   * is the second-order Laplace-Beltrami operator of each instance (c its shift; L
+   * does not depend on c). The shifted biharmonic c0 + L^2 is poly_n = 3, poly_coef
+   * = {c0, 0, 1}. One application of P(L) costs poly_n - 1 applies of A.
+   * Not combinable with transpose or use_graph. */
+  int32_t poly_n;
+  double poly_coef[5];
+  /* preconditioner applications per Arnoldi step, 1..4 (default 1): z = M^-k v. With
+   * k = 2 and M the (O)RAS of A(sqrt(c0)), M^-2 approximates A(sqrt(c0))^-2, whose
+   * inverse (sqrt(c0) - L)^2 is spectrally equivalent to c0 + L^2 (ratio within
+   * [1, 2] for a negative semi-definite L). */
+  int32_t pc_power;
 } cpm_solve_opts;
 
 typedef struct {
@@ -277,6 +349,15 @@ typedef struct {
 
 cpm_status cpm_solve_opts_default(cpm_solve_opts* opts);
 cpm_status cpm_precond_opts_default(cpm_precond_opts* opts);
+
+/* y = P(L) x = sum_{k < ncoef} coef[k] L^k x with L = c I - A(c) the operator's
+ * Laplace-Beltrami operator (Sec. 3.1.2: grid functions added and composed;
+ * the biharmonic is L L). ncoef in 1..5, coef: host [ncoef], finite.
+ * x, y: device [N_A * nrhs], nrhs in {1,2,4}, must not alias. Stream-ordered;
+ * allocates a workspace of 2 N_A nrhs doubles on first use per size (not under
+ * graph capture then). CPM_ERR_ARG on bad arguments. */
+cpm_status cpm_poly_apply(const cpm_operator* op, int32_t ncoef, const double* coef, const double* x,
+                          double* y, int32_t nrhs, void* stream);
 
 /* f, u: device [N_A * nrhs]; pc may be NULL (no preconditioner). stats may be NULL. */
 cpm_status cpm_solve(const cpm_operator* op, const cpm_precond* pc, const double* f, double* u,
@@ -421,6 +502,11 @@ const char* cpm_last_error(void);
 int32_t cpm_version(void);
 /* Number of HIP devices visible (0 when none); never fails. */
 int32_t cpm_device_count(void);
+/* sizeof of the public option / result structs, for bindings that declare
+ * them by hand: 0 cpm_solve_opts, 1 cpm_solve_stats, 2 cpm_precond_opts,
+ * 3 cpm_tune_result, 4 cpm_imex_opts, 5 cpm_band_info; -1 for any other
+ * value. Host only. */
+int64_t cpm_abi_sizeof(int32_t which);
 
 #ifdef __cplusplus
 }

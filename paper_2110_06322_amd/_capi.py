@@ -31,13 +31,14 @@ class BandInfo(C.Structure):
     _fields_ = [("n_active", C.c_int64), ("n_ghost", C.c_int64), ("n_band", C.c_int64),
                 ("d", C.c_int32), ("p", C.c_int32), ("h", C.c_double), ("gamma", C.c_double),
                 ("lo", C.c_double * 3), ("shape", C.c_int32 * 3), ("n_bricks", C.c_int64),
-                ("closure_iterations", C.c_int32)]
+                ("closure_iterations", C.c_int32), ("reach", C.c_int32)]
 
 
 class PrecondOpts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_parts", C.c_int32), ("overlap", C.c_double),
                 ("alpha", C.c_double), ("alpha_cross", C.c_double), ("subsolver", C.c_int32),
-                ("precision", C.c_int32), ("transpose", C.c_int32), ("ordering", C.c_int32)]
+                ("precision", C.c_int32), ("transpose", C.c_int32), ("ordering", C.c_int32),
+                ("coarse", C.c_int32)]
 
 
 class PrecondInfo(C.Structure):
@@ -50,7 +51,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double),
                 ("max_it", C.c_int32), ("mode", C.c_int32), ("transpose", C.c_int32),
                 ("use_graph", C.c_int32), ("inner_rtol", C.c_double), ("stagnation_cycles", C.c_int32),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("poly_n", C.c_int32), ("poly_coef", C.c_double * 5),
+                ("pc_power", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -73,16 +75,24 @@ class TuneResult(C.Structure):
 
 P = C.c_void_p
 I32 = C.c_int32
+# int32 cb(int64 n, const double* x, double* cp, int32* flag, void* ctx)
+CP_CALLBACK = C.CFUNCTYPE(C.c_int32, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                          C.POINTER(C.c_int32), C.c_void_p)
 I64 = C.c_int64
 D = C.c_double
 
 # (name, restype, argtypes) for every function declared in include/cpm.h
 SIGNATURES = [
     ("cpm_band_build", I32, [C.POINTER(Surface), I32, D, I32, C.POINTER(D), C.POINTER(D), D, C.POINTER(P)]),
+    ("cpm_band_build_user", I32, [CP_CALLBACK, P, I32, D, I32, C.POINTER(D), C.POINTER(D), D, C.POINTER(P)]),
+    ("cpm_band_build_reach", I32, [C.POINTER(Surface), CP_CALLBACK, P, I32, D, I32, C.POINTER(D), C.POINTER(D), D,
+                                   I32, C.POINTER(P)]),
     ("cpm_band_get_info", I32, [P, C.POINTER(BandInfo)]),
     ("cpm_band_export", I32, [P, P, P, P]),
+    ("cpm_band_export_interp", I32, [P, P, P]),
     ("cpm_band_destroy", None, [P]),
     ("cpm_operator_create", I32, [P, D, P, C.POINTER(P)]),
+    ("cpm_operator_create_order", I32, [P, D, I32, P, C.POINTER(P)]),
     ("cpm_operator_set_shift", I32, [P, D]),
     ("cpm_operator_get_shift", D, [P]),
     ("cpm_operator_n_active", I64, [P]),
@@ -92,6 +102,7 @@ SIGNATURES = [
     ("cpm_apply_T", I32, [P, P, P, I32, P]),
     ("cpm_apply_T_noalloc", I32, [P, P, P, I32, P]),
     ("cpm_shift_gradient", I32, [P, P, P, I32, P, P]),
+    ("cpm_poly_apply", I32, [P, I32, C.POINTER(D), P, P, I32, P]),
     ("cpm_precond_create", I32, [P, C.POINTER(PrecondOpts), C.POINTER(P)]),
     ("cpm_precond_get_info", I32, [P, C.POINTER(PrecondInfo)]),
     ("cpm_precond_export_partition", I32, [P, P, P, P]),
@@ -115,7 +126,11 @@ SIGNATURES = [
     ("cpm_last_error", C.c_char_p, []),
     ("cpm_version", I32, []),
     ("cpm_device_count", I32, []),
+    ("cpm_abi_sizeof", I64, [I32]),
 ]
+
+# ctypes mirrors of the public structs, in the order cpm_abi_sizeof numbers them
+ABI_STRUCTS = [SolveOpts, SolveStats, PrecondOpts, TuneResult, ImexOpts, BandInfo]
 
 _lib = None
 

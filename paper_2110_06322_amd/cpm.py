@@ -19,6 +19,7 @@ SUBSOLVER = {"ilu0": 0, "lu": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 MODE = {"fp64": 0, "mixed": 1}
 ORDERING = {"rcm": 0, "distance": 1}
+COARSE = {"none": 0, "additive": 1, "first": 2}
 
 
 def _torch():
@@ -81,7 +82,7 @@ class Band:
     """The CPM band (Sigma_A, Sigma_G) of an analytic surface, built on the host."""
 
     def __init__(self, kind: str, params, d: int, h: float, p: int, lo=None, hi=None,
-                 gamma: float = 0.0, center=(0.0, 0.0, 0.0)):
+                 gamma: float = 0.0, center=(0.0, 0.0, 0.0), reach: int = 1):
         s = _capi.Surface()
         s.kind = SURFACES[kind]
         for k, v in enumerate(params):
@@ -92,8 +93,55 @@ class Band:
         hi = [2.0] * d if hi is None else list(hi)
         arr = C.c_double * d
         h_ = C.c_void_p()
-        check(lib().cpm_band_build(C.byref(s), d, float(h), p, arr(*lo), arr(*hi), float(gamma), C.byref(h_)))
+        if reach == 1:
+            check(lib().cpm_band_build(C.byref(s), d, float(h), p, arr(*lo), arr(*hi), float(gamma), C.byref(h_)))
+        else:
+            check(lib().cpm_band_build_reach(C.byref(s), _capi.CP_CALLBACK(), None, d, float(h), p, arr(*lo),
+                                             arr(*hi), float(gamma), int(reach), C.byref(h_)))
         self._h = h_
+        self._init_info(kind, params, d, h, p)
+
+    @classmethod
+    def from_closest_point(cls, fn, d: int, h: float, p: int, lo, hi, gamma: float = 0.0, name: str = "user",
+                           reach: int = 1):
+        """Band of a surface given by a closest point function (cpm_band_build_user).
+
+        fn(x) with x an (n, d) float64 array returns (cp, flag): the (n, d) closest points
+        and an (n,) integer array, 1 where the closest point lies on a boundary part with
+        homogeneous Dirichlet conditions (those rows are mirrored), else 0. The function
+        only evaluates the surface; the band is built by the library."""
+        err = []
+
+        def cb(n, xp, cpp, flp, ctx):
+            try:
+                x = np.ctypeslib.as_array(xp, shape=(n, d))
+                cp, flag = fn(np.array(x))
+                np.ctypeslib.as_array(cpp, shape=(n, d))[:] = np.asarray(cp, dtype=np.float64).reshape(n, d)
+                np.ctypeslib.as_array(flp, shape=(n,))[:] = np.asarray(flag, dtype=np.int32).reshape(n)
+                return 0
+            except Exception as e:  # reported after the call returns
+                err.append(e)
+                return 1
+        self = cls.__new__(cls)
+        c_cb = _capi.CP_CALLBACK(cb)
+        arr = C.c_double * d
+        lo = list(lo)
+        hi = list(hi)
+        h_ = C.c_void_p()
+        if reach == 1:
+            code = lib().cpm_band_build_user(c_cb, None, d, float(h), p, arr(*lo), arr(*hi), float(gamma),
+                                             C.byref(h_))
+        else:
+            code = lib().cpm_band_build_reach(None, c_cb, None, d, float(h), p, arr(*lo), arr(*hi), float(gamma),
+                                              int(reach), C.byref(h_))
+        if err:
+            raise err[0]
+        check(code)
+        self._h = h_
+        self._init_info(name, (), d, h, p)
+        return self
+
+    def _init_info(self, kind, params, d, h, p):
         self.kind, self.params, self.d, self.h, self.p = kind, tuple(params), d, h, p
         info = _capi.BandInfo()
         check(lib().cpm_band_get_info(self._h, C.byref(info)))
@@ -102,9 +150,18 @@ class Band:
         self.n_ghost = int(info.n_ghost)
         self.n_band = int(info.n_band)
         self.gamma = float(info.gamma)
+        self.reach = int(info.reach)
         self.shape = tuple(int(info.shape[k]) for k in range(d))
         self.lo = np.array([info.lo[k] for k in range(d)])
         self._export = None
+
+    def export_interp(self):
+        """(ip [n, d], sign [n]): interpolation point and sign of every extension row."""
+        n = self.n_active + self.n_ghost
+        ip = np.zeros((n, self.d), dtype=np.float64)
+        sg = np.zeros(n, dtype=np.float64)
+        check(lib().cpm_band_export_interp(self._h, ip.ctypes.data_as(C.c_void_p), sg.ctypes.data_as(C.c_void_p)))
+        return ip, sg
 
     def export(self):
         """(gidx [n, d] int32, cp [n, d] float64, kind [n] uint8), Sigma_A first."""
@@ -135,11 +192,16 @@ class Band:
 
 
 class Operator:
-    """A = (c + 2d/h^2) I - h^-2 O E on a band, resident on the GPU."""
+    """A = (c + 2d/h^2) I - h^-2 O E on a band, resident on the GPU (order 4: the
+    fourth-order stencil, on a band of reach 2)."""
 
-    def __init__(self, band: Band, c: float, stream=None):
+    def __init__(self, band: Band, c: float, stream=None, order: int = 2):
         h_ = C.c_void_p()
-        check(lib().cpm_operator_create(band._h, float(c), _stream(stream), C.byref(h_)))
+        if order == 2:
+            check(lib().cpm_operator_create(band._h, float(c), _stream(stream), C.byref(h_)))
+        else:
+            check(lib().cpm_operator_create_order(band._h, float(c), int(order), _stream(stream), C.byref(h_)))
+        self.order = order
         self._h = h_
         self.band = band
         self.n_active = band.n_active
@@ -163,6 +225,17 @@ class Operator:
     def apply(self, x, out=None, nrhs: int = 1, stream=None):
         x, y, n = self._io(x, out, nrhs)
         check(lib().cpm_apply(self._h, _dptr(x, n), _dptr(y, n), nrhs, _stream(stream)))
+        return y
+
+    def poly_apply(self, coef, x, out=None, nrhs: int = 1, stream=None):
+        """y = sum_k coef[k] L^k x with L = c I - A(c), the band's Laplace-Beltrami operator
+        (1 to 5 coefficients)."""
+        coef = [float(a) for a in coef]
+        if not 1 <= len(coef) <= 5:
+            raise ValueError("1 to 5 polynomial coefficients")
+        x, y, n = self._io(x, out, nrhs)
+        ca = (C.c_double * len(coef))(*coef)
+        check(lib().cpm_poly_apply(self._h, len(coef), ca, _dptr(x, n), _dptr(y, n), nrhs, _stream(stream)))
         return y
 
     def apply_T(self, x, out=None, nrhs: int = 1, stream=None):
@@ -218,6 +291,7 @@ class PrecondOptions:
     precision: str = "fp64"
     transpose: bool = False
     ordering: str = "rcm"
+    coarse: str = "none"
 
     def to_c(self):
         o = _capi.PrecondOpts()
@@ -230,6 +304,7 @@ class PrecondOptions:
         o.precision = PRECISION[self.precision]
         o.transpose = int(bool(self.transpose))
         o.ordering = ORDERING[self.ordering]
+        o.coarse = COARSE[self.coarse]
         return o
 
 
@@ -297,6 +372,10 @@ class SolveOptions:
     inner_rtol: float = 1e-4
     stagnation_cycles: int = 50
     profile: bool = False
+    # operator algebra: solve P(L) u = f with P(L) = sum_k poly[k] L^k (empty: A u = f)
+    poly: tuple = ()
+    # preconditioner applications per step (2 with the (O)RAS of A(sqrt(c0)) for c0 + L^2)
+    pc_power: int = 1
 
     def to_c(self):
         o = _capi.SolveOpts()
@@ -310,6 +389,13 @@ class SolveOptions:
         o.inner_rtol = float(self.inner_rtol)
         o.stagnation_cycles = int(self.stagnation_cycles)
         o.profile = int(bool(self.profile))
+        coef = [float(a) for a in self.poly]
+        if len(coef) > 5:
+            raise ValueError("at most 5 polynomial coefficients (degree 4)")
+        o.poly_n = len(coef)
+        for k, a in enumerate(coef):
+            o.poly_coef[k] = a
+        o.pc_power = int(self.pc_power)
         return o
 
 

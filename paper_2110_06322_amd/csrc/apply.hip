@@ -98,11 +98,23 @@ __device__ __forceinline__ void lagrange(double s, double* w) {
   else if (P == 2) {
     double a = s, b = s - 1.0, c = s - 2.0;
     w[0] = 0.5 * b * c; w[1] = -a * c; w[2] = 0.5 * a * b;
-  } else {
+  } else if (P == 3) {
     double a = s, b = s - 1.0, c = s - 2.0, e = s - 3.0;
     const double i6 = 1.0 / 6.0;
     w[0] = -i6 * (b * c) * e; w[1] = 0.5 * (a * c) * e;
     w[2] = -0.5 * (a * b) * e; w[3] = i6 * (a * b) * c;
+  } else if (P == 4) {
+    const double a = s, b = s - 1.0, c = s - 2.0, d = s - 3.0, e = s - 4.0;
+    const double i24 = 1.0 / 24.0, i6 = 1.0 / 6.0;
+    w[0] = i24 * ((b * c) * (d * e)); w[1] = -i6 * ((a * c) * (d * e));
+    w[2] = 0.25 * ((a * b) * (d * e)); w[3] = -i6 * ((a * b) * (c * e));
+    w[4] = i24 * ((a * b) * (c * d));
+  } else {
+    const double a = s, b = s - 1.0, c = s - 2.0, d = s - 3.0, e = s - 4.0, f = s - 5.0;
+    const double i120 = 1.0 / 120.0, i24 = 1.0 / 24.0, i12 = 1.0 / 12.0;
+    w[0] = -i120 * (((b * c) * (d * e)) * f); w[1] = i24 * (((a * c) * (d * e)) * f);
+    w[2] = -i12 * (((a * b) * (d * e)) * f); w[3] = i12 * (((a * b) * (c * e)) * f);
+    w[4] = -i24 * (((a * b) * (c * d)) * f); w[5] = i120 * (((a * b) * (c * d)) * e);
   }
 }
 
@@ -250,6 +262,7 @@ __global__ void __launch_bounds__(256) k_extend(DevInst I, const double* __restr
   double cp[3], out[1];
   load_tcp<D>(I, j, cp);
   erow_global<D, P, 1>(I, cp, u, out);
+  if (I.esgn) out[0] *= I.esgn[j];
   v[j] = out[0];
 }
 
@@ -313,16 +326,18 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
 
   // jobs of this thread (at most two: a tile has at most 2^d*64 band nodes plus its face halo)
   int slot0 = -1, slot1 = -1;
-  double cp0[3] = {0, 0, 0}, cp1[3] = {0, 0, 0};
+  double cp0[3] = {0, 0, 0}, cp1[3] = {0, 0, 0}, sg0 = 1.0, sg1 = 1.0;
   if (tid < nj) {
     const Job j = jl[tid];
     slot0 = j.slot;
     load_tcp<D>(I, j.node, cp0);
+    if (I.esgn) sg0 = I.esgn[j.node];
   }
   if (tid + NT < nj) {
     const Job j = jl[tid + NT];
     slot1 = j.slot;
     load_tcp<D>(I, j.node, cp1);
+    if (I.esgn) sg1 = I.esgn[j.node];
   }
   // stencil row of this thread: wavefront = tile brick, lane = node
   uint64_t mS = 0;
@@ -367,8 +382,16 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
     }
     __syncthreads();
     // ---- D. extension rows
-    if (slot0 >= 0) V[slot0] = erow_lds<D, P>(cp0, U, s0, s1, fbase);
-    if (slot1 >= 0) V[slot1] = erow_lds<D, P>(cp1, U, s0, s1, fbase);
+    if (slot0 >= 0) {
+      double e = erow_lds<D, P>(cp0, U, s0, s1, fbase);
+      if (I.esgn) e *= sg0;
+      V[slot0] = e;
+    }
+    if (slot1 >= 0) {
+      double e = erow_lds<D, P>(cp1, U, s0, s1, fbase);
+      if (I.esgn) e *= sg1;
+      V[slot1] = e;
+    }
     __syncthreads();
     // ---- E. stencil
     if (has_row) yb[(int64_t)row * NRHS + r] = stencil_row<D>(V, vi, I.diag, I.inv_h2, xi[r]);
@@ -443,20 +466,25 @@ struct PipeList {
 // no scalar loads
 struct InstView {
   const double* tcp;
+  const double* esgn;       // extension-row signs, or null
   const Job* jobs;
   const FootBrick* fbrec;
-  int64_t vec_off;
+  int64_t vec_off;          // offset of the output (y, or extension values in the two-pass kernel)
+  int64_t xoff;             // offset of x
   double diag, inv_h2;
   int ntot, inst;
 };
 
+template <bool TWO = false>
 __device__ __forceinline__ void inst_refresh(InstView& v, const DevInst* __restrict__ insts, int i) {
   if (i == v.inst) return;
   const DevInst& I = insts[i];
   v.tcp = I.tcp;
-  v.jobs = I.jobs;
-  v.fbrec = I.fbrec;
-  v.vec_off = I.vec_off;
+  v.esgn = I.esgn;
+  v.jobs = TWO ? I.jobsE : I.jobs;
+  v.fbrec = TWO ? I.fbrecE : I.fbrec;
+  v.vec_off = TWO ? I.vnode_off : I.vec_off;
+  v.xoff = I.vec_off;
   v.diag = I.diag;
   v.inv_h2 = I.inv_h2;
   v.ntot = I.nA + I.nG;
@@ -502,7 +530,7 @@ template <int D>
 __device__ __forceinline__ void pipe_data(const InstView& I, const PipeRec& R, const PipeList& L,
                                           const double* __restrict__ x, const int* l, int wave, int lane,
                                           PipeData<D>& Dt) {
-  const double* xb = x + I.vec_off;
+  const double* xb = x + I.xoff;
 #pragma unroll
   for (int k = 0; k < 3; ++k) Dt.t0[k] = 0.0;
   if (L.slot0 >= 0) view_tcp<D>(I, L.node0, Dt.t0);
@@ -527,7 +555,11 @@ __device__ __forceinline__ void pipe_data(const InstView& I, const PipeRec& R, c
   if ((R.mA >> lane) & 1ull) Dt.xi = xb[R.oA + mbcnt64(R.mA)];
 }
 
-template <int D, int P>
+// TWO = true: the extension pass of the two-pass apply. The jobs are the tile's
+// own band nodes (no face halo), each extension row goes to y[vnode_off + node]
+// (the scratch vector of extension values) and the work-ordered tile copies
+// carry no Sigma_A masks, so the stencil stage is empty.
+template <int D, int P, bool TWO>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_apply_pipe(const DevInst* __restrict__ insts,
                                                     const DevTile* __restrict__ wtiles,
                                                     const PipeSpan* __restrict__ plan, int ucap,
@@ -560,19 +592,19 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
   InstView V0, V1, V2;   // instance views of the stencil, data and list stages
   V0.inst = V1.inst = V2.inst = -1;
   PipeRec R0 = pipe_unpack<D>(pipe_rec_raw(wtiles, w, lane), wave, gate);
-  inst_refresh(V1, insts, R0.inst);
+  inst_refresh<TWO>(V1, insts, R0.inst);
   PipeList L0 = pipe_list<D>(V1, R0, tid, wave, lane);
   PipeData<D> D0;
   pipe_data<D>(V1, R0, L0, x, l, wave, lane, D0);
   const bool v1 = w + per < w_end, v2 = w + 2 * per < w_end;
   PipeRec R1 = v1 ? pipe_unpack<D>(pipe_rec_raw(wtiles, w + per, lane), wave, gate) : R0;
-  inst_refresh(V2, insts, R1.inst);
+  inst_refresh<TWO>(V2, insts, R1.inst);
   PipeList L1 = v1 ? pipe_list<D>(V2, R1, tid, wave, lane) : L0;
   uint32_t W2 = v2 ? pipe_rec_raw(wtiles, w + 2 * per, lane) : 0u;
 
 #pragma unroll 1
   for (; w < w_end; w += per) {
-    inst_refresh(V0, insts, R0.inst);
+    inst_refresh<TWO>(V0, insts, R0.inst);
     const InstView& I = V0;
     // ---- stage this tile's footprint of x
 #pragma unroll
@@ -584,29 +616,37 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     const double diag = I.diag, inv_h2 = I.inv_h2;
     double* yb = y + I.vec_off;
     const int s0 = R0.s0, s1 = R0.s1, fbase = R0.fbase;
-    const int slot0 = L0.slot0, slot1 = L0.slot1, node1 = L0.node1;
+    const int slot0 = L0.slot0, slot1 = L0.slot1, node0 = L0.node0, node1 = L0.node1;
     double t0[3] = {D0.t0[0], D0.t0[1], D0.t0[2]};
     __syncthreads();
     // ---- next tiles' loads: data of w+per, lists of w+2per, record of w+3per
     const bool n1 = w + per < w_end, n2 = w + 2 * per < w_end, n3 = w + 3 * per < w_end;
     if (n1) {
-      inst_refresh(V1, insts, R1.inst);
+      inst_refresh<TWO>(V1, insts, R1.inst);
       pipe_data<D>(V1, R1, L1, x, l, wave, lane, D0);
     }
     PipeRec R2 = R1;
     PipeList L2 = L1;
     if (n2) {
       R2 = pipe_unpack<D>(W2, wave, gate);
-      inst_refresh(V2, insts, R2.inst);
+      inst_refresh<TWO>(V2, insts, R2.inst);
       L2 = pipe_list<D>(V2, R2, tid, wave, lane);
     }
     const uint32_t W3 = n3 ? pipe_rec_raw(wtiles, w + 3 * per, lane) : 0u;
     // ---- extension rows of this tile
-    if (slot0 >= 0) V[slot0] = erow_lds<D, P>(t0, U, s0, s1, fbase);
+    if (slot0 >= 0) {
+      double e = erow_lds<D, P>(t0, U, s0, s1, fbase);
+      if (I.esgn) e *= I.esgn[node0];
+      if constexpr (TWO) yb[node0] = e;
+      else V[slot0] = e;
+    }
     if (slot1 >= 0) {
       double t1[3];
       view_tcp<D>(I, node1, t1);
-      V[slot1] = erow_lds<D, P>(t1, U, s0, s1, fbase);
+      double e = erow_lds<D, P>(t1, U, s0, s1, fbase);
+      if (I.esgn) e *= I.esgn[node1];
+      if constexpr (TWO) yb[node1] = e;
+      else V[slot1] = e;
     }
     __syncthreads();
     // ---- stencil
@@ -642,21 +682,37 @@ __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restric
     int g[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < D; ++k) g[k] = tile.origin[k] + sub[k] * E + l[k];
+    // neighbour sum in the fused kernel's order: (x- + x+), then + (y- + y+), then + (z- + z+)
     double s[NRHS];
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) s[r] = 0.0;
-    for (int k = 0; k < D; ++k)
+    for (int k = 0; k < D; ++k) {
+      double pr[NRHS];
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) pr[r] = 0.0;
       for (int sd = -1; sd <= 1; sd += 2) {
         int gn[3] = {g[0], g[1], g[2]};
         gn[k] += sd;
         int j = node_at<D>(I, gn);
-        if (j < 0) continue;  // cannot happen on a closed band
-        double cp[3], out[NRHS];
-        load_tcp<D>(I, j, cp);
-        erow_global<D, P, NRHS>(I, cp, x, out);
+        double out[NRHS];
 #pragma unroll
-        for (int r = 0; r < NRHS; ++r) s[r] += out[r];
+        for (int r = 0; r < NRHS; ++r) out[r] = 0.0;
+        if (j >= 0) {  // always on a closed band
+          double cp[3];
+          load_tcp<D>(I, j, cp);
+          erow_global<D, P, NRHS>(I, cp, x, out);
+          if (I.esgn) {
+            const double sgn = I.esgn[j];
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r) out[r] *= sgn;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) pr[r] = sd < 0 ? out[r] : pr[r] + out[r];
       }
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) s[r] = k == 0 ? pr[r] : s[r] + pr[r];
+    }
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) {
       const int64_t e = (I.vec_off + i) * NRHS + r;
@@ -665,87 +721,313 @@ __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restric
   }
 }
 
-// ---- transpose: z = O^T y over Sigma_A u Sigma_G
+// Extension pass of the two-pass apply for tiles whose footprint exceeds the LDS
+// budget: each node of the tile's bricks evaluates its extension row with index
+// lookups into the global vector (wavefront = brick, lane = node).
+template <int D, int P>
+__global__ void __launch_bounds__(512) k_extend_tiles(const DevInst* __restrict__ insts,
+                                                      const WorkItem* __restrict__ work, int nwork,
+                                                      const double* __restrict__ x, double* __restrict__ v,
+                                                      Gate gate) {
+  const int w = blockIdx.x;
+  if (w >= nwork) return;
+  const WorkItem wi = work[w];
+  if (gate_skip(gate, wi.inst)) return;
+  const DevInst& I = insts[wi.inst];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
+  if (wave >= (1 << D)) return;
+  const int id = I.tiles[wi.idx].bid[wave];
+  if (id < 0) return;
+  const uint64_t mA = I.maskA[id], mG = I.maskG[id];
+  int node = -1;
+  if ((mA >> lane) & 1ull) node = I.offA[id] + mbcnt64(mA);
+  else if ((mG >> lane) & 1ull) node = I.nA + I.offG[id] + mbcnt64(mG);
+  if (node < 0) return;
+  double cp[3], out[1];
+  load_tcp<D>(I, node, cp);
+  erow_global<D, P, 1>(I, cp, x, out);
+  if (I.esgn) out[0] *= I.esgn[node];
+  v[I.vnode_off + node] = out[0];
+}
+
+// Stencil pass of the two-pass apply: y_i = (c + 2d/h^2) x_i - h^-2 sum_n v_n
+// with v the extension values of Sigma_A u Sigma_G written by the extension
+// pass. One workgroup per tile with active nodes, one wavefront per brick,
+// lane = node. A node's grid neighbours lie in its own brick or in the brick
+// across one face; the masks and offsets of those 2d + 1 bricks are uniform
+// over the wavefront (scalar loads), so a neighbour's index is a popcount.
+// The sum is formed in the fused kernel's order (x pair, y pair, z pair).
+template <int D>
+__global__ void __launch_bounds__(512) k_stencil(const DevInst* __restrict__ insts, const WorkItem* __restrict__ work,
+                                                 int nwork, const double* __restrict__ v, const double* __restrict__ x,
+                                                 double* __restrict__ y, Gate gate) {
+  constexpr int E = kEdge<D>;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  if (w >= nwork) return;
+  const WorkItem wi = work[w];
+  if (gate_skip(gate, wi.inst)) return;
+  const DevInst& I = insts[wi.inst];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
+  if (wave >= (1 << D)) return;
+  const DevTile& tile = I.tiles[wi.idx];
+  const uint64_t mA = tile.mA[wave];
+  if (!((mA >> lane) & 1ull)) return;
+  const int id = tile.bid[wave];
+  const int row = tile.oA[wave] + mbcnt64(mA);
+  int l[3];
+  local_of<D>(lane, l);
+  const double* vb = v + I.vnode_off;
+  double nb[2 * D];
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      int ln[3] = {l[0], l[1], l[2]};
+      ln[k] += s ? 1 : -1;
+      int b = id;
+      if (ln[k] < 0 || ln[k] >= E) {
+        b = I.bnbr[id * 2 * D + 2 * k + s];
+        ln[k] = (ln[k] + E) & (E - 1);
+      }
+      const int bit = bit_of<D>(ln[0], ln[1], ln[2]);
+      const uint64_t ma = I.maskA[b];
+      int j;
+      if ((ma >> bit) & 1ull) j = I.offA[b] + popc_below(ma, bit);
+      else j = I.nA + I.offG[b] + popc_below(I.maskG[b], bit);
+      nb[2 * k + s] = vb[j];
+    }
+  double sum = nb[0] + nb[1];
+  sum += nb[2] + nb[3];
+  if (D == 3) sum += nb[4] + nb[5];
+  const int64_t e = I.vec_off + row;
+  y[e] = I.diag * x[e] - I.inv_h2 * sum;
+}
+
+// ---- transpose: z = O^T y over Sigma_A u Sigma_G (z_j = sum of y over the active grid
+// neighbours of node j, in the order -x, +x, -y, +y, -z, +z). One wavefront per brick; a
+// neighbour lies in the node's brick or in the brick across one face.
 template <int D, int NRHS>
 __global__ void __launch_bounds__(256) k_OT(DevInst I, const double* __restrict__ y, double* __restrict__ z,
                                             Gate gate, int inst) {
+  constexpr int E = kEdge<D>;
   if (gate_skip(gate, inst)) return;
   const int id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (id >= I.nbricks) return;
   const int lane = lane_id();
-  uint64_t mA = I.maskA[id], mG = I.maskG[id];
+  const uint64_t mA = I.maskA[id], mG = I.maskG[id];
   if (!(((mA | mG) >> lane) & 1ull)) return;
-  int j = ((mA >> lane) & 1ull) ? I.offA[id] + mbcnt64(mA) : I.nA + I.offG[id] + mbcnt64(mG);
+  const int j = ((mA >> lane) & 1ull) ? I.offA[id] + mbcnt64(mA) : I.nA + I.offG[id] + mbcnt64(mG);
   int l[3];
   local_of<D>(lane, l);
-  int g[3] = {0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < D; ++k) g[k] = I.bcoord[id * 3 + k] * kEdge<D> + l[k];
   double s[NRHS];
 #pragma unroll
   for (int r = 0; r < NRHS; ++r) s[r] = 0.0;
-  for (int k = 0; k < D; ++k)
-    for (int sd = -1; sd <= 1; sd += 2) {
-      int gn[3] = {g[0], g[1], g[2]};
-      gn[k] += sd;
-      int n = node_at<D>(I, gn);
-      if (n >= 0 && n < I.nA) {
 #pragma unroll
-        for (int r = 0; r < NRHS; ++r) s[r] += y[(I.vec_off + n) * NRHS + r];
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      int ln[3] = {l[0], l[1], l[2]};
+      ln[k] += sd ? 1 : -1;
+      int b = id;
+      if (ln[k] < 0 || ln[k] >= E) {
+        b = I.bnbr[id * 2 * D + 2 * k + sd];
+        ln[k] = (ln[k] + E) & (E - 1);
       }
+      if (b < 0) continue;
+      const int bit = bit_of<D>(ln[0], ln[1], ln[2]);
+      const uint64_t ma = I.maskA[b];
+      if (!((ma >> bit) & 1ull)) continue;
+      const int64_t n = I.vec_off + I.offA[b] + popc_below(ma, bit);
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) s[r] += y[n * NRHS + r];
     }
 #pragma unroll
   for (int r = 0; r < NRHS; ++r) z[(int64_t)j * NRHS + r] = s[r];
 }
 
-// ---- transpose: y_out = diag y - h^-2 E^T z, each output gathers the rows whose cube holds it
+// ---- transpose: y_out = diag y - h^-2 E^T z. One wavefront per brick with active nodes,
+// a lane per node of the brick. The extension rows whose interpolation cube overlaps the
+// brick (a list in ascending row order) are staged 64 at a time in LDS: cube corner
+// relative to the brick, per-axis weights, and sign times z. Every lane then adds the
+// contributions of the staged rows whose cube holds its node, in list order; a row's
+// weights are computed once per overlapped brick instead of once per cube node.
 template <int D, int P, int NRHS>
-__global__ void __launch_bounds__(256) k_ET(DevInst I, const double* __restrict__ yin, const double* __restrict__ z,
-                                            double* __restrict__ yout, Gate gate, int inst) {
+__global__ void __launch_bounds__(64) k_ET(DevInst I, const double* __restrict__ yin, const double* __restrict__ z,
+                                           double* __restrict__ yout, Gate gate, int inst) {
+  constexpr int E = kEdge<D>, NW = D * (P + 1);
+  __shared__ int32_t s_rel[64];
+  __shared__ double s_w[64][NW];
+  __shared__ double s_z[64][NRHS];
   if (gate_skip(gate, inst)) return;
-  const int id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (id >= I.nbricks) return;
-  const int lane = lane_id();
-  uint64_t mA = I.maskA[id];
-  if (!((mA >> lane) & 1ull)) return;
-  const int k = I.offA[id] + mbcnt64(mA);
-  int l[3];
+  if ((int)blockIdx.x >= I.ntbricks) return;
+  const int id = I.tbricks[xcd_remap(blockIdx.x, gridDim.x)];   // neighbouring bricks share an XCD's L2
+  const int lane = threadIdx.x;
+  int l[3] = {0, 0, 0}, org[3] = {0, 0, 0};
   local_of<D>(lane, l);
-  int g[3] = {0, 0, 0};
 #pragma unroll
-  for (int a = 0; a < D; ++a) g[a] = I.bcoord[id * 3 + a] * kEdge<D> + l[a];
+  for (int k = 0; k < D; ++k) org[k] = I.bcoord[id * 3 + k] * E;
+  const uint64_t mA = I.maskA[id];
   double acc[NRHS];
 #pragma unroll
   for (int r = 0; r < NRHS; ++r) acc[r] = 0.0;
-  constexpr int NC = D == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1);
-  for (int c = 0; c < NC; ++c) {
-    int a[3] = {0, 0, 0};
-    int rem = c;
-    for (int q = D - 1; q >= 0; --q) { a[q] = rem % (P + 1); rem /= (P + 1); }
-    int gb[3] = {g[0] - a[0], g[1] - a[1], D == 3 ? g[2] - a[2] : 0};
-    int bnode = node_at<D>(I, gb);
-    if (bnode < 0 || bnode >= I.nA) continue;
-    for (int e = I.bucket_ptr[bnode]; e < I.bucket_ptr[bnode + 1]; ++e) {
-      int j = I.bucket_rows[e];
-      double cp[3];
-      load_tcp<D>(I, j, cp);
-      double wgt = 1.0;
+  const int rb = I.trow_ptr[id], re = I.trow_ptr[id + 1];
+  for (int c0 = rb; c0 < re; c0 += 64) {
+    const int nr = min(64, re - c0);
+    if (lane < nr) {
+      const int j = I.trows[c0 + lane];
+      double t[3];
+      load_tcp<D>(I, j, t);
+      int rel = 0;
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        double bf = floor(cp[q] - (P - 1) * 0.5);
-        double wl[P + 1];
-        lagrange<P>(cp[q] - bf, wl);
-        wgt *= wl[a[q]];
+      for (int k = 0; k < D; ++k) {
+        const double bf = floor(t[k] - (P - 1) * 0.5);
+        double w[P + 1];
+        lagrange<P>(t[k] - bf, w);
+#pragma unroll
+        for (int a = 0; a <= P; ++a) s_w[lane][k * (P + 1) + a] = w[a];
+        rel |= (((int)bf - org[k] + 16) & 0xff) << (8 * k);   // corner - origin in [-P, E-1], biased
       }
+      s_rel[lane] = rel;
+      const double sg = I.esgn ? I.esgn[j] : 1.0;
 #pragma unroll
-      for (int r = 0; r < NRHS; ++r) acc[r] += wgt * z[(int64_t)j * NRHS + r];
+      for (int r = 0; r < NRHS; ++r) s_z[lane][r] = sg * z[(int64_t)j * NRHS + r];
     }
+    __syncthreads();
+    for (int q = 0; q < nr; ++q) {
+      const int rel = s_rel[q];
+      int a[3] = {0, 0, 0};
+      bool in = true;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        a[k] = l[k] - (((rel >> (8 * k)) & 0xff) - 16);
+        in = in && a[k] >= 0 && a[k] <= P;
+      }
+      if (in) {
+        double w = s_w[q][a[0]];
+#pragma unroll
+        for (int k = 1; k < D; ++k) w *= s_w[q][k * (P + 1) + a[k]];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc[r] += w * s_z[q][r];
+      }
+    }
+    __syncthreads();
   }
+  if (!((mA >> lane) & 1ull)) return;
+  const int64_t row = I.vec_off + I.offA[id] + mbcnt64(mA);
 #pragma unroll
   for (int r = 0; r < NRHS; ++r) {
-    const int64_t e = (I.vec_off + k) * NRHS + r;
+    const int64_t e = row * NRHS + r;
     yout[e] = I.diag * yin[e] - I.inv_h2 * acc[r];
   }
+}
+
+// ---- two-kernel apply (fourth-order stencil, or interpolation degree 4 or 5).
+// Pass 1: v = E x at every node of Sigma_A u Sigma_G, R right-hand sides (signed rows of
+// open surfaces included); v is the instance's own scratch, indexed by node.
+template <int D, int P, int R>
+__global__ void __launch_bounds__(256) k_gen_extend(DevInst I, const double* __restrict__ x, double* __restrict__ v,
+                                                    Gate gate, int inst) {
+  if (gate_skip(gate, inst)) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= I.nA + I.nG) return;
+  double t[3], out[R];
+  load_tcp<D>(I, j, t);
+  erow_global<D, P, R>(I, t, x, out);
+  const double sg = I.esgn ? I.esgn[j] : 1.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[(int64_t)j * R + r] = sg * out[r];
+}
+
+// Pass 2: y = diag x - w (sum of the stencil's extension values), one wavefront per brick
+// with active nodes. Order 2: w = 1/h^2, the six (four) nearest neighbours, summed in
+// pairs per axis. Order 4: w = 1/(12h^2), 16 times the nearest pairs' sum minus the sum of
+// the pairs two steps away. A neighbour lies in the node's brick or the one across a face
+// (bricks are at least 4 nodes wide).
+template <int D, int R, int ORDER>
+__global__ void __launch_bounds__(256) k_gen_stencil(DevInst I, const double* __restrict__ v,
+                                                     const double* __restrict__ x, double* __restrict__ y,
+                                                     Gate gate, int inst) {
+  constexpr int E = kEdge<D>;
+  if (gate_skip(gate, inst)) return;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= I.ntbricks) return;
+  const int id = I.tbricks[w];
+  const int lane = lane_id();
+  const uint64_t mA = I.maskA[id];
+  if (!((mA >> lane) & 1ull)) return;
+  int l[3];
+  local_of<D>(lane, l);
+  double s1[R], s2[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) { s1[r] = 0.0; s2[r] = 0.0; }
+#pragma unroll
+  for (int step = 1; step <= ORDER / 2; ++step)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double pr[2][R];
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        int ln[3] = {l[0], l[1], l[2]};
+        ln[k] += sd ? step : -step;
+        int b = id;
+        if (ln[k] < 0 || ln[k] >= E) {
+          b = I.bnbr[id * 2 * D + 2 * k + sd];
+          ln[k] = (ln[k] + E) & (E - 1);
+        }
+        int j = -1;
+        if (b >= 0) {
+          const int bit = bit_of<D>(ln[0], ln[1], ln[2]);
+          const uint64_t ma = I.maskA[b], mg = I.maskG[b];
+          if ((ma >> bit) & 1ull) j = I.offA[b] + popc_below(ma, bit);
+          else if ((mg >> bit) & 1ull) j = I.nA + I.offG[b] + popc_below(mg, bit);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) pr[sd][r] = j >= 0 ? v[(int64_t)j * R + r] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double q = pr[0][r] + pr[1][r];
+        if (step == 1) s1[r] += q;
+        else s2[r] += q;
+      }
+    }
+  const int64_t row = I.vec_off + I.offA[id] + mbcnt64(mA);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double sum = ORDER == 2 ? s1[r] : 16.0 * s1[r] - s2[r];
+    const int64_t e = row * R + r;
+    y[e] = I.diag * x[e] - I.inv_h2 * sum;
+  }
+}
+
+template <int D, int P, int R>
+static hipError_t launch_generic_t(const GenericPlan& G, const double* x, double* y, hipStream_t s,
+                                   const Gate& gate) {
+  for (int i = 0; i < G.ninst; ++i) {
+    const DevInst& I = G.inst[i];
+    const int n = I.nA + I.nG;
+    if (n == 0 || I.ntbricks == 0) continue;
+    double* v = G.vscr + G.voff[i] * R;
+    hipLaunchKernelGGL((k_gen_extend<D, P, R>), dim3((n + 255) / 256), dim3(256), 0, s, I, x, v, gate, i);
+    if (I.order == 4)
+      hipLaunchKernelGGL((k_gen_stencil<D, R, 4>), dim3((I.ntbricks + 3) / 4), dim3(256), 0, s, I, v, x, y, gate, i);
+    else
+      hipLaunchKernelGGL((k_gen_stencil<D, R, 2>), dim3((I.ntbricks + 3) / 4), dim3(256), 0, s, I, v, x, y, gate, i);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_generic(const GenericPlan& G, int d, int p, int nrhs, const double* x, double* y,
+                                 hipStream_t s, const Gate& gate) {
+  if (!G.vscr || !G.inst || !G.voff) return hipErrorInvalidValue;
+#define CPM_CASE(D, P, R) \
+  if (d == D && p == P && nrhs == R) return launch_generic_t<D, P, R>(G, x, y, s, gate);
+#define CPM_CASES(D, P) CPM_CASE(D, P, 1) CPM_CASE(D, P, 2) CPM_CASE(D, P, 4)
+  CPM_CASES(3, 1) CPM_CASES(3, 2) CPM_CASES(3, 3) CPM_CASES(3, 4) CPM_CASES(3, 5)
+  CPM_CASES(2, 1) CPM_CASES(2, 2) CPM_CASES(2, 3) CPM_CASES(2, 4) CPM_CASES(2, 5)
+#undef CPM_CASES
+#undef CPM_CASE
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------- launchers
@@ -779,31 +1061,47 @@ static int pipe_grid(int nwork, size_t shm, const void* kern) {
 }
 
 template <int D, int P, int NRHS>
-static hipError_t launch_apply_t(int variant, const DevInst* insts, const WorkItem* work, const PipeWork& pw,
-                                 int nwork, int ucap, const WorkItem* fb, int nfb, const double* x, double* y,
-                                 hipStream_t s, const Gate& gate) {
-  if (nwork > 0) {
-    const size_t shm = (size_t)ucap * sizeof(double) + tile_lds_extra<D>();
+static hipError_t launch_apply_t(const ApplyArgs& A, int variant, const double* x, double* y, hipStream_t s,
+                                 const Gate& gate) {
+  if (NRHS == 1 && variant == kApplyTwoPass) {
+    // extension rows of every band node into the scratch vector, then the stencil
+    if (!A.twopass || !A.vscr || (A.pipeE.nplan > 0 && (!A.pipeE.wtiles || !A.pipeE.plan))) return hipErrorInvalidValue;
+    const size_t shmE = (size_t)A.ucapE * sizeof(double);
+    if (A.pipeE.nplan > 0)
+      hipLaunchKernelGGL((k_apply_pipe<D, P, true>), dim3(A.pipeE.nplan), dim3(512), shmE, s, A.insts, A.pipeE.wtiles,
+                         A.pipeE.plan, A.ucapE, x, A.vscr, gate);
+    if (A.nfbE > 0)
+      hipLaunchKernelGGL((k_extend_tiles<D, P>), dim3(A.nfbE), dim3(512), 0, s, A.insts, A.fbE, A.nfbE, x, A.vscr,
+                         gate);
+    if (A.nswork > 0)
+      hipLaunchKernelGGL((k_stencil<D>), dim3(A.nswork), dim3(512), 0, s, A.insts, A.swork, A.nswork, A.vscr, x, y,
+                         gate);
+    return hipGetLastError();
+  }
+  if (A.nwork > 0) {
+    const size_t shm = (size_t)A.ucap * sizeof(double) + tile_lds_extra<D>();
     if (NRHS == 1 && variant == kApplyPipelined) {
-      if (!pw.wtiles || !pw.plan || pw.nplan <= 0) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_apply_pipe<D, P>), dim3(pw.nplan), dim3(512), shm, s, insts, pw.wtiles, pw.plan, ucap, x,
-                         y, gate);
+      if (!A.pipe.wtiles || !A.pipe.plan || A.pipe.nplan <= 0) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_apply_pipe<D, P, false>), dim3(A.pipe.nplan), dim3(512), shm, s, A.insts, A.pipe.wtiles,
+                         A.pipe.plan, A.ucap, x, y, gate);
     } else {
-      hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(nwork), dim3(512), shm, s, insts, work, nwork, ucap, x,
-                         y, gate);
+      hipLaunchKernelGGL((k_apply_tile<D, P, NRHS>), dim3(A.nwork), dim3(512), shm, s, A.insts, A.work, A.nwork,
+                         A.ucap, x, y, gate);
     }
   }
-  if (nfb > 0)
-    hipLaunchKernelGGL((k_apply_fallback<D, P, NRHS>), dim3(nfb), dim3(256), 0, s, insts, fb, nfb, x, y, gate);
+  if (A.nfb > 0)
+    hipLaunchKernelGGL((k_apply_fallback<D, P, NRHS>), dim3(A.nfb), dim3(256), 0, s, A.insts, A.fb, A.nfb, x, y,
+                       gate);
   return hipGetLastError();
 }
 
-hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* insts, const WorkItem* work,
-                        const PipeWork& pw, int nwork, int ucap, const WorkItem* fb, int nfb, const double* x,
-                        double* y, hipStream_t s, const Gate& gate) {
+hipError_t launch_apply(const ApplyArgs& A, int nrhs, int variant, const double* x, double* y, hipStream_t s,
+                        const Gate& gate) {
+  const int d = A.d, p = A.p;
+  if (A.gen) return launch_generic(*A.gen, d, p, nrhs, x, y, s, gate);
 #define CPM_CASE(D, P, R) \
   if (d == D && p == P && nrhs == R)                                                              \
-    return launch_apply_t<D, P, R>(variant, insts, work, pw, nwork, ucap, fb, nfb, x, y, s, gate);
+    return launch_apply_t<D, P, R>(A, variant, x, y, s, gate);
   CPM_CASE(3, 3, 1) CPM_CASE(3, 3, 2) CPM_CASE(3, 3, 4)
   CPM_CASE(3, 2, 1) CPM_CASE(3, 2, 2) CPM_CASE(3, 2, 4)
   CPM_CASE(3, 1, 1) CPM_CASE(3, 1, 2) CPM_CASE(3, 1, 4)
@@ -814,10 +1112,12 @@ hipError_t launch_apply(int d, int p, int nrhs, int variant, const DevInst* inst
   return hipErrorInvalidValue;
 }
 
-int apply_pipe_grid(int d, int p, int nwork, int ucap) {
+int apply_pipe_grid(int d, int p, int nwork, int ucap, bool extension_pass) {
 #define CPM_CASE(D, P)                                                                             \
   if (d == D && p == P)                                                                            \
-    return pipe_grid(nwork, (size_t)ucap * sizeof(double) + tile_lds_extra<D>(), (const void*)k_apply_pipe<D, P>);
+    return extension_pass ? pipe_grid(nwork, (size_t)ucap * sizeof(double), (const void*)k_apply_pipe<D, P, true>) \
+                          : pipe_grid(nwork, (size_t)ucap * sizeof(double) + tile_lds_extra<D>(),          \
+                                      (const void*)k_apply_pipe<D, P, false>);
   CPM_CASE(3, 3) CPM_CASE(3, 2) CPM_CASE(3, 1) CPM_CASE(2, 3) CPM_CASE(2, 2) CPM_CASE(2, 1)
 #undef CPM_CASE
   return 0;
@@ -829,7 +1129,8 @@ hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream
   dim3 g((n + 255) / 256), b(256);
 #define CPM_CASE(D, P) \
   if (I.d == D && I.p == P) { hipLaunchKernelGGL((k_extend<D, P>), g, b, 0, s, I, u, v); return hipGetLastError(); }
-  CPM_CASE(3, 3) CPM_CASE(3, 2) CPM_CASE(3, 1) CPM_CASE(2, 3) CPM_CASE(2, 2) CPM_CASE(2, 1)
+  CPM_CASE(3, 5) CPM_CASE(3, 4) CPM_CASE(3, 3) CPM_CASE(3, 2) CPM_CASE(3, 1)
+  CPM_CASE(2, 5) CPM_CASE(2, 4) CPM_CASE(2, 3) CPM_CASE(2, 2) CPM_CASE(2, 1)
 #undef CPM_CASE
   return hipErrorInvalidValue;
 }
@@ -837,9 +1138,11 @@ hipError_t launch_extend(const DevInst& I, const double* u, double* v, hipStream
 template <int D, int P, int NRHS>
 static hipError_t launch_apply_T_t(const DevInst& I, const double* x, double* z, double* y, hipStream_t s,
                                    const Gate& gate, int inst) {
+  if (!I.bnbr || !I.trow_ptr || !I.trows || !I.tbricks) return hipErrorInvalidValue;
   dim3 g((I.nbricks + 3) / 4), b(256);
   hipLaunchKernelGGL((k_OT<D, NRHS>), g, b, 0, s, I, x, z, gate, inst);
-  hipLaunchKernelGGL((k_ET<D, P, NRHS>), g, b, 0, s, I, x, z, y, gate, inst);
+  if (I.ntbricks > 0)
+    hipLaunchKernelGGL((k_ET<D, P, NRHS>), dim3(I.ntbricks), dim3(64), 0, s, I, x, z, y, gate, inst);
   return hipGetLastError();
 }
 

@@ -24,3 +24,15 @@ int32_t cpm_device_count(void) {
   if (hipGetDeviceCount(&n) != hipSuccess) return 0;
   return n;
 }
+
+int64_t cpm_abi_sizeof(int32_t which) {
+  switch (which) {
+    case 0: return (int64_t)sizeof(cpm_solve_opts);
+    case 1: return (int64_t)sizeof(cpm_solve_stats);
+    case 2: return (int64_t)sizeof(cpm_precond_opts);
+    case 3: return (int64_t)sizeof(cpm_tune_result);
+    case 4: return (int64_t)sizeof(cpm_imex_opts);
+    case 5: return (int64_t)sizeof(cpm_band_info);
+    default: return -1;
+  }
+}

@@ -272,6 +272,7 @@ cpm_status cpm_imex_step(cpm_imex* im, double t, double* const* w, int32_t nstep
     for (int sp = 0; sp < M.ns; ++sp)
       if (!w[sp] && M.n) fail(CPM_ERR_ARG, "null state vector");
     if (sopts->transpose) fail(CPM_ERR_ARG, "stage solves are not transposed");
+    if (sopts->poly_n != 0) fail(CPM_ERR_ARG, "stage solves use the shifted operator itself (poly_n = 0)");
     hipStream_t s = (hipStream_t)stream;
     std::vector<cpm_solve_stats> acc(M.ns);
     for (auto& a : acc) {

@@ -37,6 +37,7 @@ void closest_point(const Surface& s, int d, const double* x, double* cp);
 // The band as built on the host (node order: Sigma_A bricks, then Sigma_G bricks).
 struct cpm_band_s {
   int d = 3, p = 3;
+  int reach = 1;                 // the ghost set holds the nodes within `reach` steps along an axis of Sigma_A
   double h = 0, gamma = 0;
   double lo[3] = {0, 0, 0};
   int32_t shape[3] = {1, 1, 1};
@@ -52,6 +53,11 @@ struct cpm_band_s {
   // per node (Sigma_A then Sigma_G): grid index and closest point, [node][axis]
   std::vector<int32_t> gidx;
   std::vector<double> cp;
+  // extension rows interpolate at ip with sign sgn: ip = cp and sign +1, except on open
+  // surfaces for nodes whose closest point lies on a Dirichlet boundary (ip = cp of the
+  // mirror image 2 cp - x, sign -1); sgn is empty when every sign is +1
+  std::vector<double> ip;
+  std::vector<double> sgn;
   int64_t nodes() const { return nA + nG; }
   int64_t nbricks() const { return (int64_t)maskA.size(); }
   // node index of grid point g (global index: Sigma_A then Sigma_G), -1 if absent

@@ -46,6 +46,7 @@ cpm_status cpm_apply_T_noalloc(const cpm_operator* op, const double* x, double* 
     if (!op || !x || !y) fail(CPM_ERR_ARG, "null argument");
     if (nrhs != 1 && nrhs != 2 && nrhs != 4) fail(CPM_ERR_ARG, "nrhs must be 1, 2 or 4");
     if (x == y) fail(CPM_ERR_ARG, "x and y must not alias");
+    if (op->generic) fail(CPM_ERR_ARG, "the transposed apply needs a second-order operator with p <= 3");
     const size_t need = (size_t)op->band->nodes() * (size_t)nrhs;
     if (need > kNoAllocScratchDoubles)
       fail(CPM_ERR_ARG, "cpm_apply_T_noalloc: (N_A + N_G) * nrhs = " + std::to_string(need) +

@@ -1,5 +1,6 @@
-// Operator setup: tiles and LDS footprints for the fused apply, extension-row
-// buckets for the atomic-free transpose, upload of the band to the device.
+// Operator setup: tiles and LDS footprints for the fused apply, per-brick
+// extension-row lists for the atomic-free transpose, upload of the band to the
+// device.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -30,8 +31,10 @@ void local_of(int d, int bit, int* l) {
 // boundary nodes, each with its slot in the tile's LDS box), the bounding box
 // of their interpolation cubes (the LDS footprint) and the Sigma_A bricks
 // overlapping that footprint.
+// halo = false: the extension pass of the two-pass apply (jobs are the tile's own
+// band nodes only; their slots are unused).
 void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<int32_t>& fvol,
-                 std::vector<FootBrick>& fbrec, std::vector<Job>& jobs) {
+                 std::vector<FootBrick>& fbrec, std::vector<Job>& jobs, bool halo = true) {
   bool orphan = false;
   const int d = B.d, E = brick_edge(d), T = 2 * E, P = B.p, W = T + 2;
   const int64_t nb = B.nbricks();
@@ -55,13 +58,13 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t t = 0; t < nt; ++t) {
     DevTile& tl = tiles[t];
-    for (int q = 0; q < 8; ++q) { tl.oA[q] = 0; tl.mA[q] = 0; }
+    for (int q = 0; q < 8; ++q) { tl.oA[q] = 0; tl.mA[q] = 0; tl.bid[q] = -1; }
     for (int k = 0; k < 3; ++k) tl.origin[k] = 0;
     for (int k = 0; k < d; ++k) tl.origin[k] = (B.bcoord[start[t] * 3 + k] >> 1) * T;
     int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
     auto add_job = [&](int64_t node, const int* l) {
       int32_t b[3];
-      base_of(B, &B.cp[node * d], b);
+      base_of(B, &B.ip[node * d], b);
       for (int k = 0; k < d; ++k) { lo[k] = std::min(lo[k], b[k]); hi[k] = std::max(hi[k], b[k] + P); }
       jb[t].push_back(Job{(int32_t)node, (int32_t)slot_of(l)});
     };
@@ -70,6 +73,7 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
       for (int k = 0; k < d; ++k) sub = sub * 2 + (B.bcoord[i * 3 + k] & 1);
       tl.oA[sub] = B.offA[i];
       tl.mA[sub] = B.maskA[i];
+      tl.bid[sub] = (int32_t)i;
       for (int set = 0; set < 2; ++set) {
         uint64_t m = set == 0 ? B.maskA[i] : B.maskG[i];
         int64_t base = set == 0 ? B.offA[i] : B.nA + B.offG[i];
@@ -83,7 +87,7 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
           int lt[3] = {0, 0, 0};
           for (int k = 0; k < d; ++k) lt[k] = B.bcoord[i * 3 + k] * E + l[k] - tl.origin[k];
           add_job(node, lt);
-          if (set != 0) continue;
+          if (set != 0 || !halo) continue;
           // face halo: outward neighbours of active nodes on the tile boundary
           for (int k = 0; k < d; ++k)
             for (int s = -1; s <= 1; s += 2) {
@@ -110,7 +114,7 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
       key.reserve(jb[t].size());
       for (const Job& j : jb[t]) {
         int32_t b[3] = {0, 0, 0};
-        base_of(B, &B.cp[(int64_t)j.node * d], b);
+        base_of(B, &B.ip[(int64_t)j.node * d], b);
         uint64_t kk = 0;
         for (int bit = 20; bit >= 0; --bit)
           for (int k = 0; k < d; ++k) kk = (kk << 1) | (uint64_t)((b[k] >> bit) & 1);
@@ -181,31 +185,112 @@ void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<i
   }
 }
 
-// Extension rows bucketed by their cube's lower corner (an active node).
-void build_buckets(const cpm_band_s& B, std::vector<int32_t>& ptr, std::vector<int32_t>& rows) {
-  const int64_t n = B.nodes();
-  std::vector<int32_t> corner(n);
+// Brick across each face of every brick: bnbr[i*2d + 2k + s] for axis k, side s
+// (0: lower, 1: upper), -1 when that brick holds no band node. Every grid
+// neighbour of an active node is a band node, so for an active node on a face
+// the brick across it exists (checked here).
+void build_brick_neighbours(const cpm_band_s& B, std::vector<int32_t>& bnbr) {
+  const int d = B.d, sh = brick_shift(d), E = brick_edge(d);
+  const int64_t nb = B.nbricks();
+  bnbr.assign(nb * 2 * d, -1);
+  bool bad = false;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nb; ++i) {
+    for (int k = 0; k < d; ++k)
+      for (int s = 0; s < 2; ++s) {
+        int32_t g[3] = {0, 0, 0};
+        for (int q = 0; q < d; ++q) g[q] = B.bcoord[i * 3 + q] << sh;
+        g[k] += s ? E : -1;
+        int32_t rel[3] = {0, 0, 0};
+        bool in = true;
+        for (int q = 0; q < d; ++q) {
+          rel[q] = (g[q] >> sh) - B.bm_lo[q];
+          if (g[q] < 0 || rel[q] < 0 || rel[q] >= B.bm_dim[q]) in = false;
+        }
+        int32_t id = -1;
+        if (in) {
+          const int64_t bi = d == 3 ? ((int64_t)rel[0] * B.bm_dim[1] + rel[1]) * B.bm_dim[2] + rel[2]
+                                    : (int64_t)rel[0] * B.bm_dim[1] + rel[1];
+          id = B.bmap[bi];
+        }
+        bnbr[i * 2 * d + 2 * k + s] = id;
+        // active nodes on this face need the neighbouring brick
+        uint64_t face = 0;
+        for (int bit = 0; bit < 64; ++bit) {
+          int l[3];
+          local_of(d, bit, l);
+          if (l[k] == (s ? E - 1 : 0)) face |= 1ull << bit;
+        }
+        if ((B.maskA[i] & face) && id < 0) {
+#pragma omp atomic write
+          bad = true;
+        }
+      }
+  }
+  if (bad) fail(CPM_ERR_BAND, "active node whose face neighbour brick is missing");
+}
+
+// Transpose lists: for every brick holding active nodes, the extension rows whose
+// interpolation cube overlaps the brick's box, in increasing row order (a row's
+// cube of (p+1)^d nodes overlaps at most 2^d bricks). ptr is indexed by brick id;
+// list = the bricks with active nodes.
+void build_brick_rows(const cpm_band_s& B, std::vector<int32_t>& ptr, std::vector<int32_t>& rows,
+                      std::vector<int32_t>& list) {
+  const int d = B.d, E = d == 3 ? 4 : 8, P = B.p;
+  const int64_t n = B.nodes(), nb = B.nbricks();
+  auto brick_id = [&](const int32_t* bc) -> int32_t {
+    int64_t r = 0;
+    for (int k = 0; k < d; ++k) {
+      const int32_t q = bc[k] - B.bm_lo[k];
+      if (q < 0 || q >= B.bm_dim[k]) return -1;
+      r = r * B.bm_dim[k] + q;
+    }
+    return B.bmap[r];
+  };
+  // bricks overlapped by each row's cube (up to 2 per axis)
+  std::vector<int32_t> hit(n * 8, -1);
   bool bad = false;
 #pragma omp parallel for schedule(static)
   for (int64_t j = 0; j < n; ++j) {
     int32_t b[3] = {0, 0, 0};
-    base_of(B, &B.cp[j * B.d], b);
-    int64_t c = B.lookup(b);
-    if (c < 0 || c >= B.nA) {
+    base_of(B, &B.ip[j * d], b);
+    int32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    bool ok = true;
+    for (int k = 0; k < d; ++k) {
+      ok = ok && b[k] >= 0;
+      lo[k] = b[k] / E;
+      hi[k] = (b[k] + P) / E;
+    }
+    if (!ok) {
 #pragma omp atomic write
       bad = true;
-      corner[j] = 0;
-    } else {
-      corner[j] = (int32_t)c;
+      continue;
     }
+    int m = 0;
+    for (int32_t x = lo[0]; x <= hi[0]; ++x)
+      for (int32_t y = lo[1]; y <= hi[1]; ++y)
+        for (int32_t z = lo[2]; z <= (d == 3 ? hi[2] : lo[2]); ++z) {
+          const int32_t bc[3] = {x, y, z};
+          const int32_t id = brick_id(bc);
+          if (id >= 0 && B.maskA[id]) hit[j * 8 + m++] = id;
+        }
   }
-  if (bad) fail(CPM_ERR_BAND, "interpolation cube corner outside Sigma_A");
-  ptr.assign(B.nA + 1, 0);
-  for (int64_t j = 0; j < n; ++j) ptr[corner[j] + 1]++;
-  for (int64_t i = 0; i < B.nA; ++i) ptr[i + 1] += ptr[i];
-  rows.assign(n, 0);
+  if (bad) fail(CPM_ERR_BAND, "interpolation cube outside the grid");
+  ptr.assign(nb + 1, 0);
+  for (int64_t e = 0; e < n * 8; ++e)
+    if (hit[e] >= 0) ptr[hit[e] + 1]++;
+  for (int64_t i = 0; i < nb; ++i) ptr[i + 1] += ptr[i];
+  if (ptr[nb] > INT32_MAX - 1) fail(CPM_ERR_BAND, "band too large for the transpose lists");
+  rows.assign(ptr[nb], 0);
   std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
-  for (int64_t j = 0; j < n; ++j) rows[fill[corner[j]]++] = (int32_t)j;
+  for (int64_t j = 0; j < n; ++j)
+    for (int m = 0; m < 8; ++m) {
+      const int32_t id = hit[j * 8 + m];
+      if (id >= 0) rows[fill[id]++] = (int32_t)j;
+    }
+  list.clear();
+  for (int64_t i = 0; i < nb; ++i)
+    if (B.maskA[i]) list.push_back((int32_t)i);
 }
 
 }  // namespace
@@ -247,32 +332,114 @@ void cpm::plan_pipe(std::vector<WorkItem>& work, const std::vector<int32_t>& cos
   work.swap(out);
 }
 
-cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out) {
-  (void)stream;
+// Lists of the two-pass apply: the extension pass visits every tile (a tile of
+// ghost nodes only still owes their extension rows), with jobs = its own band
+// nodes and the footprint of their cubes; the stencil pass visits the tiles with
+// active nodes. Available when every extension-pass footprint fits the LDS budget.
+static void setup_two_pass(cpm_operator_s& op, const cpm_band_s& B) {
+  const int d = B.d;
+  std::vector<int32_t> fvolE;
+  std::vector<FootBrick> fbrecE;
+  std::vector<Job> jobsE;
+  build_tiles(B, op.tilesE, fvolE, fbrecE, jobsE, false);
+  const int cap = (int)(kApplyLdsBytes / sizeof(double));
+  std::vector<WorkItem> ework, eslow;
+  int ucapE = 0;
+  for (size_t t = 0; t < op.tilesE.size(); ++t) {
+    const DevTile& tl = op.tilesE[t];
+    if (tl.job_cnt == 0) continue;
+    if (fvolE[t] > cap || tl.job_cnt > 512 || tl.fb_cnt > kMaxFootBricks) {
+      eslow.push_back(WorkItem{0, (int32_t)t});
+      continue;
+    }
+    ework.push_back(WorkItem{0, (int32_t)t});
+    ucapE = std::max(ucapE, fvolE[t]);
+  }
+  std::vector<WorkItem> swork;
+  for (size_t t = 0; t < op.tiles.size(); ++t) {
+    bool has_active = false;
+    for (int q = 0; q < 8; ++q)
+      if (op.tiles[t].mA[q]) has_active = true;
+    if (has_active) swork.push_back(WorkItem{0, (int32_t)t});
+  }
+  op.twopass = !ework.empty() || !eslow.empty();
+  if (!op.twopass) return;
+  op.h_fbE = eslow;
+  op.d_fbE.upload(eslow);
+  op.d_fbrecE.upload(fbrecE);
+  op.d_jobsE.upload(jobsE);
+  std::vector<int32_t> cost(ework.size());
+  for (size_t i = 0; i < ework.size(); ++i) cost[i] = op.tilesE[ework[i].idx].job_cnt;
+  std::vector<PipeSpan> plan;
+  plan_pipe(ework, cost, ework.empty() ? 0 : apply_pipe_grid(d, B.p, (int)ework.size(), ucapE, true), plan);
+  op.d_planE.upload(plan);
+  op.nplanE = (int)plan.size();
+  std::vector<DevTile> wt;
+  wt.reserve(ework.size());
+  for (const WorkItem& wi : ework) {
+    wt.push_back(op.tilesE[wi.idx]);
+    wt.back().inst = 0;
+    for (int q = 0; q < 8; ++q) wt.back().mA[q] = 0;   // no stencil rows in the extension pass
+  }
+  op.d_wtilesE.upload(wt);
+  op.h_workE = ework;
+  op.h_swork = swork;
+  op.d_swork.upload(swork);
+  op.ucapE = ucapE;
+  op.d_v.alloc((size_t)B.nodes());
+  op.I.fbrecE = op.d_fbrecE.p;
+  op.I.jobsE = op.d_jobsE.p;
+  op.I.vnode_off = 0;
+  op.d_inst.upload(&op.I, 1);
+}
+
+// diagonal and neighbour weight of the stabilized operator of stencil order 2 or 4
+static void stencil_coefficients(int order, int d, double h, double c, double& diag, double& w) {
+  if (order == 4) {
+    w = 1.0 / (12.0 * h * h);
+    diag = c + 30.0 * d * w;
+  } else {
+    w = 1.0 / (h * h);
+    diag = c + 2.0 * d / (h * h);
+  }
+}
+
+static cpm_status operator_create(const cpm_band* band, double c, int order, cpm_operator** out) {
   try {
     if (!band || !out) fail(CPM_ERR_ARG, "null argument");
     *out = nullptr;
     if (!(c > 0) || !std::isfinite(c)) fail(CPM_ERR_ARG, "shift c must be positive and finite");
+    if (order != 2 && order != 4) fail(CPM_ERR_ARG, "order must be 2 or 4");
+    if (order == 4 && band->reach < 2) fail(CPM_ERR_ARG, "the fourth-order stencil needs a band of reach 2");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) fail(CPM_ERR_DEVICE, "no HIP device available");
     auto op = std::make_unique<cpm_operator_s>();
     op->band = std::make_shared<cpm_band_s>(*band);
     op->c = c;
+    op->order = order;
+    op->generic = order == 4 || band->p > 3;
     const cpm_band_s& B = *op->band;
     const int d = B.d;
     const int64_t n = B.nodes();
     std::vector<FootBrick> fbrec;
     std::vector<Job> jobs;
-    build_tiles(B, op->tiles, op->tile_fvol, fbrec, jobs);
-    op->d_fbrec.upload(fbrec);
-    op->d_jobs.upload(jobs);
-    std::vector<int32_t> bptr, brows;
-    build_buckets(B, bptr, brows);
+    std::vector<int32_t> tptr, trows, tlist, bnbr;
+    if (!op->generic) {
+      build_tiles(B, op->tiles, op->tile_fvol, fbrec, jobs);
+      op->d_fbrec.upload(fbrec);
+      op->d_jobs.upload(jobs);
+      build_brick_rows(B, tptr, trows, tlist);
+    } else {
+      for (int64_t i = 0; i < B.nbricks(); ++i)
+        if (B.maskA[i]) tlist.push_back((int32_t)i);
+    }
+    build_brick_neighbours(B, bnbr);
     // SoA closest points
     std::vector<double> cps(n * d);
     for (int64_t j = 0; j < n; ++j)
-      for (int k = 0; k < d; ++k) cps[k * n + j] = (B.cp[j * d + k] - B.lo[k]) / B.h;
+      for (int k = 0; k < d; ++k) cps[k * n + j] = (B.ip[j * d + k] - B.lo[k]) / B.h;
     op->d_tcp.upload(cps);
+    if (!B.sgn.empty()) op->d_sgn.upload(B.sgn);
     op->d_maskA.upload(B.maskA);
     op->d_maskG.upload(B.maskG);
     op->d_offA.upload(B.offA);
@@ -280,16 +447,19 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     op->d_bcoord.upload(B.bcoord);
     op->d_bmap.upload(B.bmap);
     op->d_tiles.upload(op->tiles);
-    op->d_bptr.upload(bptr);
-    op->d_brows.upload(brows);
+    op->d_bptr.upload(tptr);
+    op->d_brows.upload(trows);
+    op->d_tlist.upload(tlist);
+    op->d_bnbr.upload(bnbr);
     DevInst& I = op->I;
     std::memset(&I, 0, sizeof(I));
     I.d = d; I.p = B.p; I.nA = (int32_t)B.nA; I.nG = (int32_t)B.nG;
     I.h = B.h;
-    I.inv_h2 = 1.0 / (B.h * B.h);
-    I.diag = c + 2.0 * d / (B.h * B.h);
+    I.order = order;
+    stencil_coefficients(order, d, B.h, c, I.diag, I.inv_h2);
     for (int k = 0; k < 3; ++k) { I.lo[k] = B.lo[k]; I.bm_lo[k] = B.bm_lo[k]; I.bm_dim[k] = B.bm_dim[k]; }
     I.tcp = op->d_tcp.p;
+    I.esgn = B.sgn.empty() ? nullptr : op->d_sgn.p;
     I.maskA = op->d_maskA.p; I.maskG = op->d_maskG.p;
     I.offA = op->d_offA.p; I.offG = op->d_offG.p;
     I.bcoord = op->d_bcoord.p; I.bmap = op->d_bmap.p;
@@ -298,9 +468,22 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     I.jobs = op->d_jobs.p;
     I.ntiles = (int32_t)op->tiles.size();
     I.nbricks = (int32_t)B.nbricks();
-    I.bucket_ptr = op->d_bptr.p; I.bucket_rows = op->d_brows.p;
+    I.trow_ptr = op->d_bptr.p; I.trows = op->d_brows.p;
+    I.tbricks = op->d_tlist.p; I.ntbricks = (int32_t)tlist.size();
+    I.bnbr = op->d_bnbr.p;
     I.vec_off = 0;
     op->d_inst.upload(&I, 1);
+    if (op->generic) {
+      // two-kernel apply: extension values of up to four right-hand sides
+      op->d_v.alloc((size_t)n * 4);
+      op->gvoff = 0;
+      op->gen.inst = &op->I;
+      op->gen.voff = &op->gvoff;
+      op->gen.ninst = 1;
+      op->gen.vscr = op->d_v.p;
+      *out = op.release();
+      return CPM_OK;
+    }
     // work lists: tiles whose footprint fits the LDS budget, the rest take the slow path
     const int cap = (int)((kApplyLdsBytes - tile_lds_extra_bytes(d)) / sizeof(double));
     const int max_jobs = d == 3 ? 8 * 64 + 6 * 64 : 4 * 64 + 4 * 16;
@@ -343,6 +526,7 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
     op->nwork = (int)fast.size();
     op->nfb = (int)slow.size();
     op->ucap = ucap;
+    setup_two_pass(*op, B);
     *out = op.release();
     return CPM_OK;
   } catch (const Error& e) {
@@ -354,13 +538,24 @@ cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm
   }
 }
 
+cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out) {
+  (void)stream;
+  return operator_create(band, c, 2, out);
+}
+
+cpm_status cpm_operator_create_order(const cpm_band* band, double c, int32_t order, void* stream,
+                                     cpm_operator** out) {
+  (void)stream;
+  return operator_create(band, c, order, out);
+}
+
 cpm_status cpm_operator_set_shift(cpm_operator* op, double c) {
   try {
     if (!op) fail(CPM_ERR_ARG, "null operator");
     if (!(c > 0) || !std::isfinite(c)) fail(CPM_ERR_ARG, "shift c must be positive and finite");
     hip_check(hipDeviceSynchronize(), "set_shift");
     op->c = c;
-    op->I.diag = c + 2.0 * op->I.d / (op->I.h * op->I.h);
+    stencil_coefficients(op->order, op->I.d, op->I.h, c, op->I.diag, op->I.inv_h2);
     op->d_inst.upload(&op->I, 1);
     // the cached single-solve batch holds a copy of the old shift
     op->solve_cache.reset();
@@ -380,6 +575,7 @@ void cpm_operator_destroy(cpm_operator* op) { delete op; }
 cpm_status cpm_extend_apply(const cpm_operator* op, const double* u, double* v, void* stream) {
   try {
     if (!op || (!u && op->band->nA) || (!v && op->band->nodes())) fail(CPM_ERR_ARG, "null argument");
+    if (u == v && u) fail(CPM_ERR_ARG, "u and v must not alias");
     hip_check(launch_extend(op->I, u, v, (hipStream_t)stream), "cpm_extend_apply");
     return CPM_OK;
   } catch (const Error& e) {
@@ -393,9 +589,9 @@ cpm_status cpm_apply(const cpm_operator* op, const double* x, double* y, int32_t
     if (!op || !x || !y) fail(CPM_ERR_ARG, "null argument");
     if (nrhs != 1 && nrhs != 2 && nrhs != 4) fail(CPM_ERR_ARG, "nrhs must be 1, 2 or 4");
     if (x == y) fail(CPM_ERR_ARG, "x and y must not alias");
-    hip_check(launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->pipe(), op->nwork, op->ucap,
-                           op->d_fb.p, op->nfb, x, y, (hipStream_t)stream),
-              "cpm_apply");
+    const int variant = (nrhs == 1 && op->apply_variant == kApplyTwoPass && !op->twopass) ? kApplyPipelined
+                                                                                         : op->apply_variant;
+    hip_check(launch_apply(op->apply_args(), nrhs, variant, x, y, (hipStream_t)stream), "cpm_apply");
     return CPM_OK;
   } catch (const Error& e) {
     set_error(e.msg);
@@ -408,6 +604,7 @@ cpm_status cpm_apply_T(const cpm_operator* op, const double* x, double* y, int32
     if (!op || !x || !y) fail(CPM_ERR_ARG, "null argument");
     if (nrhs != 1 && nrhs != 2 && nrhs != 4) fail(CPM_ERR_ARG, "nrhs must be 1, 2 or 4");
     if (x == y) fail(CPM_ERR_ARG, "x and y must not alias");
+    if (op->generic) fail(CPM_ERR_ARG, "the transposed apply needs a second-order operator with p <= 3");
     op->d_z.alloc((size_t)op->band->nodes() * 4);
     hip_check(launch_apply_T(op->I, nrhs, x, op->d_z.p, y, (hipStream_t)stream), "cpm_apply_T");
     return CPM_OK;

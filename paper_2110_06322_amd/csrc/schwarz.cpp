@@ -137,13 +137,15 @@ int64_t grid_key(const cpm_band_s& B, int64_t node) {
 
 namespace cpm {
 
-// Extension row of node n: global active indices and weights of its cube.
+// Extension row of node n: global active indices and weights of its cube. Bands of degree
+// p > 3 use degree 3 here: the preconditioner approximates the operator with cubic
+// interpolation (the cubic cube lies inside the degree-p one, hence in Sigma_A).
 void extension_row(const cpm_band_s& B, int64_t n, std::vector<int32_t>& cols, std::vector<double>& w) {
-  const int d = B.d, p = B.p, P1 = p + 1;
+  const int d = B.d, p = std::min(B.p, 3), P1 = p + 1;
   int32_t b[3] = {0, 0, 0};
   double wk[3][4];
   for (int k = 0; k < d; ++k) {
-    double t = (B.cp[n * d + k] - B.lo[k]) / B.h;
+    double t = (B.ip[n * d + k] - B.lo[k]) / B.h;
     double bf = std::floor(t - (p - 1) / 2.0);
     b[k] = (int32_t)bf;
     lagrange(p, t - bf, wk[k]);
@@ -160,7 +162,7 @@ void extension_row(const cpm_band_s& B, int64_t n, std::vector<int32_t>& cols, s
     cols[q] = (int32_t)j;
     double v = 1.0;
     for (int k = 0; k < d; ++k) v *= wk[k][a[k]];
-    w[q] = v;
+    w[q] = B.sgn.empty() ? v : B.sgn[n] * v;
   }
 }
 

@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <vector>
 
+#include "coarse.h"
 #include "common.h"
 
 namespace cpm {
@@ -125,4 +126,9 @@ struct cpm_precond_s {
   cpm::SchwarzCfg cfg;          // kernel configuration (tunable)
   int max_rows = 0, max_levels = 0, max_len = 0;
   int64_t total_rows = 0, total_nnz = 0;
+  // coarse level (two-level Schwarz): device arrays and the kernels' view of them
+  cpm::DevCoarse C{};
+  cpm::DevBuf<int32_t> d_own_ptr, d_own_idx, d_owner;
+  cpm::DevBuf<double> d_ainv;
+  mutable cpm::DevBuf<double> d_cv, d_ev, d_tz, d_tr;   // scratch of the single-preconditioner apply
 };

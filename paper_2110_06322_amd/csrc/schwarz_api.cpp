@@ -19,10 +19,98 @@ cpm_status cpm_precond_opts_default(cpm_precond_opts* o) {
   o->precision = CPM_PREC_FP64;
   o->transpose = 0;
   o->ordering = CPM_ORDER_RCM;
+  o->coarse = CPM_COARSE_NONE;
   return CPM_OK;
 }
 
 namespace {
+
+constexpr int kMaxCoarse = 4096;
+
+// Dense inverse by Gauss-Jordan elimination with partial pivoting (row-major n x n);
+// false when a pivot vanishes. a is overwritten.
+bool dense_inverse(int n, std::vector<double>& a, std::vector<double>& inv) {
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    double best = std::fabs(a[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      const double v = std::fabs(a[(size_t)i * n + k]);
+      if (v > best) { best = v; piv = i; }
+    }
+    if (!(best > 0.0) || !std::isfinite(best)) return false;
+    if (piv != k)
+      for (int j = 0; j < n; ++j) {
+        std::swap(a[(size_t)k * n + j], a[(size_t)piv * n + j]);
+        std::swap(inv[(size_t)k * n + j], inv[(size_t)piv * n + j]);
+      }
+    const double d = a[(size_t)k * n + k];
+    for (int j = 0; j < n; ++j) {
+      a[(size_t)k * n + j] /= d;
+      inv[(size_t)k * n + j] /= d;
+    }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double f = a[(size_t)i * n + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        a[(size_t)i * n + j] -= f * a[(size_t)k * n + j];
+        inv[(size_t)i * n + j] -= f * inv[(size_t)k * n + j];
+      }
+    }
+  }
+  return true;
+}
+
+// Coarse level: owned-node lists, the Galerkin matrix A0 = R0 A R0^T (column
+// block j0..j0+3 from A applied to four indicator vectors, then restricted),
+// its inverse on the device.
+void build_coarse(cpm_precond_s& pc) {
+  const cpm_operator_s* op = pc.op;
+  const auto& owner = pc.host.owner;
+  const int n = pc.host.nparts;
+  const int64_t nA = op->band->nA;
+  std::vector<int32_t> ptr(n + 1, 0), idx(nA);
+  for (int64_t i = 0; i < nA; ++i) ptr[owner[i] + 1]++;
+  for (int j = 0; j < n; ++j) ptr[j + 1] += ptr[j];
+  {
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t i = 0; i < nA; ++i) idx[fill[owner[i]]++] = (int32_t)i;
+  }
+  pc.d_own_ptr.upload(ptr);
+  pc.d_own_idx.upload(idx);
+  pc.d_owner.upload(owner);
+  DevCoarse& C = pc.C;
+  C.n = n;
+  C.mode = pc.opts.coarse;
+  C.nA = nA;
+  C.own_ptr = pc.d_own_ptr.p;
+  C.own_idx = pc.d_own_idx.p;
+  C.owner = pc.d_owner.p;
+  C.vec_off = 0;
+  C.coff = 0;
+  DevBuf<double> X, Y, col;
+  X.alloc((size_t)nA * 4);
+  Y.alloc((size_t)nA * 4);
+  col.alloc((size_t)n * 4);
+  std::vector<double> A0((size_t)n * n), h(4 * (size_t)n);
+  const hipStream_t s = nullptr;
+  const ApplyArgs args = op->apply_args();
+  for (int j0 = 0; j0 < n; j0 += 4) {
+    hip_check(coarse_indicators(C, j0, X.p, s), "coarse indicators");
+    hip_check(launch_apply(args, 4, kApplyPerTile, X.p, Y.p, s), "coarse apply");
+    hip_check(coarse_restrict(C, 4, Y.p, col.p, s), "coarse restrict");
+    hip_check(hipMemcpy(h.data(), col.p, h.size() * sizeof(double), hipMemcpyDeviceToHost), "coarse column");
+    for (int j = 0; j < n; ++j)
+      for (int q = 0; q < 4 && j0 + q < n; ++q) A0[(size_t)j * n + j0 + q] = h[(size_t)j * 4 + q];
+  }
+  std::vector<double> inv;
+  if (!dense_inverse(n, A0, inv)) fail(CPM_ERR_PIVOT, "singular coarse matrix");
+  pc.d_ainv.upload(inv);
+  C.ainv = pc.d_ainv.p;
+}
 
 template <class T>
 void upload_values(cpm_precond_s* pc, const std::vector<double>& lval, const std::vector<double>& uval) {
@@ -45,6 +133,11 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     if (opts->subsolver != CPM_SUB_ILU0 && opts->subsolver != CPM_SUB_DENSE_LU) fail(CPM_ERR_ARG, "bad subsolver");
     if (opts->precision != CPM_PREC_FP64 && opts->precision != CPM_PREC_FP32) fail(CPM_ERR_ARG, "bad precision");
     if (opts->ordering != CPM_ORDER_RCM && opts->ordering != CPM_ORDER_DISTANCE) fail(CPM_ERR_ARG, "bad ordering");
+    if (opts->coarse != CPM_COARSE_NONE && opts->coarse != CPM_COARSE_ADDITIVE && opts->coarse != CPM_COARSE_FIRST)
+      fail(CPM_ERR_ARG, "bad coarse option");
+    if (opts->coarse != CPM_COARSE_NONE && opts->transpose) fail(CPM_ERR_ARG, "no coarse level with transpose = 1");
+    if (opts->coarse != CPM_COARSE_NONE && opts->n_parts > kMaxCoarse)
+      fail(CPM_ERR_ARG, "coarse level limited to 4096 subdomains");
     auto pc = std::make_unique<cpm_precond_s>();
     pc->op = op;
     pc->opts = *opts;
@@ -189,6 +282,7 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
     for (int j = 0; j < np; ++j) work[j] = WorkItem{0, order[j]};
     pc->d_work.upload(work);
     pc->h_work = work;
+    if (opts->coarse != CPM_COARSE_NONE) build_coarse(*pc);
     pc->serial = next_serial();
     *out = pc.release();
     return CPM_OK;
@@ -231,8 +325,32 @@ cpm_status cpm_precond_export_partition(const cpm_precond* pc, int32_t* owner, i
 namespace cpm {
 // z = M^-1 r for one preconditioner (also used by the solver)
 hipError_t precond_apply_raw(const cpm_precond_s* pc, const double* r, double* z, int nrhs, hipStream_t s) {
-  return launch_schwarz(pc->cfg, pc->d_pc.p, pc->d_work.p, pc->host.nparts, pc->max_rows, pc->max_len, pc->P.fp32,
-                        nrhs, r, z, s);
+  auto one_level = [&](const double* rr) {
+    return launch_schwarz(pc->cfg, pc->d_pc.p, pc->d_work.p, pc->host.nparts, pc->max_rows, pc->max_len, pc->P.fp32,
+                          nrhs, rr, z, s);
+  };
+  if (pc->C.n == 0) return one_level(r);
+  const DevCoarse& C = pc->C;
+  const int64_t nv = C.nA * nrhs;
+  pc->d_cv.alloc((size_t)C.n * 4);
+  pc->d_ev.alloc((size_t)C.n * 4);
+  hipError_t e;
+  if ((e = coarse_restrict(C, nrhs, r, pc->d_cv.p, s)) != hipSuccess) return e;
+  if ((e = coarse_solve(C, nrhs, pc->d_cv.p, pc->d_ev.p, s)) != hipSuccess) return e;
+  if (C.mode == CPM_COARSE_ADDITIVE) {
+    if ((e = one_level(r)) != hipSuccess) return e;
+    return coarse_prolong(C, nrhs, pc->d_ev.p, z, true, s);
+  }
+  // coarse first: r' = r - A R0^T e, z = M1^-1 r' + R0^T e
+  pc->d_tz.alloc((size_t)C.nA * 4);
+  pc->d_tr.alloc((size_t)C.nA * 4);
+  if ((e = coarse_prolong(C, nrhs, pc->d_ev.p, pc->d_tz.p, false, s)) != hipSuccess) return e;
+  const int variant = (nrhs == 1 && pc->op->apply_variant == kApplyTwoPass && !pc->op->twopass) ? kApplyPipelined
+                                                                                                : pc->op->apply_variant;
+  if ((e = launch_apply(pc->op->apply_args(), nrhs, variant, pc->d_tz.p, pc->d_tr.p, s)) != hipSuccess) return e;
+  if ((e = coarse_sub(nv, r, pc->d_tr.p, pc->d_tr.p, s)) != hipSuccess) return e;
+  if ((e = one_level(pc->d_tr.p)) != hipSuccess) return e;
+  return coarse_prolong(C, nrhs, pc->d_ev.p, z, true, s);
 }
 // error flag of the bounded waits (0 = fine); resets it
 int precond_take_error(const cpm_precond_s* pc) {

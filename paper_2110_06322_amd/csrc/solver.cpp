@@ -32,6 +32,11 @@ struct cpm_batch_s {
   // operator apply over all instances
   std::vector<DevInst> hinst;
   DevBuf<DevInst> d_insts;
+  // two-kernel apply (operators of stencil order 4 or degree p > 3): per-instance launches
+  bool generic = false;
+  std::vector<int64_t> gvoff;
+  DevBuf<double> gv;
+  GenericPlan gen;
   DevBuf<WorkItem> d_work, d_fb;
   DevBuf<DevTile> d_wtiles;   // tiles of d_work in work order, with their instance
   DevBuf<PipeSpan> d_plan;     // spans of the persistent apply's workgroups
@@ -39,7 +44,39 @@ struct cpm_batch_s {
   int nwork = 0, nfb = 0, ucap = 0;
   PipeWork pipe() const { return PipeWork{d_wtiles.p, d_plan.p, nplan}; }
   int apply_variant = kApplyPipelined;
+  // two-pass apply over all instances (when every operator has it)
+  bool twopass = false;
+  DevBuf<DevTile> d_wtilesE;
+  DevBuf<PipeSpan> d_planE;
+  DevBuf<WorkItem> d_swork, d_fbE;
+  DevBuf<double> vscr;
+  int nplanE = 0, ucapE = 0, nswork = 0, nfbE = 0;
+  ApplyArgs apply_args() const {
+    ApplyArgs A;
+    A.gen = generic ? &gen : nullptr;
+    A.d = d; A.p = p; A.insts = d_insts.p;
+    A.work = d_work.p; A.nwork = nwork; A.pipe = pipe(); A.ucap = ucap;
+    A.fb = d_fb.p; A.nfb = nfb;
+    A.twopass = twopass;
+    A.pipeE = PipeWork{d_wtilesE.p, d_planE.p, nplanE};
+    A.ucapE = ucapE;
+    A.swork = d_swork.p; A.nswork = nswork;
+    A.fbE = d_fbE.p; A.nfbE = nfbE;
+    A.vscr = vscr.p;
+    return A;
+  }
   SchwarzCfg pc_cfg;
+  // operator algebra of the current solve: the operator is P(L) = sum_k poly_coef[k] L^k with
+  // L = c_i I - A_i (poly_n = 0: A itself), the preconditioner is applied pc_power times
+  std::vector<double> shift;   // c_i of every instance at creation
+  DevBuf<double> d_shift;
+  int poly_n = 0, pc_power = 1;
+  double poly_coef[kMaxPoly] = {};
+  DevBuf<double> pbuf, pctmp;
+  // coarse levels (two-level Schwarz): each instance's view with batch offsets
+  std::vector<DevCoarse> coarse;
+  bool any_coarse = false, any_coarse_first = false;
+  DevBuf<double> cvec, evec, ctz, ctr;
   // preconditioners
   bool any_pc = false, all_pc = true, pc_packets = false;
   int pc_fp32 = 0, pc_transpose = -1, max_rows = 0, max_len = 0, npcwork = 0;
@@ -88,21 +125,34 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
   Bt.d = ops[0]->I.d;
   Bt.p = ops[0]->I.p;
   Bt.off.assign(n + 1, 0);
-  std::vector<WorkItem> fast, slow, pcw;
+  std::vector<WorkItem> fast, slow, pcw, ework, swork, eslow;
+  Bt.twopass = true;
+  int64_t vnodes = 0;
   std::vector<DevPC> hpcs(n);
   std::vector<int32_t> copy_inst(n, 0);
   for (int i = 0; i < n; ++i) {
     const cpm_operator_s* op = ops[i];
     if (!op) fail(CPM_ERR_ARG, "null operator in batch");
     if (op->I.d != Bt.d || op->I.p != Bt.p) fail(CPM_ERR_ARG, "all operators of a batch need the same d and p");
+    if (i == 0) Bt.generic = op->generic;
+    if (op->generic != Bt.generic)
+      fail(CPM_ERR_ARG, "a batch cannot mix fused (second order, p <= 3) and two-kernel operators");
     Bt.ops.push_back(op);
     Bt.off[i + 1] = Bt.off[i] + op->band->nA;
     DevInst I = op->I;
     I.vec_off = Bt.off[i];
+    I.vnode_off = vnodes;
+    vnodes += op->band->nodes();
     Bt.hinst.push_back(I);
+    Bt.shift.push_back(op->c);
     for (const WorkItem& wi : op->h_work) fast.push_back(WorkItem{i, wi.idx});
     for (const WorkItem& wi : op->h_fb) slow.push_back(WorkItem{i, wi.idx});
     Bt.ucap = std::max(Bt.ucap, op->ucap);
+    if (!op->twopass) Bt.twopass = false;
+    for (const WorkItem& wi : op->h_workE) ework.push_back(WorkItem{i, wi.idx});
+    for (const WorkItem& wi : op->h_swork) swork.push_back(WorkItem{i, wi.idx});
+    for (const WorkItem& wi : op->h_fbE) eslow.push_back(WorkItem{i, wi.idx});
+    Bt.ucapE = std::max(Bt.ucapE, op->ucapE);
     if (i == 0) Bt.apply_variant = op->apply_variant;
     const cpm_precond_s* pc = pcs ? pcs[i] : nullptr;
     Bt.pcs.push_back(pc);
@@ -132,6 +182,20 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
   }
   Bt.Ntot = Bt.off[n];
   Bt.d_insts.upload(Bt.hinst);
+  if (Bt.generic) {
+    Bt.gvoff.assign(n, 0);
+    int64_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+      Bt.gvoff[i] = tot;
+      tot += ops[i]->band->nodes();
+    }
+    Bt.gv.alloc((size_t)tot * R);
+    Bt.gen.inst = Bt.hinst.data();
+    Bt.gen.voff = Bt.gvoff.data();
+    Bt.gen.ninst = n;
+    Bt.gen.vscr = Bt.gv.p;
+  }
+  Bt.d_shift.upload(Bt.shift);
   {
     std::vector<int32_t> cost(fast.size());
     for (size_t i = 0; i < fast.size(); ++i) cost[i] = ops[fast[i].inst]->tiles[fast[i].idx].job_cnt;
@@ -153,6 +217,53 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
   Bt.d_fb.upload(slow);
   Bt.nwork = (int)fast.size();
   Bt.nfb = (int)slow.size();
+  if (Bt.twopass && (!ework.empty() || !eslow.empty())) {
+    std::vector<int32_t> cost(ework.size());
+    for (size_t i = 0; i < ework.size(); ++i) cost[i] = ops[ework[i].inst]->tilesE[ework[i].idx].job_cnt;
+    std::vector<PipeSpan> plan;
+    plan_pipe(ework, cost, ework.empty() ? 0 : apply_pipe_grid(Bt.d, Bt.p, (int)ework.size(), Bt.ucapE, true), plan);
+    Bt.d_fbE.upload(eslow);
+    Bt.nfbE = (int)eslow.size();
+    Bt.d_planE.upload(plan);
+    Bt.nplanE = (int)plan.size();
+    std::vector<DevTile> wt;
+    wt.reserve(ework.size());
+    for (const WorkItem& wi : ework) {
+      wt.push_back(ops[wi.inst]->tilesE[wi.idx]);
+      wt.back().inst = wi.inst;
+      for (int q = 0; q < 8; ++q) wt.back().mA[q] = 0;
+    }
+    Bt.d_wtilesE.upload(wt);
+    Bt.d_swork.upload(swork);
+    Bt.nswork = (int)swork.size();
+    Bt.vscr.alloc((size_t)vnodes * Bt.R);
+  } else {
+    Bt.twopass = false;
+  }
+  if (Bt.apply_variant == kApplyTwoPass && !Bt.twopass) Bt.apply_variant = kApplyPipelined;
+  {
+    int64_t coff = 0;
+    Bt.coarse.assign(n, DevCoarse{});
+    for (int i = 0; i < n; ++i) {
+      const cpm_precond_s* pc = pcs ? pcs[i] : nullptr;
+      if (!pc || pc->C.n == 0) continue;
+      DevCoarse C = pc->C;
+      C.vec_off = Bt.off[i];
+      C.coff = coff;
+      coff += C.n;
+      Bt.coarse[i] = C;
+      Bt.any_coarse = true;
+      if (C.mode == CPM_COARSE_FIRST) Bt.any_coarse_first = true;
+    }
+    if (Bt.any_coarse) {
+      Bt.cvec.alloc((size_t)coff * R);
+      Bt.evec.alloc((size_t)coff * R);
+      if (Bt.any_coarse_first) {
+        Bt.ctz.alloc((size_t)Bt.Ntot * R);
+        Bt.ctr.alloc((size_t)Bt.Ntot * R);
+      }
+    }
+  }
   // largest subdomains first across the whole batch
   if (Bt.any_pc) {
     std::stable_sort(pcw.begin(), pcw.end(), [&](const WorkItem& a, const WorkItem& b) {
@@ -228,10 +339,22 @@ GmresState state_of(cpm_batch_s& Bt, int m) {
 // y = A x (or A^T x) over all instances of the batch, packed layout
 void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hipStream_t s,
                  const Gate& gate = Gate{}) {
+  if (!transpose && Bt.poly_n > 0) {
+    // y = a_0 x; v_0 = x; v_k = c v_{k-1} - A v_{k-1}; y += a_k v_k (v_k in buffer (k-1) mod 2)
+    const size_t Ns = (size_t)Bt.Ntot * Bt.R;
+    hip_check(poly_scale((int64_t)Ns, Bt.poly_coef[0], x, y, s), "polynomial apply");
+    const double* v = x;
+    for (int k = 1; k < Bt.poly_n; ++k) {
+      double* buf = Bt.pbuf.p + (size_t)((k - 1) & 1) * Ns;
+      hip_check(launch_apply(Bt.apply_args(), Bt.R, Bt.apply_variant, v, buf, s, gate), "operator apply");
+      hip_check(poly_step_chunks(Bt.R, Bt.d_chunks.p, Bt.nchunks, Bt.d_shift.p, Bt.poly_coef[k], v, buf, buf, y, s),
+                "polynomial apply");
+      v = buf;
+    }
+    return;
+  }
   if (!transpose) {
-    hip_check(launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.pipe(), Bt.nwork, Bt.ucap, Bt.d_fb.p,
-                           Bt.nfb, x, y, s, gate),
-              "operator apply");
+    hip_check(launch_apply(Bt.apply_args(), Bt.R, Bt.apply_variant, x, y, s, gate), "operator apply");
     return;
   }
   int64_t mx = 0;
@@ -241,15 +364,58 @@ void batch_apply(cpm_batch_s& Bt, const double* x, double* y, bool transpose, hi
     hip_check(launch_apply_T(Bt.hinst[i], Bt.R, x, Bt.zT.p, y, s, gate, i), "transposed operator apply");
 }
 
-void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s, const Gate& gate = Gate{}) {
+void batch_precond_once(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s, const Gate& gate) {
+  // coarse levels: coarse-first instances solve their one-level problem on r - A z_c
+  const double* vin = v;
+  if (Bt.any_coarse) {
+    for (int i = 0; i < Bt.ni; ++i) {
+      const DevCoarse& C = Bt.coarse[i];
+      if (C.n == 0) continue;
+      hip_check(coarse_restrict(C, Bt.R, v, Bt.cvec.p, s), "coarse restrict");
+      hip_check(coarse_solve(C, Bt.R, Bt.cvec.p, Bt.evec.p, s), "coarse solve");
+    }
+    if (Bt.any_coarse_first) {
+      hip_check(hipMemcpyAsync(Bt.ctr.p, v, (size_t)Bt.Ntot * Bt.R * sizeof(double), hipMemcpyDeviceToDevice, s),
+                "copy");
+      for (int i = 0; i < Bt.ni; ++i) {
+        const DevCoarse& C = Bt.coarse[i];
+        if (C.n == 0 || C.mode != CPM_COARSE_FIRST) continue;
+        const cpm_operator_s* op = Bt.ops[i];
+        const int64_t o = Bt.off[i] * Bt.R;
+        DevCoarse L = C;   // the operator's own (unpacked) view of the instance's vectors
+        L.vec_off = 0;
+        hip_check(coarse_prolong(L, Bt.R, Bt.evec.p, Bt.ctz.p + o, false, s), "coarse prolong");
+        const int variant = (Bt.R == 1 && op->apply_variant == kApplyTwoPass && !op->twopass) ? kApplyPipelined
+                                                                                              : op->apply_variant;
+        hip_check(launch_apply(op->apply_args(), Bt.R, variant, Bt.ctz.p + o, Bt.ctr.p + o, s), "coarse apply");
+        hip_check(coarse_sub(op->band->nA * Bt.R, v + o, Bt.ctr.p + o, Bt.ctr.p + o, s), "coarse residual");
+      }
+      vin = Bt.ctr.p;
+    }
+  }
   if (Bt.any_pc) {
     hipError_t e = launch_schwarz(Bt.pc_cfg, Bt.d_pcs.p, Bt.d_pcwork.p, Bt.npcwork, Bt.max_rows, Bt.max_len,
-                                  Bt.pc_fp32, Bt.R, v, z, s, gate);
+                                  Bt.pc_fp32, Bt.R, vin, z, s, gate);
     if (e == hipErrorInvalidConfiguration)
       fail(CPM_ERR_ARG, "subdomains too large for the local-memory budget at this nrhs/precision");
     hip_check(e, "preconditioner apply");
   }
   if (!Bt.all_pc) hip_check(vec_copy(Bt.R, v, z, Bt.d_chunks.p, Bt.nchunks, Bt.d_copy_inst.p, s), "copy");
+  if (Bt.any_coarse)
+    for (int i = 0; i < Bt.ni; ++i)
+      if (Bt.coarse[i].n) hip_check(coarse_prolong(Bt.coarse[i], Bt.R, Bt.evec.p, z, true, s), "coarse prolong");
+}
+
+// z = M^-k v with k = pc_power (the intermediate results alternate between pctmp and z)
+void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s, const Gate& gate = Gate{}) {
+  const int k = Bt.pc_power;
+  if (k <= 1) return batch_precond_once(Bt, v, z, s, gate);
+  const double* in = v;
+  for (int q = 0; q < k; ++q) {
+    double* out = ((k - 1 - q) & 1) ? Bt.pctmp.p : z;
+    batch_precond_once(Bt, in, out, s, gate);
+    in = out;
+  }
 }
 
 // One Arnoldi step j of every active system (preconditioner, operator, CGS2,
@@ -353,11 +519,35 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
   if (o.mode == CPM_MODE_MIXED_IR && !(o.inner_rtol > 0 && o.inner_rtol < 1)) fail(CPM_ERR_ARG, "inner_rtol in (0,1)");
   if (Bt.any_pc && (Bt.pc_transpose != 0) != (o.transpose != 0))
     fail(CPM_ERR_ARG, "preconditioner transpose flag does not match the solve");
+  if (o.transpose && Bt.generic)
+    fail(CPM_ERR_ARG, "transposed solves need second-order operators with p <= 3");
   for (int i = 0; i < Bt.ni; ++i)
     if (!fin[i] || !uin[i]) fail(CPM_ERR_ARG, "null vector");
+  if (o.poly_n < 0 || o.poly_n > kMaxPoly) fail(CPM_ERR_ARG, "poly_n must be in 0..5");
+  if (o.pc_power < 0 || o.pc_power > 4) fail(CPM_ERR_ARG, "pc_power must be in 1..4 (0 = 1)");
+  if (o.poly_n > 0) {
+    if (o.transpose) fail(CPM_ERR_ARG, "polynomial operators cannot be solved transposed");
+    if (o.use_graph) fail(CPM_ERR_ARG, "polynomial operators cannot be combined with use_graph");
+    bool nz = false;
+    for (int k = 0; k < o.poly_n; ++k) {
+      if (!std::isfinite(o.poly_coef[k])) fail(CPM_ERR_ARG, "non-finite polynomial coefficient");
+      nz = nz || o.poly_coef[k] != 0.0;
+    }
+    if (!nz) fail(CPM_ERR_ARG, "all polynomial coefficients are zero");
+  }
+  if (o.pc_power > 1 && o.use_graph) fail(CPM_ERR_ARG, "pc_power > 1 cannot be combined with use_graph");
   ensure_workspace(Bt, m);
+  // the operator algebra holds for this solve only
+  struct PolyScope {
+    cpm_batch_s& B;
+    ~PolyScope() { B.poly_n = 0; B.pc_power = 1; }
+  } poly_scope{Bt};
+  Bt.poly_n = o.poly_n;
+  for (int k = 0; k < kMaxPoly; ++k) Bt.poly_coef[k] = k < o.poly_n ? o.poly_coef[k] : 0.0;
+  Bt.pc_power = std::max(1, (int)o.pc_power);
+  if (Bt.poly_n > 1) Bt.pbuf.alloc((size_t)Bt.Ntot * Bt.R * 2);
+  if (Bt.pc_power > 1 && Bt.any_pc) Bt.pctmp.alloc((size_t)Bt.Ntot * Bt.R);
   const int R = Bt.R, ns = Bt.ns;
-  const size_t Ns = (size_t)Bt.Ntot * R;
   const bool tr = o.transpose != 0;
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "event");
@@ -539,6 +729,8 @@ cpm_status cpm_solve_opts_default(cpm_solve_opts* o) {
   o->mode = CPM_MODE_FP64;
   o->inner_rtol = 1e-4;
   o->stagnation_cycles = 50;
+  o->poly_n = 0;
+  o->pc_power = 1;
   return CPM_OK;
 }
 
@@ -621,21 +813,19 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
                     tune::log2i(Bt.ni), tune::log2i((double)Bt.Ntot));
       auto it = cache.find(key);
       if (!force && it != cache.end() && it->second.size() == 1 &&
-          (it->second[0] == kApplyPipelined || it->second[0] == kApplyPerTile)) {
+          (it->second[0] == kApplyPipelined || it->second[0] == kApplyPerTile ||
+           (it->second[0] == kApplyTwoPass && Bt.twopass && Bt.R == 1))) {
         Bt.apply_variant = it->second[0];
       } else {
         all_cached = false;
         double best = 1e30;
         int bestv = kApplyPipelined;
-        for (int v : {kApplyPipelined, kApplyPerTile}) {
-          if (v == kApplyPipelined && Bt.R != 1) continue;
+        for (int v : {kApplyPipelined, kApplyPerTile, kApplyTwoPass}) {
+          if ((v == kApplyPipelined || v == kApplyTwoPass) && Bt.R != 1) continue;
+          if (v == kApplyTwoPass && !Bt.twopass) continue;
           Bt.apply_variant = v;
           const double ms = tune::time_ms(
-              [&] {
-                return launch_apply(Bt.d, Bt.p, Bt.R, v, Bt.d_insts.p, Bt.d_work.p, Bt.pipe(), Bt.nwork, Bt.ucap, Bt.d_fb.p,
-                                    Bt.nfb, Bt.r.p, Bt.w.p, s);
-              },
-              reps, s);
+              [&] { return launch_apply(Bt.apply_args(), Bt.R, v, Bt.r.p, Bt.w.p, s); }, reps, s);
           if (ms < best) { best = ms; bestv = v; }
         }
         Bt.apply_variant = bestv;
@@ -644,11 +834,7 @@ cpm_status cpm_batch_autotune(cpm_batch* b, const char* cache_path, int32_t forc
       }
       out->apply_variant = Bt.apply_variant;
       out->apply_ms = tune::time_ms(
-          [&] {
-            return launch_apply(Bt.d, Bt.p, Bt.R, Bt.apply_variant, Bt.d_insts.p, Bt.d_work.p, Bt.pipe(), Bt.nwork, Bt.ucap,
-                                Bt.d_fb.p, Bt.nfb, Bt.r.p, Bt.w.p, s);
-          },
-          reps, s);
+          [&] { return launch_apply(Bt.apply_args(), Bt.R, Bt.apply_variant, Bt.r.p, Bt.w.p, s); }, reps, s);
     }
     if (Bt.any_pc) {
       int max_levels = 0;

@@ -189,24 +189,22 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
       char key[160];
       std::snprintf(key, sizeof key, "apply|%s|d%dp%dr%d|nA2^%d", dev.c_str(), op->I.d, op->I.p, nrhs,
                     log2i((double)n));
-      const int cand[2] = {kApplyPipelined, kApplyPerTile};
-      const int ncand = nrhs == 1 ? 2 : 1;
+      std::vector<int> cand = {kApplyPerTile};
+      if (nrhs == 1) {
+        cand = {kApplyPipelined, kApplyPerTile};
+        if (op->twopass) cand.push_back(kApplyTwoPass);
+      }
       auto it = cache.find(key);
       if (!force && it != cache.end() && !it->second.empty() &&
-          (it->second[0] == kApplyPipelined || it->second[0] == kApplyPerTile)) {
+          (it->second[0] == kApplyPipelined || it->second[0] == kApplyPerTile ||
+           (it->second[0] == kApplyTwoPass && op->twopass && nrhs == 1))) {
         op->apply_variant = it->second[0];
       } else {
         all_cached = false;
         double best = 1e30;
         int bestv = kApplyPipelined;
-        for (int c = 0; c < ncand; ++c) {
-          const int v = cand[c];
-          const double ms = time_ms(
-              [&] {
-                return launch_apply(op->I.d, op->I.p, nrhs, v, op->d_inst.p, op->d_work.p, op->pipe(), op->nwork, op->ucap,
-                                    op->d_fb.p, op->nfb, x.p, y.p, s);
-              },
-              reps, s);
+        for (const int v : cand) {
+          const double ms = time_ms([&] { return launch_apply(op->apply_args(), nrhs, v, x.p, y.p, s); }, reps, s);
           if (ms < best) { best = ms; bestv = v; }
         }
         op->apply_variant = bestv;
@@ -214,10 +212,7 @@ cpm_status cpm_autotune(cpm_operator* op, cpm_precond* pc, int32_t nrhs, const c
         dirty = true;
       }
       out->apply_variant = op->apply_variant;
-      auto f = [&] {
-        return launch_apply(op->I.d, op->I.p, nrhs, op->apply_variant, op->d_inst.p, op->d_work.p, op->pipe(), op->nwork,
-                            op->ucap, op->d_fb.p, op->nfb, x.p, y.p, s);
-      };
+      auto f = [&] { return launch_apply(op->apply_args(), nrhs, op->apply_variant, x.p, y.p, s); };
       out->apply_ms = time_ms(f, reps, s);
     }
 

@@ -37,6 +37,16 @@ def test_library_exports_every_declared_symbol():
     assert sorted(n for n, _, _ in _capi.SIGNATURES) == names
 
 
+def test_binding_structs_match_the_header_layout():
+    L = _capi.lib()
+    for i, st in enumerate(_capi.ABI_STRUCTS):
+        assert L.cpm_abi_sizeof(i) == ctypes.sizeof(st), st.__name__
+    assert L.cpm_abi_sizeof(len(_capi.ABI_STRUCTS)) == -1
+    o = _capi.SolveOpts()
+    assert L.cpm_solve_opts_default(ctypes.byref(o)) == 0
+    assert o.poly_n == 0 and o.pc_power == 1 and o.restart == 30
+
+
 def test_version_and_error_string():
     assert _capi.lib().cpm_version() == 1
     assert isinstance(_capi.lib().cpm_last_error(), bytes)
@@ -89,7 +99,7 @@ def test_band_errors():
     assert e.value.status == "CPM_ERR_BAND"
     for bad in [dict(kind="circle", params=(1.0,), d=3, h=0.1, p=3),
                 dict(kind="sphere", params=(1.0,), d=3, h=-0.1, p=3),
-                dict(kind="sphere", params=(1.0,), d=3, h=0.1, p=5),
+                dict(kind="sphere", params=(1.0,), d=3, h=0.1, p=6),
                 dict(kind="torus", params=(0.4, 1.0), d=3, h=0.1, p=3)]:
         with pytest.raises(_capi.CpmError) as e:
             cpm.Band(**bad)

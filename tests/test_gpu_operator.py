@@ -89,3 +89,33 @@ def test_shift_update_and_constant_vector():
         y = op.apply(one)
         diag = c + 6 / 0.01
         assert float((y - c).abs().max()) <= 64 * G.EPS * 2 * diag
+
+
+def _force_apply(path, variant):
+    import json
+    c = json.loads(path.read_text())
+    keys = [k for k in c if k.startswith("apply|")]
+    assert keys
+    for k in keys:
+        c[k] = [variant]
+    path.write_text(json.dumps(c))
+
+
+@pytest.mark.parametrize("case", G.cases(), ids=lambda c: f"{c[0]}-h{c[3]}-p{c[4]}")
+def test_two_pass_apply_equals_fused(case, tmp_path):
+    """The two-pass apply (extension rows of every band node once into a scratch vector, then
+    the stencil) gives the fused kernel's bits: the same extension-row arithmetic and the same
+    order of the neighbour sum. The fused kernel is the one checked against the oracle above."""
+    kind, params, d, h, p = case
+    lb = G.lib_band(kind, params, d, h, p)
+    op = cpm.Operator(lb, C_SHIFT)
+    x = torch.tensor(G.field(lb.active_keys, 11), dtype=torch.float64, device=DEV)
+    cache = tmp_path / "tune.json"
+    cpm.autotune(op, None, cache=cache)
+    outs = {}
+    for v in (0, 2):
+        _force_apply(cache, v)
+        r = cpm.autotune(op, None, cache=cache)
+        assert r["apply_variant"] == v and r["from_cache"] == 1
+        outs[v] = op.apply(x)
+    assert torch.equal(outs[0], outs[2])

@@ -58,7 +58,7 @@ def test_apply_variants_bit_identical(sphere, tmp_path, nrhs):
     x = _vec(b, nrhs, 11)
     cpm.autotune(op, None, nrhs=nrhs, cache=cache)
     outs = []
-    for v in ([0, 1] if nrhs == 1 else [0]):
+    for v in ([0, 1, 2] if nrhs == 1 else [0]):
         _force(cache, "apply|", [v])
         r = cpm.autotune(op, None, nrhs=nrhs, cache=cache)
         assert r["apply_variant"] == v and r["from_cache"] == 1
