@@ -60,6 +60,8 @@ def _args(argv=None):
                     help="row order of the batched leg (rcm: fewer iterations win on mixed surfaces)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-surface batched leg")
     ap.add_argument("--no-scaling", action="store_true", help="skip the other apply workloads")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the IMEX / two-level / biharmonic / fourth-order / open-surface timings")
     ap.add_argument("--oracle-worker", default=None, help=argparse.SUPPRESS)
     return ap.parse_args(argv)
 
@@ -350,7 +352,7 @@ def scaling_leg(cpm, inputs, torch, dev):
 
 
 def transpose_leg(cpm, inputs, torch, dev):
-    """A^T apply (neighbour gather, then the bucketed extension transpose) on the adjoint
+    """A^T apply (neighbour sums, then the brick-staged extension transpose) on the adjoint
     workload's torus, h = 0.01."""
     band = cpm.Band("torus", (1.0, 0.4), 3, 0.01, 3)
     op = cpm.Operator(band, 1.0)
@@ -360,15 +362,116 @@ def transpose_leg(cpm, inputs, torch, dev):
     ms_t = timed_applies(op, xs, ys, 20, st, torch, transpose=True)
     ms_f = timed_applies(op, xs, ys, 20, st, torch)
     nA, nG = band.n_active, band.n_ghost
-    # algorithmic bytes per active node of A^T: y (8) and the neighbour sums z over
+    # algorithmic bytes per active node of A^T: x (8) and the neighbour sums z over
     # Sigma_A u Sigma_G written and read (2 * 8 (1+g)), closest points (8 d (1+g)),
-    # bucket indices (4 (1+g)), output (8)
+    # per-brick row lists (about 5.4 entries of 4 B per row, (1+g) rows), output (8)
     g = nG / nA
-    b = 8 + 16 * (1 + g) + 24 * (1 + g) + 4 * (1 + g) + 8
+    b = 8 + 16 * (1 + g) + 24 * (1 + g) + 4 * 5.4 * (1 + g) + 8
     return {"workload": "torus R=1 r=0.4 h=0.01 p=3 (adjoint system)", "n_active": nA,
             "ms": round(ms_t, 4), "gnodes_per_s": round(nA / (ms_t * 1e-3) / 1e9, 3),
             "hbm_frac": round(b * nA / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_node": round(b, 2),
             "forward_ms": round(ms_f, 4)}
+
+
+def extensions_leg(cpm, inputs, surfaces, torch, dev):
+    """Timings of the widened rows: higher-order IMEX steps, the two-level preconditioner's
+    iterations, the shifted biharmonic, the fourth-order operator and an open surface."""
+    import numpy as np
+    out = {}
+    st = torch.cuda.current_stream()
+
+    def median_solve(op, f, pc, reps=3, **kw):
+        times = []
+        for _ in range(reps):
+            u, s = cpm.solve(op, f, pc=pc, **kw)
+            times.append(s["ms_total"])
+        return u, s, float(np.median(times))
+
+    # f1: ARK3(2)4L[2]SA against IMEX Euler, Gray-Scott on the torus h = 0.01, dt = 1
+    band = cpm.Band("torus", (1.0, 0.4), 3, 0.01, 3)
+    nA = band.n_active
+    imex = {"workload": "Gray-Scott torus R=1 r=0.4 h=0.01 p=3, mu=(2e-5,1e-5) F=0.04 k=0.06 dt=1, "
+                        "FP32 ORAS 256 boxes, stage solves mixed to 1e-8", "n_active": nA}
+    for scheme in ("euler", "ark3"):
+        ops = [cpm.Operator(band, cpm.imex_shift(scheme, 1.0, mu)) for mu in (2e-5, 1e-5)]
+        pcs = [cpm.Precond(o, kind="oras", n_parts=256, overlap=2.0, precision="fp32") for o in ops]
+        im = cpm.Imex(ops, pcs, scheme=scheme, dt=1.0, tune=True)
+        g = np.random.default_rng(5)
+        ws = [torch.tensor(1.0 - 0.5 * g.random(nA), dtype=torch.float64, device=dev),
+              torch.tensor(0.25 * g.random(nA), dtype=torch.float64, device=dev)]
+        im.step(ws, nsteps=2, rtol=1e-8, mode="mixed")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = im.step(ws, nsteps=5, rtol=1e-8, mode="mixed")
+        torch.cuda.synchronize()
+        imex[scheme] = {"ms_per_step": round((time.perf_counter() - t0) * 1e3 / 5, 3),
+                        "stage_iterations": [int(x["iterations"]) for x in stats]}
+        del im, pcs, ops, ws
+    out["imex"] = imex
+    del band
+    torch.cuda.empty_cache()
+
+    # f2: one level against coarse-first two levels, unit sphere h = 0.01, 256 boxes
+    band = cpm.Band("sphere", (1.0,), 3, 0.01, 3)
+    op = cpm.Operator(band, 1.0)
+    _, cp, _ = band.export()
+    f = torch.tensor(21.0 * inputs.sphere_y4(cp[:band.n_active], 2), dtype=torch.float64, device=dev)
+    two = {"workload": "unit sphere h=0.01 p=3 c=1, f=21*Y4, FP32 ORAS 256 boxes, mixed to 1e-8",
+           "n_active": band.n_active}
+    for coarse in ("none", "first"):
+        pc = cpm.Precond(op, kind="oras", n_parts=256, overlap=2.0, precision="fp32", coarse=coarse)
+        _, s, ms = median_solve(op, f, pc, rtol=1e-8, mode="mixed", max_it=20000)
+        two[coarse] = {"iterations": int(s["iterations"]), "ms": round(ms, 3), "converged": bool(s["converged"])}
+        del pc
+    out["two_level"] = two
+    del op, band, f
+    torch.cuda.empty_cache()
+
+    # f3: shifted biharmonic (1 + Lap^2) u = f on the unit sphere h = 0.05, and the
+    # fourth-order operator with quintic interpolation on the torus h = 0.01
+    band = cpm.Band("sphere", (1.0,), 3, 0.05, 3)
+    op = cpm.Operator(band, 1.0)
+    _, cp, _ = band.export()
+    f = torch.tensor(401.0 * inputs.sphere_y4(cp[:band.n_active], 2), dtype=torch.float64, device=dev)
+    pc = cpm.Precond(op, kind="oras", n_parts=8, overlap=2.0, precision="fp64", coarse="first")
+    _, s, ms = median_solve(op, f, pc, rtol=1e-8, max_it=40000, poly=(1.0, 0.0, 1.0), pc_power=2, restart=60,
+                            stagnation_cycles=400)
+    out["biharmonic"] = {"workload": "(1 + Lap^2) u = 401 Y4, unit sphere h=0.05 p=3, two-level ORAS of A(1) "
+                                     "applied twice, GMRES(60) to 1e-8", "n_active": band.n_active,
+                         "iterations": int(s["iterations"]), "ms": round(ms, 3), "converged": bool(s["converged"])}
+    del pc, op, band, f
+    band = cpm.Band("torus", (1.0, 0.4), 3, 0.01, 5, reach=2)
+    op = cpm.Operator(band, 1.0, order=4)
+    xs, ys = rotating(band, torch, dev, inputs)
+    timed_applies(op, xs, ys, 2, st, torch)
+    ms_a = timed_applies(op, xs, ys, 10, st, torch)
+    pc = cpm.Precond(op, kind="oras", n_parts=128, overlap=2.0, precision="fp32")
+    _, s, ms = median_solve(op, xs[0], pc, rtol=1e-8, mode="mixed", max_it=20000)
+    out["fourth_order"] = {"workload": "fourth-order operator, torus R=1 r=0.4 h=0.01 p=5 (reach-2 band), "
+                                       "two-kernel apply; solve of a N(0,1) right-hand side, FP32 ORAS 128 boxes "
+                                       "(second-order cubic operator), mixed to 1e-8",
+                           "n_active": band.n_active, "n_ghost": band.n_ghost, "apply_ms": round(ms_a, 4),
+                           "apply_gnodes_per_s": round(band.n_active / (ms_a * 1e-3) / 1e9, 3),
+                           "iterations": int(s["iterations"]), "solve_ms": round(ms, 3),
+                           "converged": bool(s["converged"])}
+    del xs, ys, pc, op, band
+    torch.cuda.empty_cache()
+
+    # f4: the hemisphere with the paper's mixed rim (Dirichlet where sin(3 phi) < -0.5)
+    fn = surfaces.hemisphere(1.0, lambda phi: np.sin(3.0 * phi) < -0.5)
+    t0 = time.perf_counter()
+    band = cpm.Band.from_closest_point(fn, 3, 0.01, 3, [-1.6] * 3, [1.6] * 3)
+    t_band = time.perf_counter() - t0
+    op = cpm.Operator(band, 1.0)
+    _, cp, _ = band.export()
+    f = torch.tensor(cp[:band.n_active, 2].copy(), dtype=torch.float64, device=dev)
+    pc = cpm.Precond(op, kind="oras", n_parts=64, overlap=2.0, precision="fp32")
+    _, s, ms = median_solve(op, f, pc, rtol=1e-8, mode="mixed", max_it=20000)
+    out["open_surface"] = {"workload": "hemisphere h=0.01 p=3 from a Python closest-point callback, mixed rim, "
+                                       "f = z, FP32 ORAS 64 boxes, mixed to 1e-8", "n_active": band.n_active,
+                           "band_build_s": round(t_band, 2), "iterations": int(s["iterations"]),
+                           "ms": round(ms, 3), "converged": bool(s["converged"])}
+    return out
 
 
 def main():
@@ -384,7 +487,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2110_06322_amd import _capi, cpm, gray_scott, inputs, workloads
+    from paper_2110_06322_amd import _capi, cpm, gray_scott, inputs, surfaces, workloads
     if not os.path.exists(_capi.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
@@ -478,6 +581,7 @@ def main():
     legs["batched"] = None if a.no_batched else batched_leg(cpm, workloads, torch, a.batched_ordering)
     oracle = finish_oracle(*worker) if worker is not None else {}
     legs["solve"] = sphere_leg(cpm, inputs, torch, dev, a, oracle.get("ref"))
+    legs["extensions"] = None if a.no_extensions else extensions_leg(cpm, inputs, surfaces, torch, dev)
 
     out = {
         "metric": METRIC,

@@ -1,12 +1,13 @@
 """Short, profiler-friendly driver: a fixed number of operator applies (or,
 with a fourth argument, ORAS preconditioner applies with that local row order
-and FP32 factors, 64 subdomains, overlap 2h, or with `transpose` transpose
-applies) on one workload and a device-to-device copy of known size (the copy
-calibrates the hardware byte counters against a kernel whose traffic is
-exactly known). Applies rotate through four input/output pairs, as the
-benchmark's do.
+and FP32 factors, 64 subdomains, overlap 2h, `transpose` transpose applies, or
+`order4` applies of the fourth-order operator on a band of reach 2, with the
+interpolation degree as a fifth argument, default 3) on one workload and a
+device-to-device copy of known size (the copy calibrates the hardware byte
+counters against a kernel whose traffic is exactly known). Applies rotate
+through four input/output pairs, as the benchmark's do.
 
-Usage: python -m paper_2110_06322_amd.profile_apply [sphere|torus] [h] [reps] [rcm|distance|transpose]
+Usage: python -m paper_2110_06322_amd.profile_apply [sphere|torus] [h] [reps] [rcm|distance|transpose|order4] [p]
 """
 from __future__ import annotations
 
@@ -22,12 +23,17 @@ def main():
     h = float(sys.argv[2]) if len(sys.argv) > 2 else 0.02
     reps = int(sys.argv[3]) if len(sys.argv) > 3 else 20
     params = (1.0,) if kind == "sphere" else (1.0, 0.4)
-    band = cpm.Band(kind, params, 3, h, 3)
-    op = cpm.Operator(band, 1.0)
+    mode = sys.argv[4] if len(sys.argv) > 4 else None
+    if mode == "order4":
+        p = int(sys.argv[5]) if len(sys.argv) > 5 else 3
+        band = cpm.Band(kind, params, 3, h, p, reach=2)
+        op = cpm.Operator(band, 1.0, order=4)
+    else:
+        band = cpm.Band(kind, params, 3, h, 3)
+        op = cpm.Operator(band, 1.0)
     xs = [torch.tensor(inputs.normal(10 + i, 0, band.active_keys), dtype=torch.float64, device="cuda")
           for i in range(4)]
     ys = [torch.empty_like(x) for x in xs]
-    mode = sys.argv[4] if len(sys.argv) > 4 else None
     if mode in ("rcm", "distance"):
         pc = cpm.Precond(op, kind="oras", n_parts=64, overlap=2.0, precision="fp32", ordering=mode)
         cpm.autotune(op, pc)
@@ -36,6 +42,9 @@ def main():
     elif mode == "transpose":
         for r in range(reps):
             op.apply_T(xs[r % 4], out=ys[r % 4])
+    elif mode == "order4":
+        for r in range(reps):
+            op.apply(xs[r % 4], out=ys[r % 4])
     else:
         cpm.autotune(op, None)
         for r in range(reps):
