@@ -93,7 +93,7 @@ typedef struct {
  * b = floor((cp(x)-lo)/h - (p-1)/2); Sigma_G = grid neighbours of Sigma_A not
  * in Sigma_A. gamma <= 0 selects h sqrt((d-1)((p+1)/2)^2 + (1+(p+1)/2)^2).
  * d in {2,3}, p in 1..5 (the fused second-order apply takes p <= 3; p = 4, 5
- * run the two-kernel path of cpm_operator_create_order). Errors: CPM_ERR_ARG (bad sizes / surface),
+ * run the two-kernel path, see cpm_operator_opts). Errors: CPM_ERR_ARG (bad sizes / surface),
  * CPM_ERR_BAND (a cube or neighbour leaves the grid box, or closure needs
  * more than one extra pass). lo/hi: host arrays of d doubles. */
 cpm_status cpm_band_build(const cpm_surface* surface, int32_t d, double h, int32_t p,
@@ -145,24 +145,45 @@ typedef struct cpm_operator_s cpm_operator;
 /* Uploads the band (closest points, brick map, tiles) to device memory
  * owned by the operator. The band may be destroyed afterwards. c > 0. */
 cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out);
-/* The stabilized operator of a chosen stencil order (Sec. 3.1.2: built-in
- * second- and fourth-order Laplace-Beltrami grid functions):
- *   order 2: A = (c + 2d/h^2) I - h^-2 O1 E (as cpm_operator_create);
- *   order 4: A = (c + 30d/(12h^2)) I - (12h^2)^-1 (16 O1 - O2) E, with O1 the
- *            sum over the 2d nearest grid neighbours and O2 over the 2d nodes
- *            two steps away along an axis (the five-point fourth-order second
- *            difference per axis, the node's own term un-extended);
- *            needs a band of reach 2 (cpm_band_build_reach).
- * Order 2 with p <= 3 runs the fused apply; order 4, or p = 4 or 5, runs two
- * kernels (every extension row into an operator-owned vector of (N_A+N_G) * 4
- * doubles, then the stencil). With degree-p interpolation the surface
- * solution's error is O(h^order) + O(h^(p-1)): order 4 needs p = 5 for fourth
- * order. Such operators support everything but the transposed apply (and so
- * transposed solves); a preconditioner built on them is the (O)RAS of the
- * second-order operator with degree min(p, 3) interpolation at the same
- * shift, a spectrally equivalent approximation. */
-cpm_status cpm_operator_create_order(const cpm_band* band, double c, int32_t order, void* stream,
-                                     cpm_operator** out);
+/* Operator options.
+ * order: the stabilized operator's stencil order (Sec. 3.1.2: built-in
+ *   second- and fourth-order Laplace-Beltrami grid functions):
+ *   2: A = (c + 2d/h^2) I - h^-2 O1 E (as cpm_operator_create);
+ *   4: A = (c + 30d/(12h^2)) I - (12h^2)^-1 (16 O1 - O2) E, with O1 the sum
+ *      over the 2d nearest grid neighbours and O2 over the 2d nodes two steps
+ *      away along an axis (the five-point fourth-order second difference per
+ *      axis, the node's own term un-extended); needs a band of reach 2
+ *      (cpm_band_build_reach).
+ *   Order 2 with p <= 3 runs the fused apply; order 4, or p = 4 or 5, runs two
+ *   kernels (every extension row into an operator-owned vector of
+ *   (N_A+N_G) * 4 doubles, then the stencil). With degree-p interpolation the
+ *   surface solution's error is O(h^order) + O(h^(p-1)): order 4 needs p = 5
+ *   for fourth order. Two-kernel operators support everything but the
+ *   transposed apply (and so transposed solves); a preconditioner built on
+ *   them is the (O)RAS of the second-order operator with degree min(p, 3)
+ *   interpolation at the same shift, a spectrally equivalent approximation.
+ * apply_lds_bytes: LDS budget per tile of the fused apply, 16384..65536
+ *   (0: 65536); tiles whose footprint does not fit are applied by a slower
+ *   kernel that reads x from global memory (same results, bit for bit). */
+typedef struct {
+  int32_t order;            /* 2 (default) or 4 */
+  int32_t apply_lds_bytes;  /* 0 (default) or 16384..65536 */
+} cpm_operator_opts;
+
+typedef struct {
+  int32_t order;
+  int32_t two_kernel;        /* 1: the two-kernel apply (order 4 or p > 3) */
+  int32_t two_pass;          /* 1: the two-pass variant of the fused apply is available */
+  int32_t apply_lds_bytes;
+  int32_t n_tiles;           /* tiles of the fused apply with active nodes */
+  int32_t n_fallback_tiles;  /* of which applied by the global-memory kernel */
+  int32_t apply_variant;     /* one-RHS kernel in use (see cpm_tune_result) */
+} cpm_operator_info;
+
+cpm_status cpm_operator_opts_default(cpm_operator_opts* opts);
+cpm_status cpm_operator_create_ex(const cpm_band* band, double c, const cpm_operator_opts* opts, void* stream,
+                                  cpm_operator** out);
+cpm_status cpm_operator_get_info(const cpm_operator* op, cpm_operator_info* info);
 /* Changes the shift c (> 0) of A = (c + 2d/h^2) I - h^-2 O E. Synchronizes
  * the device. Later cpm_solve calls use the new shift; a batch takes its
  * operators' shifts when it is created, so create batches after this call. */
@@ -504,8 +525,8 @@ int32_t cpm_version(void);
 int32_t cpm_device_count(void);
 /* sizeof of the public option / result structs, for bindings that declare
  * them by hand: 0 cpm_solve_opts, 1 cpm_solve_stats, 2 cpm_precond_opts,
- * 3 cpm_tune_result, 4 cpm_imex_opts, 5 cpm_band_info; -1 for any other
- * value. Host only. */
+ * 3 cpm_tune_result, 4 cpm_imex_opts, 5 cpm_band_info, 6 cpm_operator_opts,
+ * 7 cpm_operator_info; -1 for any other value. Host only. */
 int64_t cpm_abi_sizeof(int32_t which);
 
 #ifdef __cplusplus

@@ -55,6 +55,16 @@ class SolveOpts(C.Structure):
                 ("pc_power", C.c_int32)]
 
 
+class OperatorOpts(C.Structure):
+    _fields_ = [("order", C.c_int32), ("apply_lds_bytes", C.c_int32)]
+
+
+class OperatorInfo(C.Structure):
+    _fields_ = [("order", C.c_int32), ("two_kernel", C.c_int32), ("two_pass", C.c_int32),
+                ("apply_lds_bytes", C.c_int32), ("n_tiles", C.c_int32), ("n_fallback_tiles", C.c_int32),
+                ("apply_variant", C.c_int32)]
+
+
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("status", C.c_int32), ("relres", C.c_double), ("ms_total", C.c_double),
@@ -92,7 +102,9 @@ SIGNATURES = [
     ("cpm_band_export_interp", I32, [P, P, P]),
     ("cpm_band_destroy", None, [P]),
     ("cpm_operator_create", I32, [P, D, P, C.POINTER(P)]),
-    ("cpm_operator_create_order", I32, [P, D, I32, P, C.POINTER(P)]),
+    ("cpm_operator_opts_default", I32, [C.POINTER(OperatorOpts)]),
+    ("cpm_operator_create_ex", I32, [P, D, C.POINTER(OperatorOpts), P, C.POINTER(P)]),
+    ("cpm_operator_get_info", I32, [P, C.POINTER(OperatorInfo)]),
     ("cpm_operator_set_shift", I32, [P, D]),
     ("cpm_operator_get_shift", D, [P]),
     ("cpm_operator_n_active", I64, [P]),
@@ -130,7 +142,7 @@ SIGNATURES = [
 ]
 
 # ctypes mirrors of the public structs, in the order cpm_abi_sizeof numbers them
-ABI_STRUCTS = [SolveOpts, SolveStats, PrecondOpts, TuneResult, ImexOpts, BandInfo]
+ABI_STRUCTS = [SolveOpts, SolveStats, PrecondOpts, TuneResult, ImexOpts, BandInfo, OperatorOpts, OperatorInfo]
 
 _lib = None
 

@@ -193,19 +193,30 @@ class Band:
 
 class Operator:
     """A = (c + 2d/h^2) I - h^-2 O E on a band, resident on the GPU (order 4: the
-    fourth-order stencil, on a band of reach 2)."""
+    fourth-order stencil, on a band of reach 2; lds_bytes: LDS budget per tile of the
+    fused apply, 0 for the default 64 KiB)."""
 
-    def __init__(self, band: Band, c: float, stream=None, order: int = 2):
+    def __init__(self, band: Band, c: float, stream=None, order: int = 2, lds_bytes: int = 0):
         h_ = C.c_void_p()
-        if order == 2:
+        if order == 2 and lds_bytes == 0:
             check(lib().cpm_operator_create(band._h, float(c), _stream(stream), C.byref(h_)))
         else:
-            check(lib().cpm_operator_create_order(band._h, float(c), int(order), _stream(stream), C.byref(h_)))
+            o = _capi.OperatorOpts()
+            check(lib().cpm_operator_opts_default(C.byref(o)))
+            o.order = int(order)
+            o.apply_lds_bytes = int(lds_bytes)
+            check(lib().cpm_operator_create_ex(band._h, float(c), C.byref(o), _stream(stream), C.byref(h_)))
         self.order = order
         self._h = h_
         self.band = band
         self.n_active = band.n_active
         self.d, self.p, self.h = band.d, band.p, band.h
+
+    @property
+    def info(self) -> dict:
+        i = _capi.OperatorInfo()
+        check(lib().cpm_operator_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in _capi.OperatorInfo._fields_}
 
     @property
     def c(self) -> float:

@@ -33,6 +33,8 @@ int64_t cpm_abi_sizeof(int32_t which) {
     case 3: return (int64_t)sizeof(cpm_tune_result);
     case 4: return (int64_t)sizeof(cpm_imex_opts);
     case 5: return (int64_t)sizeof(cpm_band_info);
+    case 6: return (int64_t)sizeof(cpm_operator_opts);
+    case 7: return (int64_t)sizeof(cpm_operator_info);
     default: return -1;
   }
 }

@@ -137,6 +137,7 @@ struct cpm_operator_s {
   mutable cpm::DevBuf<double> d_v;
   // stencil order; generic: the two-kernel apply (order 4, or p > 3) through gen
   int order = 2;
+  int lds_bytes = (int)cpm::kApplyLdsBytes;   // LDS budget of the fused apply's tiles
   bool generic = false;
   int64_t gvoff = 0;
   cpm::GenericPlan gen;

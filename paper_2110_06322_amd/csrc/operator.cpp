@@ -338,11 +338,12 @@ void cpm::plan_pipe(std::vector<WorkItem>& work, const std::vector<int32_t>& cos
 // active nodes. Available when every extension-pass footprint fits the LDS budget.
 static void setup_two_pass(cpm_operator_s& op, const cpm_band_s& B) {
   const int d = B.d;
+  const size_t lds_bytes = (size_t)op.lds_bytes;
   std::vector<int32_t> fvolE;
   std::vector<FootBrick> fbrecE;
   std::vector<Job> jobsE;
   build_tiles(B, op.tilesE, fvolE, fbrecE, jobsE, false);
-  const int cap = (int)(kApplyLdsBytes / sizeof(double));
+  const int cap = (int)(lds_bytes / sizeof(double));
   std::vector<WorkItem> ework, eslow;
   int ucapE = 0;
   for (size_t t = 0; t < op.tilesE.size(); ++t) {
@@ -404,12 +405,17 @@ static void stencil_coefficients(int order, int d, double h, double c, double& d
   }
 }
 
-static cpm_status operator_create(const cpm_band* band, double c, int order, cpm_operator** out) {
+static cpm_status operator_create(const cpm_band* band, double c, const cpm_operator_opts& o,
+                                  cpm_operator** out) {
   try {
     if (!band || !out) fail(CPM_ERR_ARG, "null argument");
     *out = nullptr;
     if (!(c > 0) || !std::isfinite(c)) fail(CPM_ERR_ARG, "shift c must be positive and finite");
+    const int order = o.order;
     if (order != 2 && order != 4) fail(CPM_ERR_ARG, "order must be 2 or 4");
+    const int lds_bytes = o.apply_lds_bytes == 0 ? (int)kApplyLdsBytes : o.apply_lds_bytes;
+    if (lds_bytes < 16384 || lds_bytes > (int)kApplyLdsBytes)
+      fail(CPM_ERR_ARG, "apply_lds_bytes must be 0 or in 16384..65536");
     if (order == 4 && band->reach < 2) fail(CPM_ERR_ARG, "the fourth-order stencil needs a band of reach 2");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) fail(CPM_ERR_DEVICE, "no HIP device available");
@@ -417,6 +423,7 @@ static cpm_status operator_create(const cpm_band* band, double c, int order, cpm
     op->band = std::make_shared<cpm_band_s>(*band);
     op->c = c;
     op->order = order;
+    op->lds_bytes = lds_bytes;
     op->generic = order == 4 || band->p > 3;
     const cpm_band_s& B = *op->band;
     const int d = B.d;
@@ -485,7 +492,7 @@ static cpm_status operator_create(const cpm_band* band, double c, int order, cpm
       return CPM_OK;
     }
     // work lists: tiles whose footprint fits the LDS budget, the rest take the slow path
-    const int cap = (int)((kApplyLdsBytes - tile_lds_extra_bytes(d)) / sizeof(double));
+    const int cap = (int)(((size_t)lds_bytes - tile_lds_extra_bytes(d)) / sizeof(double));
     const int max_jobs = d == 3 ? 8 * 64 + 6 * 64 : 4 * 64 + 4 * 16;
     const int max_fb = kMaxFootBricks;
     std::vector<WorkItem> fast, slow;
@@ -538,15 +545,48 @@ static cpm_status operator_create(const cpm_band* band, double c, int order, cpm
   }
 }
 
-cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out) {
-  (void)stream;
-  return operator_create(band, c, 2, out);
+cpm_status cpm_operator_opts_default(cpm_operator_opts* o) {
+  if (!o) {
+    set_error("null argument");
+    return CPM_ERR_ARG;
+  }
+  std::memset(o, 0, sizeof(*o));
+  o->order = 2;
+  o->apply_lds_bytes = 0;
+  return CPM_OK;
 }
 
-cpm_status cpm_operator_create_order(const cpm_band* band, double c, int32_t order, void* stream,
-                                     cpm_operator** out) {
+cpm_status cpm_operator_create(const cpm_band* band, double c, void* stream, cpm_operator** out) {
   (void)stream;
-  return operator_create(band, c, order, out);
+  cpm_operator_opts o;
+  cpm_operator_opts_default(&o);
+  return operator_create(band, c, o, out);
+}
+
+cpm_status cpm_operator_create_ex(const cpm_band* band, double c, const cpm_operator_opts* opts, void* stream,
+                                  cpm_operator** out) {
+  (void)stream;
+  if (!opts) {
+    set_error("null argument");
+    return CPM_ERR_ARG;
+  }
+  return operator_create(band, c, *opts, out);
+}
+
+cpm_status cpm_operator_get_info(const cpm_operator* op, cpm_operator_info* info) {
+  if (!op || !info) {
+    set_error("null argument");
+    return CPM_ERR_ARG;
+  }
+  std::memset(info, 0, sizeof(*info));
+  info->order = op->order;
+  info->two_kernel = op->generic ? 1 : 0;
+  info->two_pass = op->twopass ? 1 : 0;
+  info->apply_lds_bytes = op->lds_bytes;
+  info->n_tiles = op->nwork + op->nfb;
+  info->n_fallback_tiles = op->nfb;
+  info->apply_variant = op->apply_variant;
+  return CPM_OK;
 }
 
 cpm_status cpm_operator_set_shift(cpm_operator* op, double c) {

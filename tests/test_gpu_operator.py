@@ -119,3 +119,32 @@ def test_two_pass_apply_equals_fused(case, tmp_path):
         assert r["apply_variant"] == v and r["from_cache"] == 1
         outs[v] = op.apply(x)
     assert torch.equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("case", [("sphere", (1.0,), 3, 0.05, 3), ("torus", (1.0, 0.4), 3, 0.05, 3),
+                                  ("sphere", (1.0,), 3, 0.1, 2)], ids=lambda c: f"{c[0]}-h{c[3]}-p{c[4]}")
+def test_fallback_tiles_equal_fused_and_oracle(case):
+    """A 16 KiB LDS budget sends the tiles whose footprint does not fit to the global-memory
+    kernel (k_apply_fallback): its results equal the fused kernels' bit for bit (same
+    contraction and stencil order) for 1, 2 and 4 right-hand sides, and the oracle's within
+    the apply bar."""
+    kind, params, d, h, p = case
+    lb = G.lib_band(kind, params, d, h, p)
+    ob, E, O, A, P = G.oracle(kind, params, d, h, p, C_SHIFT)
+    keys, pos = G.mapping(lb, ob)
+    op = cpm.Operator(lb, C_SHIFT)
+    small = cpm.Operator(lb, C_SHIFT, lds_bytes=16384)
+    inf, infs = op.info, small.info
+    print(f"{kind} h={h}: tiles {inf['n_tiles']}, fallback tiles {inf['n_fallback_tiles']} at 64 KiB, "
+          f"{infs['n_fallback_tiles']} at 16 KiB", flush=True)
+    assert infs["n_tiles"] == inf["n_tiles"] and infs["n_fallback_tiles"] > inf["n_fallback_tiles"]
+    assert infs["apply_lds_bytes"] == 16384 and inf["apply_lds_bytes"] == 65536
+    for nrhs in (1, 2, 4):
+        xs = [G.field(ob.active_keys, 70 + q) for q in range(nrhs)]
+        X = torch.tensor(np.stack([x[pos] for x in xs], axis=1).ravel(), dtype=torch.float64, device=DEV)
+        y_small = small.apply(X, nrhs=nrhs)
+        assert torch.equal(y_small, op.apply(X, nrhs=nrhs)), nrhs
+        Y = y_small.cpu().numpy().reshape(-1, nrhs)
+        for q in range(nrhs):
+            bound = G.apply_bound(ob, E, O, C_SHIFT, xs[q])
+            assert (np.abs(Y[:, q] - (A @ xs[q])[pos]) <= 256 * G.EPS * bound[pos]).all()
