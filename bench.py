@@ -260,6 +260,23 @@ def sphere_leg(cpm, inputs, torch, dev, a, ref):
                                            "max_levels": int(pc.info.max_levels),
                                            "schwarz_variant": tn["schwarz_variant"]}
         out[order] = res
+    # two-level (coarse-first) ORAS of the same partition, and with 512 boxes
+    two = {}
+    for nb in (64, 512):
+        for prec, mode in (("fp32", "mixed"), ("fp64", "fp64")):
+            if nb != 64 and mode == "fp64":
+                continue
+            pc = cpm.Precond(op, kind="oras", n_parts=nb, overlap=2.0, precision=prec, ordering=a.ordering,
+                             coarse="first")
+            cpm.autotune(op, pc, cache=a.tune_cache)
+            times = []
+            for _ in range(3):
+                u, st = cpm.solve(op, f, pc=pc, rtol=1e-8, mode=mode, max_it=20000)
+                times.append(st["ms_total"])
+            two[f"{mode}_{nb}_boxes"] = {"ms": round(float(np.median(times)), 3), "iterations": int(st["iterations"]),
+                                         "converged": bool(st["converged"])}
+            del pc
+    out["two_level"] = two
     m = out[a.ordering]
     out["mixed_ms"], out["fp64_ms"] = m["mixed"]["ms"], m["fp64"]["ms"]
     out["speedup_mixed"] = round(m["fp64"]["ms"] / m["mixed"]["ms"], 3)
@@ -315,6 +332,16 @@ def batched_leg(cpm, workloads, torch, ordering):
     print(f"batched: mixed {ms1:.0f} ms", file=sys.stderr, flush=True)
     ms64, st64, tune64 = timed([pc for pc in pcs64 for _ in range(4)], "fp64")
     print(f"batched: fp64 {ms64:.0f} ms", file=sys.stderr, flush=True)
+    del pcs64
+    # the same systems with the two-level (coarse-first) FP32 preconditioners
+    t0 = time.perf_counter()
+    pcs2 = workloads.preconditioners([i.op for i in insts], [i.meta["n_sub"] for i in insts], "fp32", ordering,
+                                     coarse="first")
+    t_setup2 = time.perf_counter() - t0
+    ms2, st2, _ = timed([pc for pc in pcs2 for _ in range(4)], "mixed")
+    print(f"batched: two-level mixed {ms2:.0f} ms", file=sys.stderr, flush=True)
+    del pcs2
+    its2 = [s["iterations"] for s in st2]
     its1 = [s["iterations"] for s in st1]
     its64 = [s["iterations"] for s in st64]
     return {"workload": "48 surfaces (16 spheres, 16 ellipsoids, 16 tori), h cyclic 0.04/0.02/0.01, p=3, "
@@ -329,6 +356,10 @@ def batched_leg(cpm, workloads, torch, ordering):
             "max_relres_fp64": float(max(s["relres"] for s in st64)),
             "converged": bool(all(s["converged"] for s in st1 + st64)),
             "setup_s": round(t_setup, 2), "fp64_setup_s": round(t_setup64, 2),
+            "two_level": {"mixed_ms": round(ms2, 2), "iterations_max": int(max(its2)),
+                          "iterations_mean": round(float(np.mean(its2)), 1),
+                          "max_relres": float(max(s["relres"] for s in st2)),
+                          "converged": bool(all(s["converged"] for s in st2)), "setup_s": round(t_setup2, 2)},
             "tuning": tune1, "tuning_fp64": tune64}
 
 
@@ -367,10 +398,23 @@ def transpose_leg(cpm, inputs, torch, dev):
     # per-brick row lists (about 5.4 entries of 4 B per row, (1+g) rows), output (8)
     g = nG / nA
     b = 8 + 16 * (1 + g) + 24 * (1 + g) + 4 * 5.4 * (1 + g) + 8
-    return {"workload": "torus R=1 r=0.4 h=0.01 p=3 (adjoint system)", "n_active": nA,
-            "ms": round(ms_t, 4), "gnodes_per_s": round(nA / (ms_t * 1e-3) / 1e9, 3),
-            "hbm_frac": round(b * nA / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_node": round(b, 2),
-            "forward_ms": round(ms_f, 4)}
+    out = {"workload": "torus R=1 r=0.4 h=0.01 p=3 (adjoint system)", "n_active": nA,
+           "ms": round(ms_t, 4), "gnodes_per_s": round(nA / (ms_t * 1e-3) / 1e9, 3),
+           "hbm_frac": round(b * nA / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_node": round(b, 2),
+           "forward_ms": round(ms_f, 4)}
+    # forward and adjoint solves of the config-4 system: RAS 128 boxes (FP32 factors, of A and
+    # of A^T), mixed precision to 1e-8
+    import numpy as np
+    for name, tr in (("forward_solve", False), ("adjoint_solve", True)):
+        pc = cpm.Precond(op, kind="ras", n_parts=128, overlap=2.0, precision="fp32", transpose=tr)
+        times = []
+        for _ in range(3):
+            _, s = cpm.solve(op, xs[0], pc=pc, rtol=1e-8, mode="mixed", max_it=20000, transpose=tr)
+            times.append(s["ms_total"])
+        out[name] = {"ms": round(float(np.median(times)), 3), "iterations": int(s["iterations"]),
+                     "converged": bool(s["converged"])}
+        del pc
+    return out
 
 
 def extensions_leg(cpm, inputs, surfaces, torch, dev):

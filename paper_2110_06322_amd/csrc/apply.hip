@@ -190,6 +190,76 @@ __device__ void erow_global(const DevInst& I, const double* cp, const double* __
   }
 }
 
+// Sum over one run of the last axis of a cube: acc[r] = sum_a w[a] x[node(g + a e_last)][r].
+// All cube nodes are active, so inside one brick the run's indices are consecutive: the
+// run costs one brick lookup plus one per brick boundary it crosses. Returns false when a
+// node is missing (impossible on a closed band; the run then contributes nothing).
+template <int D, int P, int NRHS>
+__device__ __forceinline__ bool run_sum(const DevInst& I, int* g, const double* w, const double* __restrict__ x,
+                                        double* acc) {
+  constexpr int E = kEdge<D>;
+  const int g0 = g[D - 1];
+  int zl = g0 & (E - 1);
+  int j = node_at<D>(I, g);
+  bool ok = j >= 0 && j < I.nA;
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r) acc[r] = 0.0;
+#pragma unroll
+  for (int a = 0; a <= P; ++a) {
+    if (a > 0) {
+      if (++zl == E) {
+        zl = 0;
+        g[D - 1] = g0 + a;
+        j = node_at<D>(I, g);
+        ok = ok && j >= 0 && j < I.nA;
+      } else {
+        ++j;
+      }
+    }
+    if (ok) {
+      const double* xp = x + (I.vec_off + j) * NRHS;
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) acc[r] += w[a] * xp[r];
+    }
+  }
+  return ok;
+}
+
+// Extension row through global memory for the two-kernel apply: erow_global's weights and
+// summation order, with the cube's nodes located run by run (run_sum).
+template <int D, int P, int NRHS>
+__device__ void erow_runs(const DevInst& I, const double* cp, const double* __restrict__ x, double* out) {
+  int b[3] = {0, 0, 0};
+  double w[D][P + 1];
+  erow_weights<D, P>(cp, b, w);
+#pragma unroll
+  for (int r = 0; r < NRHS; ++r) out[r] = 0.0;
+  if (D == 3) {
+    for (int a0 = 0; a0 <= P; ++a0) {
+      double acc1[NRHS];
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) acc1[r] = 0.0;
+      for (int a1 = 0; a1 <= P; ++a1) {
+        int g[3] = {b[0] + a0, b[1] + a1, b[2]};
+        double acc2[NRHS];
+        if (!run_sum<3, P, NRHS>(I, g, w[2], x, acc2)) continue;
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) acc1[r] += w[1][a1] * acc2[r];
+      }
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) out[r] += w[0][a0] * acc1[r];
+    }
+  } else {
+    for (int a0 = 0; a0 <= P; ++a0) {
+      int g[3] = {b[0] + a0, b[1], 0};
+      double acc1[NRHS];
+      if (!run_sum<2, P, NRHS>(I, g, w[1], x, acc1)) continue;
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) out[r] += w[0][a0] * acc1[r];
+    }
+  }
+}
+
 // Extension row evaluated from the LDS footprint box U (node (x, y, z) of the
 // grid at U[x*s0 + y*s1 + z - fbase]; 2-D: U[x*s0 + y - fbase]).
 template <int D, int P>
@@ -721,23 +791,22 @@ __global__ void __launch_bounds__(256) k_apply_fallback(const DevInst* __restric
   }
 }
 
-// Extension pass of the two-pass apply for tiles whose footprint exceeds the LDS
-// budget: each node of the tile's bricks evaluates its extension row with index
-// lookups into the global vector (wavefront = brick, lane = node).
+// Extension pass, slow path: the bricks of the extension-pass tiles whose footprint
+// exceeds the LDS budget (one wavefront per brick, lane = node, rows evaluated from
+// global memory); each item names its instance and brick.
 template <int D, int P>
-__global__ void __launch_bounds__(512) k_extend_tiles(const DevInst* __restrict__ insts,
-                                                      const WorkItem* __restrict__ work, int nwork,
-                                                      const double* __restrict__ x, double* __restrict__ v,
-                                                      Gate gate) {
-  const int w = blockIdx.x;
-  if (w >= nwork) return;
-  const WorkItem wi = work[w];
+__global__ void __launch_bounds__(256) k_extend_bricks(const DevInst* __restrict__ insts,
+                                                       const WorkItem* __restrict__ items, int nitems,
+                                                       const double* __restrict__ x, double* __restrict__ v,
+                                                       Gate gate) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nitems) return;
+  const WorkItem wi = items[w];
   if (gate_skip(gate, wi.inst)) return;
   const DevInst& I = insts[wi.inst];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
-  if (wave >= (1 << D)) return;
-  const int id = I.tiles[wi.idx].bid[wave];
-  if (id < 0) return;
+  const int lane = lane_id();
+  const int id = wi.idx;
+  if (id < 0 || id >= I.nbricks) return;
   const uint64_t mA = I.maskA[id], mG = I.maskG[id];
   int node = -1;
   if ((mA >> lane) & 1ull) node = I.offA[id] + mbcnt64(mA);
@@ -932,7 +1001,7 @@ __global__ void __launch_bounds__(256) k_gen_extend(DevInst I, const double* __r
   if (j >= I.nA + I.nG) return;
   double t[3], out[R];
   load_tcp<D>(I, j, t);
-  erow_global<D, P, R>(I, t, x, out);
+  erow_runs<D, P, R>(I, t, x, out);
   const double sg = I.esgn ? I.esgn[j] : 1.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) v[(int64_t)j * R + r] = sg * out[r];
@@ -1008,7 +1077,25 @@ static hipError_t launch_generic_t(const GenericPlan& G, const double* x, double
     const int n = I.nA + I.nG;
     if (n == 0 || I.ntbricks == 0) continue;
     double* v = G.vscr + G.voff[i] * R;
-    hipLaunchKernelGGL((k_gen_extend<D, P, R>), dim3((n + 255) / 256), dim3(256), 0, s, I, x, v, gate, i);
+    bool done = false;
+    if constexpr (R == 1 && P <= 3) {
+      const GenericEPass* e = G.epass ? &G.epass[i] : nullptr;
+      if (e && e->dinst && (e->pipe.nplan > 0 || e->nfb > 0)) {
+        // the extension pass's tiles name instance 0: gate them by this instance only in a
+        // batch of one (a batch's other instances keep their own activity flags)
+        const Gate eg = G.ninst == 1 ? gate : Gate{};
+        if (e->pipe.nplan > 0)
+          hipLaunchKernelGGL((k_apply_pipe<D, P, true>), dim3(e->pipe.nplan), dim3(512),
+                             (size_t)e->ucap * sizeof(double), s, e->dinst, e->pipe.wtiles, e->pipe.plan, e->ucap,
+                             x, G.vscr, eg);
+        if (e->nfb > 0)
+          hipLaunchKernelGGL((k_extend_bricks<D, P>), dim3((e->nfb + 3) / 4), dim3(256), 0, s, e->dinst, e->fb,
+                             e->nfb, x, G.vscr, eg);
+        done = true;
+      }
+    }
+    if (!done)
+      hipLaunchKernelGGL((k_gen_extend<D, P, R>), dim3((n + 255) / 256), dim3(256), 0, s, I, x, v, gate, i);
     if (I.order == 4)
       hipLaunchKernelGGL((k_gen_stencil<D, R, 4>), dim3((I.ntbricks + 3) / 4), dim3(256), 0, s, I, v, x, y, gate, i);
     else
@@ -1071,8 +1158,8 @@ static hipError_t launch_apply_t(const ApplyArgs& A, int variant, const double* 
       hipLaunchKernelGGL((k_apply_pipe<D, P, true>), dim3(A.pipeE.nplan), dim3(512), shmE, s, A.insts, A.pipeE.wtiles,
                          A.pipeE.plan, A.ucapE, x, A.vscr, gate);
     if (A.nfbE > 0)
-      hipLaunchKernelGGL((k_extend_tiles<D, P>), dim3(A.nfbE), dim3(512), 0, s, A.insts, A.fbE, A.nfbE, x, A.vscr,
-                         gate);
+      hipLaunchKernelGGL((k_extend_bricks<D, P>), dim3((A.nfbE + 3) / 4), dim3(256), 0, s, A.insts, A.fbE, A.nfbE, x,
+                         A.vscr, gate);
     if (A.nswork > 0)
       hipLaunchKernelGGL((k_stencil<D>), dim3(A.nswork), dim3(512), 0, s, A.insts, A.swork, A.nswork, A.vscr, x, y,
                          gate);

@@ -140,6 +140,7 @@ struct cpm_operator_s {
   int lds_bytes = (int)cpm::kApplyLdsBytes;   // LDS budget of the fused apply's tiles
   bool generic = false;
   int64_t gvoff = 0;
+  cpm::GenericEPass gep;
   cpm::GenericPlan gen;
   cpm::ApplyArgs apply_args() const {
     cpm::ApplyArgs A;

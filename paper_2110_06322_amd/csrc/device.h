@@ -117,11 +117,23 @@ struct PipeWork {
 // Two-kernel apply of operators the fused kernels do not cover (fourth-order stencil, or
 // interpolation degree above 3): host copies of the instances, the node offset of each
 // instance's extension values in the scratch vector (times nrhs), and that vector.
+struct GenericEPass {
+  // one right-hand side, p <= 3: the extension pass of the two-pass apply (LDS tiles) instead
+  // of the per-row global gathers; its tiles name instance 0, so dinst points at this
+  // instance's record in device memory and v is written at vnode_off + node
+  const DevInst* dinst = nullptr;   // device
+  PipeWork pipe;
+  int ucap = 0;
+  const WorkItem* fb = nullptr;     // bricks of the extension-pass tiles whose footprint exceeds the LDS budget
+  int nfb = 0;
+};
+
 struct GenericPlan {
   const DevInst* inst = nullptr;    // host array of ninst
-  const int64_t* voff = nullptr;    // host array of ninst
+  const int64_t* voff = nullptr;    // host array of ninst (equal to each instance's vnode_off)
   int ninst = 0;
   double* vscr = nullptr;           // device, sum of (nA + nG) over the instances, times nrhs
+  const GenericEPass* epass = nullptr;   // host array of ninst, or null
 };
 
 struct ApplyArgs {
@@ -139,7 +151,7 @@ struct ApplyArgs {
   int ucapE = 0;
   const WorkItem* swork = nullptr;
   int nswork = 0;
-  const WorkItem* fbE = nullptr;   // extension-pass tiles whose footprint exceeds the LDS budget
+  const WorkItem* fbE = nullptr;   // bricks of the extension-pass tiles whose footprint exceeds the LDS budget
   int nfbE = 0;
   double* vscr = nullptr;
 };

@@ -350,7 +350,9 @@ static void setup_two_pass(cpm_operator_s& op, const cpm_band_s& B) {
     const DevTile& tl = op.tilesE[t];
     if (tl.job_cnt == 0) continue;
     if (fvolE[t] > cap || tl.job_cnt > 512 || tl.fb_cnt > kMaxFootBricks) {
-      eslow.push_back(WorkItem{0, (int32_t)t});
+      // slow path: the tile's bricks, one wavefront each (k_extend_bricks)
+      for (int q = 0; q < 8; ++q)
+        if (tl.bid[q] >= 0) eslow.push_back(WorkItem{0, tl.bid[q]});
       continue;
     }
     ework.push_back(WorkItem{0, (int32_t)t});
@@ -481,8 +483,20 @@ static cpm_status operator_create(const cpm_band* band, double c, const cpm_oper
     I.vec_off = 0;
     op->d_inst.upload(&I, 1);
     if (op->generic) {
-      // two-kernel apply: extension values of up to four right-hand sides
+      // two-kernel apply: extension values of up to four right-hand sides; with p <= 3 the
+      // one-RHS extension pass runs on LDS tiles (the two-pass apply's extension pass)
       op->d_v.alloc((size_t)n * 4);
+      if (B.p <= 3) {
+        setup_two_pass(*op, B);
+        if (op->twopass) {
+          op->gep.dinst = op->d_inst.p;
+          op->gep.pipe = PipeWork{op->d_wtilesE.p, op->d_planE.p, op->nplanE};
+          op->gep.ucap = op->ucapE;
+          op->gep.fb = op->d_fbE.p;
+          op->gep.nfb = (int)op->h_fbE.size();
+          op->gen.epass = &op->gep;
+        }
+      }
       op->gvoff = 0;
       op->gen.inst = &op->I;
       op->gen.voff = &op->gvoff;

@@ -35,6 +35,7 @@ struct cpm_batch_s {
   // two-kernel apply (operators of stencil order 4 or degree p > 3): per-instance launches
   bool generic = false;
   std::vector<int64_t> gvoff;
+  std::vector<GenericEPass> gep;
   DevBuf<double> gv;
   GenericPlan gen;
   DevBuf<WorkItem> d_work, d_fb;
@@ -194,6 +195,18 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
     Bt.gen.voff = Bt.gvoff.data();
     Bt.gen.ninst = n;
     Bt.gen.vscr = Bt.gv.p;
+    // LDS extension passes of the instances that have them (their tiles name instance 0:
+    // point each at its own record of the batch)
+    Bt.gep.assign(n, GenericEPass{});
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+      if (Bt.hinst[i].vnode_off != Bt.gvoff[i]) fail(CPM_ERR_STATE, "batch node offsets disagree");
+      if (!ops[i]->gen.epass) continue;
+      Bt.gep[i] = ops[i]->gep;
+      Bt.gep[i].dinst = Bt.d_insts.p + i;
+      any = true;
+    }
+    Bt.gen.epass = any ? Bt.gep.data() : nullptr;
   }
   Bt.d_shift.upload(Bt.shift);
   {

@@ -60,11 +60,12 @@ SETUP_THREADS = 4
 
 
 def preconditioners(ops, n_parts, precision="fp32", ordering="rcm", kind="oras", overlap=2.0,
-                    threads=SETUP_THREADS):
+                    threads=SETUP_THREADS, coarse="none"):
     """(O)RAS preconditioners for several operators, built concurrently, in order."""
     def one(args):
         op, ns = args
-        return cpm.Precond(op, kind=kind, n_parts=ns, overlap=overlap, precision=precision, ordering=ordering)
+        return cpm.Precond(op, kind=kind, n_parts=ns, overlap=overlap, precision=precision, ordering=ordering,
+                           coarse=coarse)
     with ThreadPoolExecutor(max(1, threads)) as ex:
         return list(ex.map(one, zip(ops, n_parts)))
 
