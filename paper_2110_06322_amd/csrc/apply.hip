@@ -814,7 +814,7 @@ __global__ void __launch_bounds__(256) k_extend_bricks(const DevInst* __restrict
   if (node < 0) return;
   double cp[3], out[1];
   load_tcp<D>(I, node, cp);
-  erow_global<D, P, 1>(I, cp, x, out);
+  erow_runs<D, P, 1>(I, cp, x, out);
   if (I.esgn) out[0] *= I.esgn[node];
   v[I.vnode_off + node] = out[0];
 }
@@ -1078,7 +1078,7 @@ static hipError_t launch_generic_t(const GenericPlan& G, const double* x, double
     if (n == 0 || I.ntbricks == 0) continue;
     double* v = G.vscr + G.voff[i] * R;
     bool done = false;
-    if constexpr (R == 1 && P <= 3) {
+    if constexpr (R == 1) {
       const GenericEPass* e = G.epass ? &G.epass[i] : nullptr;
       if (e && e->dinst && (e->pipe.nplan > 0 || e->nfb > 0)) {
         // the extension pass's tiles name instance 0: gate them by this instance only in a
@@ -1206,6 +1206,12 @@ int apply_pipe_grid(int d, int p, int nwork, int ucap, bool extension_pass) {
                           : pipe_grid(nwork, (size_t)ucap * sizeof(double) + tile_lds_extra<D>(),          \
                                       (const void*)k_apply_pipe<D, P, false>);
   CPM_CASE(3, 3) CPM_CASE(3, 2) CPM_CASE(3, 1) CPM_CASE(2, 3) CPM_CASE(2, 2) CPM_CASE(2, 1)
+#undef CPM_CASE
+  // degrees 4 and 5 have only the extension pass (the two-kernel apply)
+#define CPM_CASE(D, P)                                                                             \
+  if (d == D && p == P)                                                                            \
+    return extension_pass ? pipe_grid(nwork, (size_t)ucap * sizeof(double), (const void*)k_apply_pipe<D, P, true>) : 0;
+  CPM_CASE(3, 5) CPM_CASE(3, 4) CPM_CASE(2, 5) CPM_CASE(2, 4)
 #undef CPM_CASE
   return 0;
 }

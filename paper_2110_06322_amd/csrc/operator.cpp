@@ -32,15 +32,17 @@ void local_of(int d, int bit, int* l) {
 // of their interpolation cubes (the LDS footprint) and the Sigma_A bricks
 // overlapping that footprint.
 // halo = false: the extension pass of the two-pass apply (jobs are the tile's own
-// band nodes only; their slots are unused).
+// band nodes only; their slots are unused). per_brick: every brick is a tile of its own
+// (extension pass only: the footprint of one brick's rows always fits the LDS budget).
 void build_tiles(const cpm_band_s& B, std::vector<DevTile>& tiles, std::vector<int32_t>& fvol,
-                 std::vector<FootBrick>& fbrec, std::vector<Job>& jobs, bool halo = true) {
+                 std::vector<FootBrick>& fbrec, std::vector<Job>& jobs, bool halo = true,
+                 bool per_brick = false) {
   bool orphan = false;
   const int d = B.d, E = brick_edge(d), T = 2 * E, P = B.p, W = T + 2;
   const int64_t nb = B.nbricks();
   std::vector<int64_t> start;
   for (int64_t i = 0; i < nb; ++i) {
-    bool fresh = i == 0;
+    bool fresh = i == 0 || per_brick;
     if (!fresh)
       for (int k = 0; k < d; ++k)
         if ((B.bcoord[i * 3 + k] >> 1) != (B.bcoord[(i - 1) * 3 + k] >> 1)) fresh = true;
@@ -346,17 +348,51 @@ static void setup_two_pass(cpm_operator_s& op, const cpm_band_s& B) {
   const int cap = (int)(lds_bytes / sizeof(double));
   std::vector<WorkItem> ework, eslow;
   int ucapE = 0;
-  for (size_t t = 0; t < op.tilesE.size(); ++t) {
+  std::vector<uint8_t> split(B.nbricks(), 0);   // bricks of tiles whose footprint does not fit
+  bool any_split = false;
+  const size_t ntiles = op.tilesE.size();
+  auto fits = [&](const DevTile& tl, int32_t vol) {
+    return vol <= cap && tl.job_cnt <= 512 && tl.fb_cnt <= kMaxFootBricks;
+  };
+  for (size_t t = 0; t < ntiles; ++t) {
     const DevTile& tl = op.tilesE[t];
     if (tl.job_cnt == 0) continue;
-    if (fvolE[t] > cap || tl.job_cnt > 512 || tl.fb_cnt > kMaxFootBricks) {
-      // slow path: the tile's bricks, one wavefront each (k_extend_bricks)
+    if (!fits(tl, fvolE[t])) {
       for (int q = 0; q < 8; ++q)
-        if (tl.bid[q] >= 0) eslow.push_back(WorkItem{0, tl.bid[q]});
+        if (tl.bid[q] >= 0) { split[tl.bid[q]] = 1; any_split = true; }
       continue;
     }
     ework.push_back(WorkItem{0, (int32_t)t});
     ucapE = std::max(ucapE, fvolE[t]);
+  }
+  if (any_split) {
+    // the bricks of oversized tiles as tiles of their own, appended to the list (their
+    // records follow the first build's); a brick that still does not fit takes the slow
+    // path (k_extend_bricks)
+    std::vector<DevTile> tb;
+    std::vector<int32_t> fvb;
+    std::vector<FootBrick> fbb;
+    std::vector<Job> jbb;
+    build_tiles(B, tb, fvb, fbb, jbb, false, true);
+    const int32_t fb0 = (int32_t)fbrecE.size(), jb0 = (int32_t)jobsE.size();
+    fbrecE.insert(fbrecE.end(), fbb.begin(), fbb.end());
+    jobsE.insert(jobsE.end(), jbb.begin(), jbb.end());
+    for (size_t t = 0; t < tb.size(); ++t) {
+      DevTile tl = tb[t];
+      int32_t id = -1;
+      for (int q = 0; q < 8; ++q)
+        if (tl.bid[q] >= 0) id = tl.bid[q];
+      if (id < 0 || !split[id] || tl.job_cnt == 0) continue;
+      if (!fits(tl, fvb[t])) {
+        eslow.push_back(WorkItem{0, id});
+        continue;
+      }
+      tl.fb_off += fb0;
+      tl.job_off += jb0;
+      ework.push_back(WorkItem{0, (int32_t)op.tilesE.size()});
+      op.tilesE.push_back(tl);
+      ucapE = std::max(ucapE, fvb[t]);
+    }
   }
   std::vector<WorkItem> swork;
   for (size_t t = 0; t < op.tiles.size(); ++t) {
@@ -483,10 +519,10 @@ static cpm_status operator_create(const cpm_band* band, double c, const cpm_oper
     I.vec_off = 0;
     op->d_inst.upload(&I, 1);
     if (op->generic) {
-      // two-kernel apply: extension values of up to four right-hand sides; with p <= 3 the
-      // one-RHS extension pass runs on LDS tiles (the two-pass apply's extension pass)
+      // two-kernel apply: extension values of up to four right-hand sides; the one-RHS
+      // extension pass runs on LDS tiles (the two-pass apply's extension pass)
       op->d_v.alloc((size_t)n * 4);
-      if (B.p <= 3) {
+      {
         setup_two_pass(*op, B);
         if (op->twopass) {
           op->gep.dinst = op->d_inst.p;
