@@ -1,6 +1,7 @@
 """Additive Runge-Kutta IMEX time stepping for surface reaction-diffusion systems
-(paper Sec. 1, eq. rdsys; Sec. 4.1.3 heat equation eq. heat / eq. htForce and
-Sec. 4.1.5 Gray-Scott eq. grayscott, whose default PETSc integrator is the
+(paper Sec. 1, eq. rdsys; Sec. 4.1.3 heat equation eq. heat / eq. htForce,
+Sec. 4.1.4 FitzHugh-Nagumo eq. fitznag, Sec. 4.1.5 Gray-Scott eq. grayscott and
+Sec. 4.1.6 Schnackenberg eq. schnack, whose default PETSc integrator is the
 third-order additive Runge-Kutta IMEX scheme).
 
 For w_t = F_E(t, w) + mu Lap_S w, with the diffusion implicit and the rest
@@ -115,4 +116,24 @@ def heat_FE(g_cos, g_sin):
     f(x, t) = cos(t) g_cos(x) + sin(t) g_sin(x) (eq. htForce has this form)."""
     def fe(t, ws):
         return [np.cos(t) * g_cos + np.sin(t) * g_sin]
+    return fe
+
+
+def fitzhugh_nagumo_FE(a=0.1, eps=0.01, beta=0.5):
+    """Explicit terms of the FitzHugh-Nagumo system (Sec. 4.1.4, eq. fitznag):
+    u_t - D_u Lap u = (a - u)(u - 1) u - v,  v_t - D_v Lap v = eps (beta u - v)
+    (the paper's values a = 0.1, eps = 0.01, beta = 0.5)."""
+    def fe(t, ws):
+        u, v = ws
+        return [(a - u) * (u - 1.0) * u - v, eps * (beta * u - v)]
+    return fe
+
+
+def schnackenberg_FE(delta1=0.003, delta2=0.7, lam=0.06):
+    """Explicit terms of the Schnackenberg system (Sec. 4.1.6, eq. schnack):
+    u_t - D_u Lap u = delta1 - u + u^2 v + lam v,  v_t - D_v Lap v = delta2 - u^2 v - lam v."""
+    def fe(t, ws):
+        u, v = ws
+        u2v = u * u * v
+        return [delta1 - u + u2v + lam * v, delta2 - u2v - lam * v]
     return fe

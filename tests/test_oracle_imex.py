@@ -164,3 +164,45 @@ def test_heat_manufactured_circle():
             t += dt
         errs.append(np.abs(ws[0] - np.sin(1.0) * s).max())
     assert errs[1] < errs[0] / 3 and errs[1] < 2e-3, errs
+
+
+def _uniform(fe, w0, scheme, dt, T, mus):
+    ws = [np.array([w0[0]]), np.array([w0[1]])]
+    t = 0.0
+    for _ in range(int(round(T / dt))):
+        ws = imex.ark_step(t, ws, dt, mus, fe, lambda x: np.zeros_like(x), lambda s, gdm, rhs: rhs, scheme)
+        t += dt
+    return np.array([ws[0][0], ws[1][0]])
+
+
+@pytest.mark.parametrize("model", ["fitzhugh_nagumo", "schnackenberg"])
+def test_order_on_uniform_fhn_and_schnackenberg(model):
+    """Spatially uniform states follow the reaction ODE (Lap 1 = 0): ARK3 converges to a
+    DOP853 integration of the paper's reaction terms at third order."""
+    if model == "fitzhugh_nagumo":
+        fe, w0, T, mus = imex.fitzhugh_nagumo_FE(), (0.6, 0.1), 20.0, (1e-4, 1e-7)
+        rhs = lambda t, y: [(0.1 - y[0]) * (y[0] - 1.0) * y[0] - y[1], 0.01 * (0.5 * y[0] - y[1])]
+        dts = (0.5, 0.25, 0.125)
+    else:
+        fe, w0, T, mus = imex.schnackenberg_FE(), (0.5, 2.0), 10.0, (1e-3, 1e-1)
+        rhs = lambda t, y: [0.003 - y[0] + y[0] ** 2 * y[1] + 0.06 * y[1], 0.7 - y[0] ** 2 * y[1] - 0.06 * y[1]]
+        dts = (0.2, 0.1, 0.05)
+    ref = si.solve_ivp(rhs, (0, T), list(w0), method="DOP853", rtol=1e-13, atol=1e-15).y[:, -1]
+    e = [np.abs(_uniform(fe, w0, "ark3", dt, T, mus) - ref).max() for dt in dts]
+    rates = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    print(model, e, rates)
+    assert (np.abs(rates - 3) < 0.4).all(), (e, rates)
+
+
+def test_reaction_fixed_points():
+    """(0, 0) is a fixed point of FitzHugh-Nagumo; (d1 + d2, d2 / ((d1 + d2)^2 + lam)) of
+    Schnackenberg (the two equations' sum gives u, the second then v): one ARK3 step keeps
+    them to rounding."""
+    fe = imex.fitzhugh_nagumo_FE()
+    out = _uniform(fe, (0.0, 0.0), "ark3", 1.0, 1.0, (1e-4, 1e-7))
+    assert np.abs(out).max() == 0.0
+    d1, d2, lam = 0.003, 0.7, 0.06
+    us = d1 + d2
+    vs = d2 / (us * us + lam)
+    out = _uniform(imex.schnackenberg_FE(d1, d2, lam), (us, vs), "ark3", 0.5, 2.0, (1e-3, 1e-1))
+    assert np.abs(out - [us, vs]).max() <= 1e-14 * 4
