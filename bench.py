@@ -480,9 +480,15 @@ def extensions_leg(cpm, inputs, surfaces, torch, dev):
     pc = cpm.Precond(op, kind="oras", n_parts=8, overlap=2.0, precision="fp64", coarse="first")
     _, s, ms = median_solve(op, f, pc, rtol=1e-8, max_it=40000, poly=(1.0, 0.0, 1.0), pc_power=2, restart=60,
                             stagnation_cycles=400)
-    out["biharmonic"] = {"workload": "(1 + Lap^2) u = 401 Y4, unit sphere h=0.05 p=3, two-level ORAS of A(1) "
-                                     "applied twice, GMRES(60) to 1e-8", "n_active": band.n_active,
-                         "iterations": int(s["iterations"]), "ms": round(ms, 3), "converged": bool(s["converged"])}
+    _, s2, ms2 = median_solve(op, f, pc, rtol=1e-8, max_it=2000, poly=(1.0, 0.0, 1.0), pc_power=2,
+                              pc_inner_rtol=1e-3, pc_inner_max_it=60)
+    out["biharmonic"] = {"workload": "(1 + Lap^2) u = 401 Y4, unit sphere h=0.05 p=3, FGMRES to 1e-8, preconditioned "
+                                     "by A(1)^-2: two-level ORAS of A(1) applied twice (GMRES(60)), or inner "
+                                     "FGMRES solves of A(1) to 1e-3 with that ORAS, twice", "n_active": band.n_active,
+                         "squared_oras": {"iterations": int(s["iterations"]), "ms": round(ms, 3),
+                                          "converged": bool(s["converged"])},
+                         "inner_solves": {"iterations": int(s2["iterations"]), "ms": round(ms2, 3),
+                                          "converged": bool(s2["converged"])}}
     del pc, op, band, f
     band = cpm.Band("torus", (1.0, 0.4), 3, 0.01, 5, reach=2)
     op = cpm.Operator(band, 1.0, order=4)

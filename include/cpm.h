@@ -352,6 +352,17 @@ typedef struct {
    * inverse (sqrt(c0) - L)^2 is spectrally equivalent to c0 + L^2 (ratio within
    * [1, 2] for a negative semi-definite L). */
   int32_t pc_power;
+  /* pc_inner_rtol in (0, 1): every preconditioner application becomes an inner
+   * FGMRES solve of the instances' own operators A(c) w = v from zero, to
+   * pc_inner_rtol relative, at most pc_inner_max_it steps (default 30),
+   * preconditioned by the (O)RAS (the outer FGMRES is flexible, so an inexact
+   * inner solve is a valid variable preconditioner). With pc_power 2 and the
+   * operator at shift sqrt(c0) this applies A(sqrt(c0))^-2 almost exactly to
+   * the shifted biharmonic c0 + L^2, whose iteration count then stays flat in
+   * h, where squaring the (O)RAS itself does not. 0 (default): off.
+   * Host-synchronizing; not combinable with use_graph or transpose. */
+  double pc_inner_rtol;
+  int32_t pc_inner_max_it;
 } cpm_solve_opts;
 
 typedef struct {
@@ -477,19 +488,31 @@ cpm_status cpm_gray_scott_rhs(int64_t n, const double* u, const double* v, doubl
  * warm-started from the previous stage.
  *   kind GRAY_SCOTT: 2 species, F_E = (-u v^2 + F(1-u), u v^2 - (F+k) v);
  *   kind HEAT:       1 species, F_E = cos(t) g1 + sin(t) g2 (eq. htForce has
- *                    this form), g1, g2 given at create.
+ *                    this form), g1, g2 given at create;
+ *   kind FITZHUGH_NAGUMO (Sec. 4.1.4, eq. fitznag): 2 species,
+ *                    F_E = ((a - u)(u - 1) u - v, eps (beta u - v)),
+ *                    rd = {a, eps, beta} (the paper: 0.1, 0.01, 0.5);
+ *   kind SCHNACKENBERG (Sec. 4.1.6, eq. schnack): 2 species,
+ *                    F_E = (d1 - u + u^2 v + lam v, d2 - u^2 v - lam v),
+ *                    rd = {d1, d2, lam} (the paper: 0.003, 0.7, 0.06).
  * ------------------------------------------------------------------- */
 typedef enum { CPM_IMEX_EULER = 0, CPM_IMEX_ARK3 = 1 } cpm_imex_scheme;
-typedef enum { CPM_RD_GRAY_SCOTT = 0, CPM_RD_HEAT = 1 } cpm_rd_kind;
+typedef enum {
+  CPM_RD_GRAY_SCOTT = 0,
+  CPM_RD_HEAT = 1,
+  CPM_RD_FITZHUGH_NAGUMO = 2,
+  CPM_RD_SCHNACKENBERG = 3
+} cpm_rd_kind;
 
 typedef struct {
   int32_t scheme;         /* cpm_imex_scheme (default ARK3) */
   int32_t kind;           /* cpm_rd_kind (default GRAY_SCOTT) */
-  int32_t nspecies;       /* 2 (Gray-Scott) or 1 (heat) */
+  int32_t nspecies;       /* 1 for the heat equation, else 2 */
   double dt;              /* time step, > 0 */
   double mu[2];           /* diffusion coefficient of each species, > 0 */
   double F, k;            /* Gray-Scott feed and kill rates */
   int32_t tune;           /* 1: autotune the stage solves' kernels at creation */
+  double rd[3];           /* FitzHugh-Nagumo {a, eps, beta} or Schnackenberg {d1, d2, lam} */
 } cpm_imex_opts;
 
 typedef struct cpm_imex_s cpm_imex;

@@ -52,7 +52,7 @@ class SolveOpts(C.Structure):
                 ("max_it", C.c_int32), ("mode", C.c_int32), ("transpose", C.c_int32),
                 ("use_graph", C.c_int32), ("inner_rtol", C.c_double), ("stagnation_cycles", C.c_int32),
                 ("profile", C.c_int32), ("poly_n", C.c_int32), ("poly_coef", C.c_double * 5),
-                ("pc_power", C.c_int32)]
+                ("pc_power", C.c_int32), ("pc_inner_rtol", C.c_double), ("pc_inner_max_it", C.c_int32)]
 
 
 class OperatorOpts(C.Structure):
@@ -74,7 +74,8 @@ class SolveStats(C.Structure):
 
 class ImexOpts(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("kind", C.c_int32), ("nspecies", C.c_int32), ("dt", C.c_double),
-                ("mu", C.c_double * 2), ("F", C.c_double), ("k", C.c_double), ("tune", C.c_int32)]
+                ("mu", C.c_double * 2), ("F", C.c_double), ("k", C.c_double), ("tune", C.c_int32),
+                ("rd", C.c_double * 3)]
 
 
 class TuneResult(C.Structure):

@@ -387,6 +387,10 @@ class SolveOptions:
     poly: tuple = ()
     # preconditioner applications per step (2 with the (O)RAS of A(sqrt(c0)) for c0 + L^2)
     pc_power: int = 1
+    # > 0: each preconditioner application is an inner FGMRES solve of A w = v to this
+    # relative tolerance (at most pc_inner_max_it steps), preconditioned by the (O)RAS
+    pc_inner_rtol: float = 0.0
+    pc_inner_max_it: int = 30
 
     def to_c(self):
         o = _capi.SolveOpts()
@@ -407,6 +411,8 @@ class SolveOptions:
         for k, a in enumerate(coef):
             o.poly_coef[k] = a
         o.pc_power = int(self.pc_power)
+        o.pc_inner_rtol = float(self.pc_inner_rtol)
+        o.pc_inner_max_it = int(self.pc_inner_max_it)
         return o
 
 
@@ -567,15 +573,19 @@ class _shift:
 
 
 IMEX_SCHEME = {"euler": 0, "ark3": 1}
-RD_KIND = {"gray_scott": 0, "heat": 1}
+RD_KIND = {"gray_scott": 0, "heat": 1, "fitzhugh_nagumo": 2, "schnackenberg": 3}
+# the paper's reaction parameters (Sec. 4.1.4: a, eps, beta; Sec. 4.1.6: d1, d2, lam)
+RD_DEFAULTS = {"fitzhugh_nagumo": (0.1, 0.01, 0.5), "schnackenberg": (0.003, 0.7, 0.06)}
 
 
-def imex_options(scheme="ark3", kind="gray_scott", dt=1.0, mu=(2e-5, 1e-5), F=0.04, k=0.06, tune=False):
+def imex_options(scheme="ark3", kind="gray_scott", dt=1.0, mu=(2e-5, 1e-5), F=0.04, k=0.06, tune=False, rd=None):
     o = _capi.ImexOpts()
     check(lib().cpm_imex_opts_default(C.byref(o)))
     o.scheme = IMEX_SCHEME[scheme]
     o.kind = RD_KIND[kind]
-    o.nspecies = 2 if kind == "gray_scott" else 1
+    o.nspecies = 1 if kind == "heat" else 2
+    for q, val in enumerate(rd if rd is not None else RD_DEFAULTS.get(kind, (0.0, 0.0, 0.0))):
+        o.rd[q] = float(val)
     o.dt = float(dt)
     for s, m in enumerate(tuple(mu)[:2]):
         o.mu[s] = float(m)
@@ -601,8 +611,8 @@ class Imex:
     forcing cos(t) g1 + sin(t) g2."""
 
     def __init__(self, ops, pcs=None, scheme="ark3", kind="gray_scott", dt=1.0, mu=(2e-5, 1e-5), F=0.04, k=0.06,
-                 forcing=None, tune=False):
-        self.opts = imex_options(scheme, kind, dt, mu, F, k, tune)
+                 forcing=None, tune=False, rd=None):
+        self.opts = imex_options(scheme, kind, dt, mu, F, k, tune, rd)
         ns = self.opts.nspecies
         self._ops = check_count(ops, ns, "ops")
         self._pcs = check_count(pcs if pcs is not None else [None] * ns, ns, "pcs")

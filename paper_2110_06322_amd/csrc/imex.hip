@@ -60,6 +60,27 @@ __global__ void k_imex_gray_scott(int64_t n, double F, double k, const double* _
   ev[i] = abb - (F + k) * b;
 }
 
+// FitzHugh-Nagumo reaction (eq. fitznag): eu = (a - u)(u - 1) u - v, ev = eps (beta u - v)
+__global__ void k_imex_fhn(int64_t n, double a, double eps, double beta, const double* __restrict__ u,
+                           const double* __restrict__ v, double* __restrict__ eu, double* __restrict__ ev) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = u[i], y = v[i];
+  eu[i] = (a - x) * (x - 1.0) * x - y;
+  ev[i] = eps * (beta * x - y);
+}
+
+// Schnackenberg reaction (eq. schnack): eu = d1 - u + u^2 v + lam v, ev = d2 - u^2 v - lam v
+__global__ void k_imex_schnack(int64_t n, double d1, double d2, double lam, const double* __restrict__ u,
+                               const double* __restrict__ v, double* __restrict__ eu, double* __restrict__ ev) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = u[i], y = v[i];
+  const double xxy = x * x * y;
+  eu[i] = d1 - x + xxy + lam * y;
+  ev[i] = d2 - xxy - lam * y;
+}
+
 // forced heat equation (eq. heat): e = cos(t) g1 + sin(t) g2
 __global__ void k_imex_forcing(int64_t n, double ct, double st, const double* __restrict__ g1,
                                const double* __restrict__ g2, double* __restrict__ e) {
@@ -145,6 +166,12 @@ void explicit_terms(cpm_imex_s& M, double t, const double* const* w, int stage, 
   if (M.o.kind == CPM_RD_GRAY_SCOTT) {
     hipLaunchKernelGGL(k_imex_gray_scott, grid_for(M.n), dim3(256), 0, s, M.n, M.o.F, M.o.k, w[0], w[1],
                        M.ke(stage, 0), M.ke(stage, 1));
+  } else if (M.o.kind == CPM_RD_FITZHUGH_NAGUMO) {
+    hipLaunchKernelGGL(k_imex_fhn, grid_for(M.n), dim3(256), 0, s, M.n, M.o.rd[0], M.o.rd[1], M.o.rd[2], w[0], w[1],
+                       M.ke(stage, 0), M.ke(stage, 1));
+  } else if (M.o.kind == CPM_RD_SCHNACKENBERG) {
+    hipLaunchKernelGGL(k_imex_schnack, grid_for(M.n), dim3(256), 0, s, M.n, M.o.rd[0], M.o.rd[1], M.o.rd[2], w[0],
+                       w[1], M.ke(stage, 0), M.ke(stage, 1));
   } else {
     hipLaunchKernelGGL(k_imex_forcing, grid_for(M.n), dim3(256), 0, s, M.n, std::cos(t), std::sin(t), M.g.p,
                        M.g.p + M.n, M.ke(stage, 0));
@@ -209,9 +236,11 @@ cpm_status cpm_imex_create(const cpm_operator* const* ops, const cpm_precond* co
     *out = nullptr;
     const cpm_imex_opts& o = *opts;
     if (o.scheme != CPM_IMEX_EULER && o.scheme != CPM_IMEX_ARK3) fail(CPM_ERR_ARG, "unknown IMEX scheme");
-    if (o.kind != CPM_RD_GRAY_SCOTT && o.kind != CPM_RD_HEAT) fail(CPM_ERR_ARG, "unknown reaction-diffusion kind");
-    const int ns = o.kind == CPM_RD_GRAY_SCOTT ? 2 : 1;
-    if (o.nspecies != ns) fail(CPM_ERR_ARG, "nspecies must be 2 for Gray-Scott and 1 for the heat equation");
+    if (o.kind < CPM_RD_GRAY_SCOTT || o.kind > CPM_RD_SCHNACKENBERG) fail(CPM_ERR_ARG, "unknown reaction-diffusion kind");
+    const int ns = o.kind == CPM_RD_HEAT ? 1 : 2;
+    if (o.nspecies != ns) fail(CPM_ERR_ARG, "nspecies must be 1 for the heat equation and 2 otherwise");
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(o.rd[q])) fail(CPM_ERR_ARG, "non-finite reaction parameter");
     if (!(o.dt > 0) || !std::isfinite(o.dt)) fail(CPM_ERR_ARG, "dt must be positive");
     auto M = std::make_unique<cpm_imex_s>();
     M->o = o;

@@ -74,6 +74,12 @@ struct cpm_batch_s {
   int poly_n = 0, pc_power = 1;
   double poly_coef[kMaxPoly] = {};
   DevBuf<double> pbuf, pctmp;
+  // inner solves as the preconditioner: each application of M^-1 becomes an FGMRES solve of
+  // the instances' own operators A w = v to pc_inner_rtol (at most pc_inner_max_it steps),
+  // preconditioned by the batch's preconditioners; inner is a batch of the same operators
+  double pc_inner_rtol = 0.0;
+  int pc_inner_max_it = 0;
+  std::shared_ptr<cpm_batch_s> inner;
   // coarse levels (two-level Schwarz): each instance's view with batch offsets
   std::vector<DevCoarse> coarse;
   bool any_coarse = false, any_coarse_first = false;
@@ -419,14 +425,49 @@ void batch_precond_once(cpm_batch_s& Bt, const double* v, double* z, hipStream_t
       if (Bt.coarse[i].n) hip_check(coarse_prolong(Bt.coarse[i], Bt.R, Bt.evec.p, z, true, s), "coarse prolong");
 }
 
+cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* uin, const cpm_solve_opts& o,
+                      cpm_solve_stats* stats, hipStream_t st);
+
+// z = A^-1 v approximately: an FGMRES solve from zero of every instance's own operator,
+// preconditioned by its (O)RAS, to the inner tolerance (host-synchronizing)
+void inner_solve(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s) {
+  if (!Bt.inner) {
+    Bt.inner = std::make_shared<cpm_batch_s>();
+    build_batch(*Bt.inner, Bt.ni, Bt.ops.data(), Bt.pcs.data(), Bt.R);
+  }
+  cpm_solve_opts io;
+  std::memset(&io, 0, sizeof io);
+  io.restart = 30;
+  io.rtol = Bt.pc_inner_rtol;
+  io.max_it = Bt.pc_inner_max_it;
+  io.mode = CPM_MODE_FP64;
+  io.inner_rtol = 1e-4;
+  io.stagnation_cycles = 50;
+  io.pc_power = 1;
+  std::vector<const double*> f(Bt.ni);
+  std::vector<double*> u(Bt.ni);
+  for (int i = 0; i < Bt.ni; ++i) {
+    f[i] = v + Bt.off[i] * Bt.R;
+    u[i] = z + Bt.off[i] * Bt.R;
+  }
+  hip_check(hipMemsetAsync(z, 0, (size_t)Bt.Ntot * Bt.R * sizeof(double), s), "zero");
+  const cpm_status e = solve_impl(*Bt.inner, f.data(), u.data(), io, nullptr, s);
+  if (e != CPM_OK && e != CPM_NOT_CONVERGED) fail(e, "inner preconditioner solve failed");
+}
+
 // z = M^-k v with k = pc_power (the intermediate results alternate between pctmp and z)
 void batch_precond(cpm_batch_s& Bt, const double* v, double* z, hipStream_t s, const Gate& gate = Gate{}) {
   const int k = Bt.pc_power;
-  if (k <= 1) return batch_precond_once(Bt, v, z, s, gate);
+  const bool inner = Bt.pc_inner_rtol > 0.0;
+  if (k <= 1) {
+    if (inner) return inner_solve(Bt, v, z, s);
+    return batch_precond_once(Bt, v, z, s, gate);
+  }
   const double* in = v;
   for (int q = 0; q < k; ++q) {
     double* out = ((k - 1 - q) & 1) ? Bt.pctmp.p : z;
-    batch_precond_once(Bt, in, out, s, gate);
+    if (inner) inner_solve(Bt, in, out, s);
+    else batch_precond_once(Bt, in, out, s, gate);
     in = out;
   }
 }
@@ -549,12 +590,21 @@ cpm_status solve_impl(cpm_batch_s& Bt, const double* const* fin, double* const* 
     if (!nz) fail(CPM_ERR_ARG, "all polynomial coefficients are zero");
   }
   if (o.pc_power > 1 && o.use_graph) fail(CPM_ERR_ARG, "pc_power > 1 cannot be combined with use_graph");
+  if (!(o.pc_inner_rtol >= 0.0 && o.pc_inner_rtol < 1.0)) fail(CPM_ERR_ARG, "pc_inner_rtol must be in [0, 1)");
+  if (o.pc_inner_rtol > 0.0) {
+    if (!Bt.any_pc) fail(CPM_ERR_ARG, "inner preconditioner solves need preconditioners");
+    if (o.use_graph) fail(CPM_ERR_ARG, "inner preconditioner solves cannot be combined with use_graph");
+    if (o.transpose) fail(CPM_ERR_ARG, "inner preconditioner solves are not transposed");
+    if (o.pc_inner_max_it < 1) fail(CPM_ERR_ARG, "pc_inner_max_it must be >= 1");
+  }
   ensure_workspace(Bt, m);
   // the operator algebra holds for this solve only
   struct PolyScope {
     cpm_batch_s& B;
-    ~PolyScope() { B.poly_n = 0; B.pc_power = 1; }
+    ~PolyScope() { B.poly_n = 0; B.pc_power = 1; B.pc_inner_rtol = 0.0; B.pc_inner_max_it = 0; }
   } poly_scope{Bt};
+  Bt.pc_inner_rtol = o.pc_inner_rtol;
+  Bt.pc_inner_max_it = o.pc_inner_max_it;
   Bt.poly_n = o.poly_n;
   for (int k = 0; k < kMaxPoly; ++k) Bt.poly_coef[k] = k < o.poly_n ? o.poly_coef[k] : 0.0;
   Bt.pc_power = std::max(1, (int)o.pc_power);
@@ -744,6 +794,8 @@ cpm_status cpm_solve_opts_default(cpm_solve_opts* o) {
   o->stagnation_cycles = 50;
   o->poly_n = 0;
   o->pc_power = 1;
+  o->pc_inner_rtol = 0.0;
+  o->pc_inner_max_it = 30;
   return CPM_OK;
 }
 

@@ -167,3 +167,25 @@ def test_poly_rejects_bad_options():
             cpm.solve(op, f, raise_on_fail=True, **kw)
     with pytest.raises(_capi.CpmError):
         op.poly_apply([1.0, float("inf")], f)
+
+
+def test_biharmonic_inner_solve_preconditioner_flat_in_h():
+    """Each preconditioner application as an inner FGMRES solve of A(sqrt(c0)) (ORAS,
+    to 1e-3), applied twice: A(sqrt(c0))^-2 is spectrally equivalent to (c0 + L^2)^-1, so
+    the outer iteration count stays small and flat from h = 0.1 to 0.05 (the oracle's
+    exact A(1)^-2 preconditioner gives 6 and 5 GMRES iterations there); the solutions
+    equal those of the squared-ORAS solves to the tolerance and keep the manufactured
+    errors."""
+    its = []
+    for h, expect in ((0.1, 7.117e-01), (0.05, 1.762e-01)):
+        lb, op, f, uex = _biharm_setup("sphere", h)
+        pc = cpm.Precond(op, kind="oras", n_parts=8, overlap=2.0, precision="fp64", coarse="first")
+        u, st = cpm.solve(op, f, pc=pc, rtol=1e-8, max_it=2000, poly=(1.0, 0.0, 1.0), pc_power=2,
+                          pc_inner_rtol=1e-3, pc_inner_max_it=60)
+        assert st["converged"], st
+        e = np.abs(u.cpu().numpy() - uex).max() / np.abs(uex).max()
+        print(f"sphere h={h}: inner-solve preconditioner, {st['iterations']} outer iterations, "
+              f"{st['ms_total']:.1f} ms, error {e:.4e}", flush=True)
+        assert abs(e - expect) <= 1e-3 * expect
+        its.append(st["iterations"])
+    assert max(its) <= 30, its
