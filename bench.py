@@ -229,7 +229,8 @@ def rotating(band, torch, dev, inputs, copies=4, seed=10):
 # ---------------------------------------------------------------- legs
 def sphere_leg(cpm, inputs, torch, dev, a, ref):
     """Unit sphere h = 0.02, ORAS 64 boxes: mixed vs FP64 solve to 1e-8 and each solution's
-    error against the oracle's reference solution (max-norm, relative)."""
+    error against the oracle's reference solution (max-norm, relative), and the same errors
+    for untimed solves to the accuracy bars' tolerances (FP64 to 1e-12, mixed to 1e-10)."""
     import numpy as np
     band = cpm.Band("sphere", (1.0,), 3, 0.02, 3)
     op = cpm.Operator(band, 1.0)
@@ -253,6 +254,13 @@ def sphere_leg(cpm, inputs, torch, dev, a, ref):
                          "precond_ms": round(tn["precond_ms"], 4)}
             if order == a.ordering:
                 sols[mode] = u.cpu().numpy()
+                # the accuracy bars: FP64 solved to 1e-12, mixed refined to 1e-10, each against the
+                # oracle's reference solution (untimed)
+                tight = 1e-12 if mode == "fp64" else 1e-10
+                ut, stt = cpm.solve(op, f, pc=pc, rtol=tight, mode=mode, max_it=20000)
+                sols[mode + "_tight"] = ut.cpu().numpy()
+                res[mode]["tight"] = {"rtol": tight, "iterations": int(stt["iterations"]),
+                                      "relres": stt["relres"], "converged": bool(stt["converged"])}
                 if mode == "mixed":
                     _, stp = cpm.solve(op, f, pc=pc, rtol=1e-8, mode=mode, max_it=20000, profile=True)
                     res["precond_kernel_ms"] = round(stp["ms_precond"] / max(1, stp["n_precond"]), 5)
@@ -289,6 +297,8 @@ def sphere_leg(cpm, inputs, torch, dev, a, ref):
             sc = float(np.abs(rx).max())
             out["err_vs_oracle_mixed"] = float(np.abs(sols["mixed"] - rx[pos]).max() / sc)
             out["err_vs_oracle_fp64"] = float(np.abs(sols["fp64"] - rx[pos]).max() / sc)
+            out["err_vs_oracle_mixed_rtol_1e-10"] = float(np.abs(sols["mixed_tight"] - rx[pos]).max() / sc)
+            out["err_vs_oracle_fp64_rtol_1e-12"] = float(np.abs(sols["fp64_tight"] - rx[pos]).max() / sc)
     # the metric kernel on this cache-resident system
     xs, ys = rotating(band, torch, dev, inputs)
     cpm.autotune(op, None)

@@ -465,6 +465,9 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
                                         const int32_t* __restrict__ gsched_, const double* __restrict__ rb_,
                                         const T* yv, T* dst, int* done, int32_t* err) {
   constexpr int LEVEL = BACKWARD ? 2 : 1;
+  // one right-hand side keeps three packets' entries in registers where the register
+  // budget of the form's thread count allows it (all but the FP64 flag form)
+  constexpr bool DEEP = NRHS == 1 && (!FLAGS || sizeof(T) == 4);
   using Bits = typename Sentinel<T>::Bits;
   const auto pk = gmem(pk_);
   const auto rec = gmem(rec_);
@@ -473,6 +476,9 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
   const auto dinv = gmem(dinv_);
   const auto gsched = gmem(gsched_);
   const auto rb = gmem(rb_);
+  // a global store for the error flag, so that the rare time-out path does not
+  // leave a flat operation pending in both memory counters
+  const auto errg = (__attribute__((address_space(1))) int32_t*)err;
   int p = wave;
   if (p >= npk) return;
   const int last = npk - 1;
@@ -494,7 +500,9 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
     const auto vp = val + e0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      if (j < packet_slots(D.cls)) {   // uniform: only the slots of the packet's class
+      // uniform: only the slots of the packet's class, or all of them in the deep
+      // pipeline (a fixed number of loads per fetch keeps its waits exact)
+      if (DEEP || j < packet_slots(D.cls)) {
         D.k[j] = cp[kPacketLanes * j];
         D.v[j] = vp[kPacketLanes * j];
       }
@@ -534,7 +542,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
         if (!pending) break;
         if (SLEEP) __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(errg, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
 #pragma unroll
@@ -557,7 +565,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
         if (!pending) break;
         if (SLEEP) __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(errg, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
           for (int j = 0; j < NJ; ++j) b[j] = 0;
           break;
@@ -609,6 +617,42 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
     else if (D.cls == 1) solve_n(std::integral_constant<int, packet_slots(1)>{}, D);
     else solve_n(std::integral_constant<int, packet_slots(2)>{}, D);
   };
+  if constexpr (DEEP) {
+    // Entries two packets ahead: each step issues the packet word four packets
+    // ahead and the record three ahead first, then the entries two ahead, then
+    // solves. Vector loads complete in issue order, so a step waits only for
+    // loads issued at least one step earlier (the current packet's entries and
+    // the lookahead words and records), and the entries fetched by the previous
+    // step stay in flight across this packet's polls and sums.
+    PacketRow<T, NRHS> A, B, C;
+    auto word = [&](int q) { return pk[min(q, last)]; };
+    auto gpos = [&](uint32_t w) { return BACKWARD ? 0 : gsched[posof(w)]; };
+    uint32_t w0 = word(p), w1 = word(p + nw);
+    const uint64_t r0 = rec[posof(w0)], r1 = rec[posof(w1)];
+    const int g0 = gpos(w0), g1 = gpos(w1);
+    uint32_t w2 = word(p + 2 * nw), w3 = word(p + 3 * nw);
+    uint64_t r2 = rec[posof(w2)];
+    int g2 = gpos(w2);
+    fetch(A, w0, r0, g0);
+    fetch(B, w1, r1, g1);
+    auto step = [&](PacketRow<T, NRHS>& cur, PacketRow<T, NRHS>& ahead) {
+      const uint32_t w4 = word(p + 4 * nw);
+      const uint64_t r3 = rec[posof(w3)];
+      const int g3 = gpos(w3);
+      fetch(ahead, w2, r2, g2);   // packet p + 2nw (clamped to the last packet near the end)
+      solve_row(cur);
+      if (p + nw > last) return false;
+      p += nw;
+      w2 = w3;
+      r2 = r3;
+      g2 = g3;
+      w3 = w4;
+      return true;
+    };
+    while (step(A, C) && step(B, A) && step(C, B)) {
+    }
+    return;
+  }
   // packet words three packets ahead, records two ahead, entries one ahead
   // (fetched right after the previous packet is published)
   PacketRow<T, NRHS> A, B;

@@ -83,6 +83,7 @@ struct cpm_batch_s {
   // coarse levels (two-level Schwarz): each instance's view with batch offsets
   std::vector<DevCoarse> coarse;
   bool any_coarse = false, any_coarse_first = false;
+  bool all_coarse_first = false;   // every instance coarse-first: r - A z_c overwrites all of ctr
   DevBuf<double> cvec, evec, ctz, ctr;
   // preconditioners
   bool any_pc = false, all_pc = true, pc_packets = false;
@@ -262,6 +263,7 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
   if (Bt.apply_variant == kApplyTwoPass && !Bt.twopass) Bt.apply_variant = kApplyPipelined;
   {
     int64_t coff = 0;
+    int nfirst = 0;
     Bt.coarse.assign(n, DevCoarse{});
     for (int i = 0; i < n; ++i) {
       const cpm_precond_s* pc = pcs ? pcs[i] : nullptr;
@@ -272,8 +274,12 @@ void build_batch(cpm_batch_s& Bt, int n, const cpm_operator_s* const* ops, const
       coff += C.n;
       Bt.coarse[i] = C;
       Bt.any_coarse = true;
-      if (C.mode == CPM_COARSE_FIRST) Bt.any_coarse_first = true;
+      if (C.mode == CPM_COARSE_FIRST) {
+        Bt.any_coarse_first = true;
+        ++nfirst;
+      }
     }
+    Bt.all_coarse_first = nfirst == n;
     if (Bt.any_coarse) {
       Bt.cvec.alloc((size_t)coff * R);
       Bt.evec.alloc((size_t)coff * R);
@@ -394,8 +400,10 @@ void batch_precond_once(cpm_batch_s& Bt, const double* v, double* z, hipStream_t
       hip_check(coarse_solve(C, Bt.R, Bt.cvec.p, Bt.evec.p, s), "coarse solve");
     }
     if (Bt.any_coarse_first) {
-      hip_check(hipMemcpyAsync(Bt.ctr.p, v, (size_t)Bt.Ntot * Bt.R * sizeof(double), hipMemcpyDeviceToDevice, s),
-                "copy");
+      // instances without a coarse-first level precondition v itself
+      if (!Bt.all_coarse_first)
+        hip_check(hipMemcpyAsync(Bt.ctr.p, v, (size_t)Bt.Ntot * Bt.R * sizeof(double), hipMemcpyDeviceToDevice, s),
+                  "copy");
       for (int i = 0; i < Bt.ni; ++i) {
         const DevCoarse& C = Bt.coarse[i];
         if (C.n == 0 || C.mode != CPM_COARSE_FIRST) continue;

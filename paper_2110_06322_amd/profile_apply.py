@@ -2,12 +2,15 @@
 with a fourth argument, ORAS preconditioner applies with that local row order
 and FP32 factors, 64 subdomains, overlap 2h, `transpose` transpose applies, or
 `order4` applies of the fourth-order operator on a band of reach 2, with the
-interpolation degree as a fifth argument, default 3) on one workload and a
+interpolation degree as a fifth argument, default 3; or `solve2`: `reps`
+mixed solves to 1e-8 of f = 21 Y4 with the two-level coarse-first FP32 ORAS,
+distance order, the number of subdomains as the fifth argument, default 64) on
+one workload and a
 device-to-device copy of known size (the copy calibrates the hardware byte
 counters against a kernel whose traffic is exactly known). Applies rotate
 through four input/output pairs, as the benchmark's do.
 
-Usage: python -m paper_2110_06322_amd.profile_apply [sphere|torus] [h] [reps] [rcm|distance|transpose|order4] [p]
+Usage: python -m paper_2110_06322_amd.profile_apply [sphere|torus] [h] [reps] [rcm|distance|transpose|order4|solve2] [p|parts]
 """
 from __future__ import annotations
 
@@ -39,6 +42,16 @@ def main():
         cpm.autotune(op, pc)
         for r in range(reps):
             pc.apply(xs[r % 4], out=ys[r % 4])
+    elif mode == "solve2":
+        parts = int(sys.argv[5]) if len(sys.argv) > 5 else 64
+        _, cp, _ = band.export()
+        f = torch.tensor(21.0 * inputs.sphere_y4(cp[:band.n_active], 2), dtype=torch.float64, device="cuda")
+        pc = cpm.Precond(op, kind="oras", n_parts=parts, overlap=2.0, precision="fp32", ordering="distance",
+                         coarse="first")
+        cpm.autotune(op, pc)
+        for r in range(reps):
+            u, st = cpm.solve(op, f, pc=pc, rtol=1e-8, mode="mixed", max_it=20000)
+            print(f"solve {r}: {st['iterations']} iterations, {st['ms_total']:.2f} ms", flush=True)
     elif mode == "transpose":
         for r in range(reps):
             op.apply_T(xs[r % 4], out=ys[r % 4])
