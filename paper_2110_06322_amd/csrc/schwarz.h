@@ -75,10 +75,16 @@ constexpr int kSchwarzFlags = 0;        // LDS value array plus per-row completi
 constexpr int kSchwarzValueFlags = 1;   // values double as flags (forward and backward arrays)
 constexpr int kSchwarzPacket = 2;       // values as flags, up to four same-level rows per wavefront
 constexpr int kSchwarzPacketFlags = 3;  // packets with per-row completion flags (less local memory)
+// packets, values in two LDS arrays, one right-hand side; a packet waits until the
+// sweep's count of completed rows reaches the first position of its level (levels
+// then start one after another, so the count certifies every lower level)
+constexpr int kSchwarzPacketLevel = 4;
 // Packet layout: consecutive schedule positions of one level and one length
 // class are grouped into packets of at most kPacketRows rows; a packet word
-// holds its first position (bits 4..31), its class (bits 2..3) and its row
-// count minus one (bits 0..1). Each row is solved by kPacketLanes lanes, each
+// holds its first position (bits 4..19), its class (bits 2..3), its row count
+// minus one (bits 0..1) and how far its first position lies past the first
+// position of its level (bits 20..31, at most 4095: a wider level makes later
+// packets wait for some rows of their own level, which is slower, not wrong). Each row is solved by kPacketLanes lanes, each
 // taking at most packet_slots(class) of its entries (kPacketEntries at most).
 constexpr int kPacketRows = 4;
 constexpr int kPacketLanes = 16;

@@ -438,6 +438,8 @@ struct PacketRow {
   int len;                     // stored entries of the group's row (0 for an empty slot)
   bool live;                   // the group has a row in this packet
   int cls;                     // length class of the packet (wave-uniform)
+  int start;                   // first schedule position of the packet's level (level waits)
+  int nrows;                   // rows in the packet
   int k[kPacketEntries];
   T v[kPacketEntries];
   T own[NRHS];
@@ -458,12 +460,23 @@ __device__ __forceinline__ T row16_sum_to_15(T v) {
 // array (dst = yv, solved in place) and per-row completion flags `done`
 // (forward publishes level 1, backward level 2); less local memory, one more
 // LDS round trip per dependency, the same arithmetic in the same order.
-template <class T, int NRHS, bool BACKWARD, bool SLEEP, bool FLAGS>
+// LVL = true (value form, one right-hand side): no per-dependency polls; a
+// packet waits until the sweep's count of completed rows `cnt` reaches the first
+// position of its level (from the packet word), then reads its dependencies, and
+// its publication adds its rows to the count. A level therefore starts only once
+// every row of the previous level is complete, so a count above the first
+// position of a level certifies every lower level; one uniform LDS read per poll
+// instead of one per dependency. (In a level wider than 4095 rows a packet waits
+// for a count 4095 below its own first position, which some rows of its own level
+// help reach: slower, still every lower level.) The same arithmetic in the same
+// order.
+template <class T, int NRHS, bool BACKWARD, bool SLEEP, bool FLAGS, bool LVL = false>
 __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int lane, const uint32_t* __restrict__ pk_,
                                         const uint64_t* __restrict__ rec_, const uint16_t* __restrict__ col_,
                                         const T* __restrict__ val_, const T* __restrict__ dinv_,
                                         const int32_t* __restrict__ gsched_, const double* __restrict__ rb_,
-                                        const T* yv, T* dst, int* done, int32_t* err) {
+                                        const T* yv, T* dst, int* done, int32_t* err, int* cnt = nullptr) {
+  static_assert(!LVL || (!FLAGS && NRHS == 1), "level waits take the value form with one right-hand side");
   constexpr int LEVEL = BACKWARD ? 2 : 1;
   // one right-hand side keeps three packets' entries in registers where the register
   // budget of the form's thread count allows it (all but the FP64 flag form)
@@ -476,15 +489,25 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
   const auto dinv = gmem(dinv_);
   const auto gsched = gmem(gsched_);
   const auto rb = gmem(rb_);
-  // a global store for the error flag, so that the rare time-out path does not
-  // leave a flat operation pending in both memory counters
+  // A bounded wait that expires sets the error flag with a global store (a flat
+  // store would leave both memory counters pending). The level-wait form records
+  // it and stores once the sweep ends: a vector store inside its poll loop leaves
+  // the compiler unable to count the entry loads in flight.
   const auto errg = (__attribute__((address_space(1))) int32_t*)err;
+  bool timed_out = false;
+  auto expired = [&]() {
+    if constexpr (LVL) timed_out = true;
+    else __hip_atomic_store(errg, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto report = [&]() {
+    if (LVL && timed_out) __hip_atomic_store(errg, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
   int p = wave;
   if (p >= npk) return;
   const int last = npk - 1;
   const int g = lane >> 4, t = lane & 15;
   // schedule position of this lane group's row in a packet (clamped into the packet)
-  auto posof = [&](uint32_t w) { return (int)(w >> 4) + min(g, (int)(w & 3u)); };
+  auto posof = [&](uint32_t w) { return (int)((w >> 4) & 0xffffu) + min(g, (int)(w & 3u)); };
   auto class_of = [&](uint32_t w) { return __builtin_amdgcn_readfirstlane((int)((w >> 2) & 3u)); };
   // Entries t, t+16, ... of the row, loaded unconditionally at immediate offsets
   // from one address: slots past the row's end read the entries that follow it
@@ -530,7 +553,22 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
     // wait for every dependency: all polls issued together, pending ones re-polled
     Bits b[NJ];
     int spins = 0;
-    if constexpr (FLAGS) {
+    if constexpr (LVL) {
+      // every row of the lower levels complete (the count is uniform over the wavefront)
+      const int start = __builtin_amdgcn_readfirstlane(D.start);
+      if (start > 0) {
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < start) {
+          if (SLEEP) __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) {
+            expired();
+            break;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[j] = to_bits<T>(dst[(size_t)kk[j] * NRHS]);
+    } else if constexpr (FLAGS) {
       int f[NJ];
 #pragma unroll
       for (int j = 0; j < NJ; ++j)
@@ -542,7 +580,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
         if (!pending) break;
         if (SLEEP) __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
-          __hip_atomic_store(errg, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          expired();
           break;
         }
 #pragma unroll
@@ -565,7 +603,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
         if (!pending) break;
         if (SLEEP) __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
-          __hip_atomic_store(errg, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          expired();
 #pragma unroll
           for (int j = 0; j < NJ; ++j) b[j] = 0;
           break;
@@ -607,9 +645,17 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
                            __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
+    if constexpr (LVL) {
+      // the packet's values are written (the wavefront's LDS stores complete) before its
+      // rows are counted
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      if (lane == 0) __hip_atomic_fetch_add(cnt, D.nrows, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
   };
   auto fetch = [&](PacketRow<T, NRHS>& D, uint32_t w, uint64_t r, int gi) __attribute__((always_inline)) {
     D.cls = class_of(w);
+    D.start = (int)((w >> 4) & 0xffffu) - (int)(w >> 20);   // level waits: rows to count first
+    D.nrows = (int)(w & 3u) + 1;
     fetch_n(std::integral_constant<int, kPacketEntries>{}, D, w, r, gi);
   };
   auto solve_row = [&](PacketRow<T, NRHS>& D) __attribute__((always_inline)) {
@@ -651,6 +697,7 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
     };
     while (step(A, C) && step(B, A) && step(C, B)) {
     }
+    report();
     return;
   }
   // packet words three packets ahead, records two ahead, entries one ahead
@@ -681,9 +728,10 @@ __device__ __forceinline__ void sweep_p(int n, int npk, int wave, int nw, int la
   };
   while (step(A, B) && step(B, A)) {
   }
+  report();
 }
 
-template <class T, int NRHS, bool SLEEP, bool FLAGS>
+template <class T, int NRHS, bool SLEEP, bool FLAGS, bool LVL = false>
 __global__ void __launch_bounds__(packet_max_threads(sizeof(T) == 4, NRHS, FLAGS)) k_schwarz_p(const DevPC* __restrict__ pcs,
                                                               const WorkItem* __restrict__ work, int nwork,
                                                               const double* __restrict__ rin,
@@ -700,6 +748,8 @@ __global__ void __launch_bounds__(packet_max_threads(sizeof(T) == 4, NRHS, FLAGS
   T* yv = reinterpret_cast<T*>(smem_d);
   T* zv = FLAGS ? yv : yv + (size_t)n1 * NRHS;                // FLAGS: solved in place
   int* done = reinterpret_cast<int*>(yv + (size_t)n1 * NRHS); // FLAGS only
+  // LVL: completed-row counts of the forward and backward sweeps, after the two value arrays
+  int* cnt = reinterpret_cast<int*>(yv + 2 * (size_t)n1 * NRHS);
   const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id(), nw = blockDim.x >> 6;
   const int32_t* out_idx = P.out_idx + sub.row_off;
   const T* lv = reinterpret_cast<const T*>(P.lval) + sub.lbase;
@@ -714,15 +764,16 @@ __global__ void __launch_bounds__(packet_max_threads(sizeof(T) == 4, NRHS, FLAGS
     const T sent = bits_to<T>(Sentinel<T>::kBits);
     for (int q = tid; q < 2 * n1 * NRHS; q += blockDim.x)
       yv[q] = (q % (n1 * NRHS)) < n * NRHS ? sent : (T)0;
+    if (LVL && tid < 2) cnt[tid] = 0;
   }
   __syncthreads();
-  sweep_p<T, NRHS, false, SLEEP, FLAGS>(n, sub.npkL, wave, nw, lane, P.pk + sub.pk_off, P.recL + sub.row_off,
-                                        P.lcol + sub.lbase, lv, nullptr, P.gL + sub.row_off, rb, nullptr, yv, done,
-                                        P.error_flag);
+  sweep_p<T, NRHS, false, SLEEP, FLAGS, LVL>(n, sub.npkL, wave, nw, lane, P.pk + sub.pk_off, P.recL + sub.row_off,
+                                             P.lcol + sub.lbase, lv, nullptr, P.gL + sub.row_off, rb, nullptr, yv,
+                                             done, P.error_flag, cnt);
   __syncthreads();
-  sweep_p<T, NRHS, true, SLEEP, FLAGS>(n, sub.npkU, wave, nw, lane, P.pk + sub.pk_off + sub.npkL,
-                                       P.recU + sub.row_off, P.ucol + sub.ubase, uv, di, nullptr, nullptr, yv, zv,
-                                       done, P.error_flag);
+  sweep_p<T, NRHS, true, SLEEP, FLAGS, LVL>(n, sub.npkU, wave, nw, lane, P.pk + sub.pk_off + sub.npkL,
+                                            P.recU + sub.row_off, P.ucol + sub.ubase, uv, di, nullptr, nullptr, yv,
+                                            zv, done, P.error_flag, cnt + 1);
   __syncthreads();
   for (int q = tid; q < n; q += blockDim.x) {
     const int32_t o = out_idx[q];
@@ -748,6 +799,28 @@ template <class T, int NRHS>
 static hipError_t launch_t(const SchwarzCfg& cfg, const DevPC* pcs, const WorkItem* work, int nwork, int max_rows,
                            int max_len, const double* r, double* z, hipStream_t s, const Gate& gate) {
   const int threads = cfg.threads > 0 ? cfg.threads : kSchwarzThreads;
+  if (cfg.variant == kSchwarzPacketLevel) {
+    // level waits: value form, one right-hand side, two sweep counters after the arrays
+    if constexpr (NRHS == 1) {
+      if (max_len > kPacketLanes * kPacketEntries) return hipErrorInvalidValue;
+      const size_t shm = schwarz_value_lds(max_rows + 1, 1, sizeof(T)) + 2 * sizeof(int);
+      if (shm > kSchwarzMaxLds) return hipErrorInvalidConfiguration;
+      const int pthreads = min(threads, packet_max_threads(sizeof(T) == 4, 1, false));
+      const void* kern = cfg.sleep ? (const void*)k_schwarz_p<T, 1, true, false, true>
+                                   : (const void*)k_schwarz_p<T, 1, false, false, true>;
+      hipError_t e = lds_ok(kern, shm);
+      if (e != hipSuccess) return e;
+      if (cfg.sleep)
+        hipLaunchKernelGGL((k_schwarz_p<T, 1, true, false, true>), dim3(nwork), dim3(pthreads), shm, s, pcs, work,
+                           nwork, r, z, gate);
+      else
+        hipLaunchKernelGGL((k_schwarz_p<T, 1, false, false, true>), dim3(nwork), dim3(pthreads), shm, s, pcs, work,
+                           nwork, r, z, gate);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidConfiguration;
+    }
+  }
   if (cfg.variant == kSchwarzPacket || cfg.variant == kSchwarzPacketFlags) {
     // packet factors: the value form when its two arrays fit, else the flag form
     // (the same arithmetic); rows longer than a packet's lanes take are not packed

@@ -197,11 +197,14 @@ cpm_status cpm_precond_create(const cpm_operator* op, const cpm_precond_opts* op
           const auto& ptr = lower ? s.lptr : s.uptr;
           auto cls = [&](int t) { return packet_class(ptr[sched[t] + 1] - ptr[sched[t]]); };
           int32_t& count = lower ? subs[j].npkL : subs[j].npkU;
+          int level_start = 0;   // schedule position of the first row of the current level
           for (int t = 0; t < s.n;) {
             const int k = cls(t);
+            if (t > 0 && lev[t] != lev[t - 1]) level_start = t;
             int c = 1;
             while (c < kPacketRows && t + c < s.n && lev[t + c] == lev[t] && cls(t + c) == k) ++c;
-            pk.push_back(((uint32_t)t << 4) | ((uint32_t)k << 2) | (uint32_t)(c - 1));
+            const uint32_t back = (uint32_t)std::min(t - level_start, 4095);
+            pk.push_back((back << 20) | ((uint32_t)t << 4) | ((uint32_t)k << 2) | (uint32_t)(c - 1));
             ++count;
             t += c;
           }

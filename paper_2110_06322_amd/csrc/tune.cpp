@@ -99,7 +99,8 @@ int log2i(double v) { return v <= 1 ? 0 : (int)std::lround(std::log2(v)); }
 
 bool valid_schwarz(const std::vector<int>& v, bool packets, bool fp32, int nrhs) {
   if (v.size() != 3) return false;
-  const bool variant_ok = packets ? (v[0] == kSchwarzPacket || v[0] == kSchwarzPacketFlags)
+  const bool variant_ok = packets ? (v[0] == kSchwarzPacket || v[0] == kSchwarzPacketFlags ||
+                                     (v[0] == kSchwarzPacketLevel && nrhs == 1))
                                   : (v[0] == kSchwarzFlags || v[0] == kSchwarzValueFlags);
   return variant_ok && v[1] >= 64 && v[1] <= (packets ? packet_max_threads(fp32, nrhs, v[0] == kSchwarzPacketFlags) : 1024) && v[1] % 64 == 0 &&
          (v[2] == 0 || v[2] == 1);
@@ -109,8 +110,9 @@ bool valid_schwarz(const std::vector<int>& v, bool packets, bool fp32, int nrhs)
 // wavefront kernels, so only they are candidates for a packet layout.
 std::vector<SchwarzCfg> schwarz_candidates(bool packets, bool fp32, int nrhs) {
   std::vector<SchwarzCfg> out;
-  const std::vector<int> variants = packets ? std::vector<int>{kSchwarzPacket, kSchwarzPacketFlags}
-                                            : std::vector<int>{kSchwarzFlags, kSchwarzValueFlags};
+  std::vector<int> variants = packets ? std::vector<int>{kSchwarzPacket, kSchwarzPacketFlags}
+                                      : std::vector<int>{kSchwarzFlags, kSchwarzValueFlags};
+  if (packets && nrhs == 1) variants.push_back(kSchwarzPacketLevel);   // level waits: one right-hand side
   for (int variant : variants)
     for (int threads : {256, 512, 768, 1024})
       for (int sleep : {0, 1}) {

@@ -94,17 +94,24 @@ def test_schwarz_variants_bit_identical(sphere, tmp_path, prec, nrhs):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("nrhs", [1, 4])
 def test_packet_variants_bit_identical(sphere, tmp_path, prec, nrhs):
-    """Distance-ordered factors use the packet kernel only; its launch shapes agree bit for bit."""
+    """Distance-ordered factors use the packet kernels only (per-dependency polls in the value
+    or the flag form, and with one right-hand side the level-count waits); their forms and
+    launch shapes agree bit for bit."""
     b, op, _ = sphere
     pc = cpm.Precond(op, kind="oras", n_parts=16, overlap=2.0, precision=prec, ordering="distance")
     cache = tmp_path / "tune.json"
     r = _vec(b, nrhs, 13)
     res = cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
-    assert res["schwarz_variant"] in (2, 3) and res["schwarz_threads"] <= (768 if nrhs <= 2 else 512)
+    packet_forms = (2, 3, 4) if nrhs == 1 else (2, 3)
+    assert res["schwarz_variant"] in packet_forms and res["schwarz_threads"] <= (768 if nrhs <= 2 else 512)
     ref = None
     cfgs = [[2, 256, 0], [2, 256, 1], [2, 512, 0], [2, 512, 1], [2, 128, 1], [3, 256, 1], [3, 512, 0]]
+    if nrhs == 1:
+        cfgs += [[4, 256, 0], [4, 512, 1], [4, 128, 0]]   # level-count waits
     if prec == "fp32" and nrhs <= 2:
         cfgs += [[2, 768, 1], [3, 768, 0]]   # FP32 packets with 1-2 right-hand sides allow 768 threads
+        if nrhs == 1:
+            cfgs += [[4, 768, 0], [4, 768, 1]]
     elif nrhs == 1:
         cfgs += [[3, 768, 1]]                # so does the FP64 completion-flag form with one
     for cfg in cfgs:
@@ -120,7 +127,7 @@ def test_packet_variants_bit_identical(sphere, tmp_path, prec, nrhs):
     # a cached row-kernel choice does not apply to packet factors: the class is timed again
     _force(cache, "schwarz|", [1, 1024, 1])
     res = cpm.autotune(op, pc, nrhs=nrhs, cache=cache)
-    assert res["from_cache"] == 0 and res["schwarz_variant"] in (2, 3)
+    assert res["from_cache"] == 0 and res["schwarz_variant"] in packet_forms
 
 
 def test_tuner_skips_kernels_that_do_not_fit_local_memory():
