@@ -91,6 +91,31 @@ __device__ __forceinline__ int node_at(const DevInst& I, const int* g) {
   return -1;
 }
 
+// Pointers of the instance read through the global address space: loads through
+// a pointer taken from a struct would otherwise be flat loads, which also count in
+// the counter the LDS reads of the extension rows wait on and so force those waits
+// to drain every outstanding load.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T* p) {
+  return (gptr<T>)p;
+}
+// list records read field by field through global pointers
+__device__ __forceinline__ Job load_job(gptr<Job> p) {
+  Job j;
+  j.node = p->node;
+  j.slot = p->slot;
+  return j;
+}
+__device__ __forceinline__ FootBrick load_footbrick(gptr<FootBrick> p) {
+  FootBrick f;
+  f.mask = p->mask;
+  f.off = p->off;
+  f.lds = p->lds;
+  return f;
+}
+
 // Lagrange basis on nodes 0..P at s, product form
 template <int P>
 __device__ __forceinline__ void lagrange(double s, double* w) {
@@ -134,8 +159,9 @@ __device__ __forceinline__ void erow_weights(const double* t, int* b, double (*w
 template <int D>
 __device__ __forceinline__ void load_tcp(const DevInst& I, int j, double* t) {
   const int n = I.nA + I.nG;
+  const gptr<double> tcp = as_global(I.tcp);
 #pragma unroll
-  for (int k = 0; k < D; ++k) t[k] = I.tcp[(int64_t)k * n + j];
+  for (int k = 0; k < D; ++k) t[k] = tcp[(int64_t)k * n + j];
 }
 
 // Extension row (closest point cp given in grid units) evaluated with per-node
@@ -272,14 +298,27 @@ __device__ __forceinline__ double erow_lds(const double* t, const double* U, int
     const int base = b[0] * s0 + b[1] * s1 + b[2] - fbase;
 #pragma unroll
     for (int a0 = 0; a0 <= P; ++a0) {
+      // up to cubic interpolation the plane's (P+1)^2 values are read before they are
+      // combined, so that its LDS reads are in flight together rather than one column at
+      // a time (higher degrees read column by column: their planes exceed the registers)
+      constexpr int PB = P <= 3 ? P + 1 : 1;
+      double c[PB][P + 1];
       double acc1 = 0.0;
 #pragma unroll
-      for (int a1 = 0; a1 <= P; ++a1) {
-        const double* col = U + base + a0 * s0 + a1 * s1;
-        double acc2 = 0.0;
+      for (int a1b = 0; a1b <= P; a1b += PB) {
 #pragma unroll
-        for (int a2 = 0; a2 <= P; ++a2) acc2 += w[2][a2] * col[a2];
-        acc1 += w[1][a1] * acc2;
+        for (int q = 0; q < PB; ++q) {
+          const double* col = U + base + a0 * s0 + (a1b + q) * s1;
+#pragma unroll
+          for (int a2 = 0; a2 <= P; ++a2) c[q][a2] = col[a2];
+        }
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+          double acc2 = 0.0;
+#pragma unroll
+          for (int a2 = 0; a2 <= P; ++a2) acc2 += w[2][a2] * c[q][a2];
+          acc1 += w[1][a1b + q] * acc2;
+        }
       }
       out += w[0][a0] * acc1;
     }
@@ -382,8 +421,9 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
   const DevTile& tile = I.tiles[wi.idx];
   const int s0 = tile.fstr[0], s1 = tile.fstr[1], fbase = tile.fbase;
   const int fcnt = tile.fb_cnt, nj = tile.job_cnt;
-  const FootBrick* fb = I.fbrec + tile.fb_off;
-  const Job* jl = I.jobs + tile.job_off;
+  const gptr<FootBrick> fb = as_global(I.fbrec) + tile.fb_off;
+  const gptr<Job> jl = as_global(I.jobs) + tile.job_off;
+  const gptr<double> esgn = as_global(I.esgn);
   double* U = smem;
   double* V = U + ucap;
   const int tid = threadIdx.x, lane = lane_id();
@@ -398,16 +438,16 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
   int slot0 = -1, slot1 = -1;
   double cp0[3] = {0, 0, 0}, cp1[3] = {0, 0, 0}, sg0 = 1.0, sg1 = 1.0;
   if (tid < nj) {
-    const Job j = jl[tid];
+    const Job j = load_job(jl + tid);
     slot0 = j.slot;
     load_tcp<D>(I, j.node, cp0);
-    if (I.esgn) sg0 = I.esgn[j.node];
+    if (esgn) sg0 = esgn[j.node];
   }
   if (tid + NT < nj) {
-    const Job j = jl[tid + NT];
+    const Job j = load_job(jl + tid + NT);
     slot1 = j.slot;
     load_tcp<D>(I, j.node, cp1);
-    if (I.esgn) sg1 = I.esgn[j.node];
+    if (esgn) sg1 = esgn[j.node];
   }
   // stencil row of this thread: wavefront = tile brick, lane = node
   uint64_t mS = 0;
@@ -439,7 +479,7 @@ __global__ void __launch_bounds__(512) k_apply_tile(const DevInst* __restrict__ 
         const int q = q0 + u * NW;
         slot[u] = -1;
         if (q < fcnt) {
-          const FootBrick rec = fb[q];
+          const FootBrick rec = load_footbrick(fb + q);
           if ((rec.mask >> lane) & 1ull) {
             slot[u] = rec.lds + loff;
             val[u] = xb[(int64_t)(rec.off + mbcnt64(rec.mask)) * NRHS + r];
@@ -535,10 +575,10 @@ struct PipeList {
 // one instance are contiguous in the work list), so the steady state issues
 // no scalar loads
 struct InstView {
-  const double* tcp;
-  const double* esgn;       // extension-row signs, or null
-  const Job* jobs;
-  const FootBrick* fbrec;
+  gptr<double> tcp;
+  gptr<double> esgn;        // extension-row signs, or null
+  gptr<Job> jobs;
+  gptr<FootBrick> fbrec;
   int64_t vec_off;          // offset of the output (y, or extension values in the two-pass kernel)
   int64_t xoff;             // offset of x
   double diag, inv_h2;
@@ -549,10 +589,10 @@ template <bool TWO = false>
 __device__ __forceinline__ void inst_refresh(InstView& v, const DevInst* __restrict__ insts, int i) {
   if (i == v.inst) return;
   const DevInst& I = insts[i];
-  v.tcp = I.tcp;
-  v.esgn = I.esgn;
-  v.jobs = TWO ? I.jobsE : I.jobs;
-  v.fbrec = TWO ? I.fbrecE : I.fbrec;
+  v.tcp = as_global(I.tcp);
+  v.esgn = as_global(I.esgn);
+  v.jobs = as_global(TWO ? I.jobsE : I.jobs);
+  v.fbrec = as_global(TWO ? I.fbrecE : I.fbrec);
   v.vec_off = TWO ? I.vnode_off : I.vec_off;
   v.xoff = I.vec_off;
   v.diag = I.diag;
@@ -572,17 +612,17 @@ __device__ __forceinline__ PipeList pipe_list(const InstView& I, const PipeRec& 
   PipeList L;
   L.node0 = 0; L.slot0 = -1; L.node1 = 0; L.slot1 = -1; L.fbw = 0;
   if (tid < R.job_cnt) {
-    const Job j = I.jobs[R.job_off + tid];
+    const Job j = load_job(I.jobs + R.job_off + tid);
     L.node0 = j.node;
     L.slot0 = j.slot;
   }
   if (tid + 512 < R.job_cnt) {
-    const Job j = I.jobs[R.job_off + tid + 512];
+    const Job j = load_job(I.jobs + R.job_off + tid + 512);
     L.node1 = j.node;
     L.slot1 = j.slot;
   }
   const int q = wave + 8 * (lane >> 2);
-  if (lane < 32 && q < R.fb_cnt) L.fbw = reinterpret_cast<const uint32_t*>(I.fbrec + R.fb_off + q)[lane & 3];
+  if (lane < 32 && q < R.fb_cnt) L.fbw = reinterpret_cast<gptr<uint32_t>>(I.fbrec + R.fb_off + q)[lane & 3];
   return L;
 }
 
@@ -689,6 +729,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     const int slot0 = L0.slot0, slot1 = L0.slot1, node0 = L0.node0, node1 = L0.node1;
     double t0[3] = {D0.t0[0], D0.t0[1], D0.t0[2]};
     __syncthreads();
+    // closest point of a second job (tiles of more than 512 jobs), issued before the next
+    // tiles' loads: vector loads complete in order, so waiting for it later does not
+    // wait for those
+    double t1[3] = {0.0, 0.0, 0.0};
+    if (slot1 >= 0) view_tcp<D>(I, node1, t1);
     // ---- next tiles' loads: data of w+per, lists of w+2per, record of w+3per
     const bool n1 = w + per < w_end, n2 = w + 2 * per < w_end, n3 = w + 3 * per < w_end;
     if (n1) {
@@ -711,8 +756,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
       else V[slot0] = e;
     }
     if (slot1 >= 0) {
-      double t1[3];
-      view_tcp<D>(I, node1, t1);
       double e = erow_lds<D, P>(t1, U, s0, s1, fbase);
       if (I.esgn) e *= I.esgn[node1];
       if constexpr (TWO) yb[node1] = e;
@@ -855,14 +898,14 @@ __global__ void __launch_bounds__(512) k_stencil(const DevInst* __restrict__ ins
       ln[k] += s ? 1 : -1;
       int b = id;
       if (ln[k] < 0 || ln[k] >= E) {
-        b = I.bnbr[id * 2 * D + 2 * k + s];
+        b = as_global(I.bnbr)[id * 2 * D + 2 * k + s];
         ln[k] = (ln[k] + E) & (E - 1);
       }
       const int bit = bit_of<D>(ln[0], ln[1], ln[2]);
-      const uint64_t ma = I.maskA[b];
+      const uint64_t ma = as_global(I.maskA)[b];
       int j;
-      if ((ma >> bit) & 1ull) j = I.offA[b] + popc_below(ma, bit);
-      else j = I.nA + I.offG[b] + popc_below(I.maskG[b], bit);
+      if ((ma >> bit) & 1ull) j = as_global(I.offA)[b] + popc_below(ma, bit);
+      else j = I.nA + as_global(I.offG)[b] + popc_below(as_global(I.maskG)[b], bit);
       nb[2 * k + s] = vb[j];
     }
   double sum = nb[0] + nb[1];
