@@ -31,6 +31,13 @@ __device__ __forceinline__ bool gate_skip(const Gate& g, int inst) {
 
 constexpr int kSpinLimit = 1 << 22;
 
+// a bounded wait that expired: the error flag is set with a global store (a flat
+// store would stay pending in both memory counters and make every later wait of
+// the sweep drain all loads in flight)
+__device__ __forceinline__ void set_error(int32_t* err) {
+  __hip_atomic_store((__attribute__((address_space(1))) int32_t*)err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -43,7 +50,7 @@ __device__ __forceinline__ bool wait_flag(int* f, int level, int32_t* err) {
   while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < level) {
     __builtin_amdgcn_s_sleep(1);
     if (++spins > kSpinLimit) {
-      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      set_error(err);
       return false;
     }
   }
@@ -256,7 +263,7 @@ __device__ __forceinline__ T wait_value(T* p, int32_t* err) {
     }
     if (SLEEP) __builtin_amdgcn_s_sleep(1);
     if (++spins > kSpinLimit) {
-      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      set_error(err);
       return (T)0;
     }
   }
