@@ -93,3 +93,31 @@ def test_batch_rejects_mixed_layouts():
     pcs = [cpm.Precond(op, n_parts=4, ordering=o) for o in ("rcm", "distance")]
     with pytest.raises(Exception):
         cpm.Batch([op, op], pcs, [1, 1])
+
+
+def test_batch_level_count_packets_equal_solo():
+    """Distance-ordered factors with one right-hand side per system: the batch runs the
+    packet subdomain solves in the level-count form (forced through the tuner cache; one
+    LDS counter per sweep, no per-dependency polls); each system equals its solo solve,
+    run with the polling form, bit for bit."""
+    import json
+    import tempfile
+    insts = workloads.batched(n_each=1, hs=(0.05,), nrhs=1, n_sub_range=(4, 8), ordering="distance")
+    b = cpm.Batch([i.op for i in insts], [i.pc for i in insts], [1] * len(insts))
+    with tempfile.TemporaryDirectory() as d:
+        cache = f"{d}/tune.json"
+        b.autotune(cache=cache)
+        tab = json.load(open(cache))
+        assert any(k.startswith("batch-schwarz|") for k in tab), list(tab)
+        for k in tab:
+            if k.startswith("batch-schwarz|"):
+                tab[k] = [4, 256, 1]
+        json.dump(tab, open(cache, "w"))
+        res = b.autotune(cache=cache)
+        assert res["schwarz_variant"] == 4 and res["from_cache"] == 1, res
+        us, stats = b.solve([i.f for i in insts], rtol=1e-8, mode="mixed", max_it=5000)
+    assert all(s["converged"] for s in stats), stats
+    for k, inst in enumerate(insts):
+        u1, st1 = cpm.solve(inst.op, inst.f, pc=inst.pc, rtol=1e-8, mode="mixed", max_it=5000)
+        assert torch.equal(us[k], u1), k
+        assert st1["iterations"] == stats[k]["iterations"]
